@@ -1,0 +1,352 @@
+"""FP64 CPU oracle of the short-range TreePM step -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the GPU
+library: the arithmetic lives in ``srf_oracle.c`` (plain C, FP64, built with
+no FMA contraction) and this module only marshals numpy arrays to it and
+strings the steps together in the paper's order.
+
+Steps (Ishiyama, Nitadori & Makino, SC12):
+  a1 wrap + Morton key       (tree of Sec. 1 over the periodic box)
+  a2 sort by (key, index)
+  a3 octree                  (Barnes-Hut cells, Sec. 1 / Fig. 1)
+  a4 monopole moments
+  a5 particle groups         (Barnes' modified algorithm, Sec. 2)
+  a6 interaction lists       (opening angle theta + cutoff pruning, Fig. 2)
+  a7 same-list force         (Sec. 2 force sum with eq. (cutoff))
+  a8 unpermute
+  a9 adjoint of L = sum_i w_i . a_i with the structure held fixed.
+Plus the plain definition: brute-force minimum-image sums (O(N^2) and a
+cell list) and their gradient.
+
+Parity pins (tests/test_oracle_*.py): g against the S2-S2 cloud integral
+that defines it; brute force against O(N^2), momentum, translation and the
+two-body closed form; tree at theta = 0 against brute force; list coverage
+by brute force; adjoint against central differences, translation
+invariance and the brute-force closed form.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "srf_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+_d = C.c_double
+_i64 = C.c_int64
+_p = C.c_void_p
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle library in place (gcc, FP64, no FMA contraction)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp"
+        cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
+               "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = C.CDLL(_LIB_PATH)
+        L.or_gcut.restype = _d
+        L.or_gcut.argtypes = [_d]
+        L.or_gcut_deriv.restype = _d
+        L.or_gcut_deriv.argtypes = [_d]
+        L.or_wrap.restype = _d
+        L.or_wrap.argtypes = [_d]
+        L.or_morton3.restype = C.c_uint64
+        L.or_morton3.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32]
+        L.or_tree_count.restype = _i64
+        L.or_groups.restype = _i64
+        L.or_bf_pair_count.restype = _i64
+        L.or_bf_cells.restype = C.c_int
+        L.or_num_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
+
+
+# ---------------------------------------------------------------- kernels
+def gcut(xi):
+    """g_P3M(xi) (Sec. 2, eq. cutoff), vectorised; also its derivative."""
+    xi = _f64(np.atleast_1d(xi))
+    g = np.empty_like(xi)
+    dg = np.empty_like(xi)
+    lib().or_gcut_vec(_i64(xi.size), _ptr(xi), _ptr(g), _ptr(dg))
+    return g, dg
+
+
+def pair_force(d, r_cut, eps):
+    """F(d) = d (|d|^2+eps^2)^(-3/2) g(2|d|/r_cut) [|d| < r_cut] for one offset."""
+    out = np.empty(3)
+    lib().or_pair_force(_d(d[0]), _d(d[1]), _d(d[2]), _d(r_cut), _d(eps), _ptr(out))
+    return out
+
+
+def pair_jac(d, w, r_cut, eps):
+    """J(d) w, J = dF/dd."""
+    w = _f64(w)
+    out = np.empty(3)
+    lib().or_pair_jac(_d(d[0]), _d(d[1]), _d(d[2]), _d(r_cut), _d(eps), _ptr(w), _ptr(out))
+    return out
+
+
+# ------------------------------------------------------------- brute force
+def brute_force(x, y, z, m, G, r_cut, eps, method="cells"):
+    """Exact short-range accelerations (minimum image, all pairs within r_cut)."""
+    x, y, z, m = map(_f64, (x, y, z, m))
+    n = x.size
+    ax, ay, az = np.empty(n), np.empty(n), np.empty(n)
+    fn = lib().or_bf_cells if method == "cells" else lib().or_bf_n2
+    fn(_i64(n), _ptr(x), _ptr(y), _ptr(z), _ptr(m), _d(G), _d(r_cut), _d(eps), _ptr(ax), _ptr(ay), _ptr(az))
+    return np.stack([ax, ay, az], axis=1)
+
+
+def pair_count(x, y, z, r_cut) -> int:
+    x, y, z = map(_f64, (x, y, z))
+    return int(lib().or_bf_pair_count(_i64(x.size), _ptr(x), _ptr(y), _ptr(z), _d(r_cut)))
+
+
+def brute_force_adjoint(x, y, z, m, w, G, r_cut, eps):
+    """Gradient of L = sum w_i . a_i for the exact sum: (dL/dx [N,3], dL/dm [N])."""
+    x, y, z, m = map(_f64, (x, y, z, m))
+    w = _f64(w)
+    n = x.size
+    wx, wy, wz = (np.ascontiguousarray(w[:, k]) for k in range(3))
+    gx, gy, gz, gm = (np.empty(n) for _ in range(4))
+    lib().or_bf_adjoint(_i64(n), _ptr(x), _ptr(y), _ptr(z), _ptr(m), _ptr(wx), _ptr(wy), _ptr(wz),
+                        _d(G), _d(r_cut), _d(eps), _ptr(gx), _ptr(gy), _ptr(gz), _ptr(gm))
+    return np.stack([gx, gy, gz], axis=1), gm
+
+
+# ------------------------------------------------------------ tree steps
+def wrap(v):
+    return np.array([lib().or_wrap(float(t)) for t in np.atleast_1d(v)])
+
+
+def morton_keys(x, y, z):
+    """a1: keys in input order and the wrapped positions."""
+    x, y, z = map(_f64, (x, y, z))
+    n = x.size
+    keys = np.empty(n, dtype=np.uint64)
+    ux, uy, uz = np.empty(n), np.empty(n), np.empty(n)
+    lib().or_morton_keys(_i64(n), _ptr(x), _ptr(y), _ptr(z), _ptr(keys), _ptr(ux), _ptr(uy), _ptr(uz))
+    return keys, ux, uy, uz
+
+
+def sort_keys(keys):
+    """a2: order by (key, original index): (sorted keys, perm)."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    ks = np.empty_like(keys)
+    perm = np.empty(keys.size, dtype=np.int64)
+    lib().or_sort(_i64(keys.size), _ptr(keys), _ptr(ks), _ptr(perm))
+    return ks, perm
+
+
+@dataclass
+class Tree:
+    level: np.ndarray    # int32
+    prefix: np.ndarray   # uint64
+    first: np.ndarray    # int64
+    count: np.ndarray    # int64
+    parent: np.ndarray   # int64 (-1 for the root)
+    child: np.ndarray    # int64 [nn, 8], -1 if empty
+    leaf: np.ndarray     # uint8
+
+    @property
+    def size(self) -> int:
+        return int(self.level.size)
+
+
+def build_tree(keys_sorted, n_leaf: int) -> Tree:
+    """a3: cells in DFS preorder."""
+    ks = np.ascontiguousarray(keys_sorted, dtype=np.uint64)
+    n = ks.size
+    nn = int(lib().or_tree_count(_i64(n), _ptr(ks), _i64(n_leaf)))
+    t = Tree(np.empty(nn, np.int32), np.empty(nn, np.uint64), np.empty(nn, np.int64), np.empty(nn, np.int64),
+             np.empty(nn, np.int64), np.empty((nn, 8), np.int64), np.empty(nn, np.uint8))
+    lib().or_tree_fill(_i64(n), _ptr(ks), _i64(n_leaf), _ptr(t.level), _ptr(t.prefix), _ptr(t.first),
+                       _ptr(t.count), _ptr(t.parent), _ptr(t.child), _ptr(t.leaf))
+    return t
+
+
+def moments(tree: Tree, ux, uy, uz, m):
+    """a4: monopole mass and centre of mass of every cell (sorted-order inputs)."""
+    nn = tree.size
+    M, X, Y, Z = (np.empty(nn) for _ in range(4))
+    lib().or_moments(_i64(nn), _ptr(tree.first), _ptr(tree.count), _ptr(_f64(ux)), _ptr(_f64(uy)),
+                     _ptr(_f64(uz)), _ptr(_f64(m)), _ptr(M), _ptr(X), _ptr(Y), _ptr(Z))
+    return M, np.stack([X, Y, Z], axis=1)
+
+
+def groups(tree: Tree, n_group: int, n: int):
+    """a5: (gfirst, gcount) in order of first."""
+    gf = np.empty(max(n, 1), np.int64)
+    gc = np.empty(max(n, 1), np.int64)
+    ng = int(lib().or_groups(_ptr(tree.level), _ptr(tree.first), _ptr(tree.count), _ptr(tree.child),
+                             _i64(n_group), _ptr(gf), _ptr(gc)))
+    return gf[:ng].copy(), gc[:ng].copy()
+
+
+def group_bbox(gfirst, gcount, ux, uy, uz):
+    ng = gfirst.size
+    lo, hi = np.empty((ng, 3)), np.empty((ng, 3))
+    lib().or_group_bbox(_i64(ng), _ptr(gfirst), _ptr(gcount), _ptr(_f64(ux)), _ptr(_f64(uy)), _ptr(_f64(uz)),
+                        _ptr(lo), _ptr(hi))
+    return lo, hi
+
+
+@dataclass
+class Lists:
+    poff: np.ndarray   # int64 [ng+1]
+    pidx: np.ndarray   # int64 sorted particle indices, ascending within a group
+    noff: np.ndarray   # int64 [ng+1]
+    nidx: np.ndarray   # int64 node ids (preorder), ascending within a group
+
+
+def make_lists(tree: Tree, lo, hi, r_cut: float, theta: float) -> Lists:
+    """a6: per-group lists in canonical order (two passes: count, fill)."""
+    ng = lo.shape[0]
+    lo = _f64(lo)
+    hi = _f64(hi)
+    np_, nn_ = np.empty(ng, np.int64), np.empty(ng, np.int64)
+    args = (_ptr(tree.level), _ptr(tree.prefix), _ptr(tree.first), _ptr(tree.count), _ptr(tree.child),
+            _ptr(tree.leaf), _d(r_cut), _d(theta))
+    lib().or_lists_count(_i64(ng), _ptr(lo), _ptr(hi), *args, _ptr(np_), _ptr(nn_))
+    poff = np.zeros(ng + 1, np.int64)
+    noff = np.zeros(ng + 1, np.int64)
+    np.cumsum(np_, out=poff[1:])
+    np.cumsum(nn_, out=noff[1:])
+    pidx = np.empty(int(poff[-1]), np.int64)
+    nidx = np.empty(int(noff[-1]), np.int64)
+    lib().or_lists_fill(_i64(ng), _ptr(lo), _ptr(hi), *args, _ptr(poff), _ptr(noff), _ptr(pidx), _ptr(nidx))
+    return Lists(poff, pidx, noff, nidx)
+
+
+class OracleTree:
+    """The whole forward structure (a1-a6) for one particle set, plus the
+    same-list force (a7, a8) and the fixed-structure adjoint (a9)."""
+
+    def __init__(self, x, y, z, m, params):
+        self.params = params
+        x, y, z, m = map(_f64, (x, y, z, m))
+        self.n = x.size
+        self.keys_in, ux, uy, uz = morton_keys(x, y, z)
+        self.keys, self.perm = sort_keys(self.keys_in)
+        self.ux, self.uy, self.uz = ux[self.perm], uy[self.perm], uz[self.perm]
+        self.m = m[self.perm]
+        self.tree = build_tree(self.keys, params.n_leaf)
+        self.M, self.X = moments(self.tree, self.ux, self.uy, self.uz, self.m)
+        self.gfirst, self.gcount = groups(self.tree, params.n_group, self.n)
+        self.lo, self.hi = group_bbox(self.gfirst, self.gcount, self.ux, self.uy, self.uz)
+        self.lists = make_lists(self.tree, self.lo, self.hi, params.r_cut, params.theta)
+
+    @property
+    def n_groups(self) -> int:
+        return int(self.gfirst.size)
+
+    def interactions(self) -> int:
+        """I = sum over groups of N_i * N_j (the paper's count, Table I)."""
+        nj = np.diff(self.lists.poff) + np.diff(self.lists.noff)
+        return int(np.sum(self.gcount * nj))
+
+    def force_sorted(self, ux=None, uy=None, uz=None, m=None, sel=None):
+        """a7 in sorted order.  Optional inputs replace positions/masses with
+        the structure held fixed (moments recomputed from them)."""
+        p = self.params
+        ux = self.ux if ux is None else _f64(ux)
+        uy = self.uy if uy is None else _f64(uy)
+        uz = self.uz if uz is None else _f64(uz)
+        m = self.m if m is None else _f64(m)
+        if ux is self.ux and uy is self.uy and uz is self.uz and m is self.m:
+            M, X = self.M, self.X
+        else:
+            M, X = moments(self.tree, ux, uy, uz, m)
+        X0, X1, X2 = (np.ascontiguousarray(X[:, k]) for k in range(3))
+        ax, ay, az = np.zeros(self.n), np.zeros(self.n), np.zeros(self.n)
+        L = self.lists
+        if sel is None:
+            sel_arr, nsel = None, -1
+        else:
+            sel_arr = np.ascontiguousarray(sel, dtype=np.int64)
+            nsel = sel_arr.size
+        lib().or_tree_force(_i64(self.n_groups), _ptr(self.gfirst), _ptr(self.gcount), _ptr(L.poff), _ptr(L.pidx),
+                            _ptr(L.noff), _ptr(L.nidx), _ptr(ux), _ptr(uy), _ptr(uz), _ptr(m), _ptr(M),
+                            _ptr(X0), _ptr(X1), _ptr(X2), _d(p.G), _d(p.r_cut), _d(p.eps),
+                            _ptr(sel_arr), _i64(nsel), _ptr(ax), _ptr(ay), _ptr(az))
+        return np.stack([ax, ay, az], axis=1)
+
+    def force(self):
+        """a7 + a8: accelerations in input order."""
+        a = np.empty((self.n, 3))
+        a[self.perm] = self.force_sorted()
+        return a
+
+    def adjoint(self, w):
+        """a9: (dL/dx [N,3], dL/dm [N]) in input order for L = sum_i w_i . a_i."""
+        p = self.params
+        w = _f64(w)[self.perm]
+        wx, wy, wz = (np.ascontiguousarray(w[:, k]) for k in range(3))
+        X0, X1, X2 = (np.ascontiguousarray(self.X[:, k]) for k in range(3))
+        gx, gy, gz, gm = (np.empty(self.n) for _ in range(4))
+        L = self.lists
+        lib().or_tree_adjoint(_i64(self.n), _i64(self.n_groups), _ptr(self.gfirst), _ptr(self.gcount),
+                              _ptr(L.poff), _ptr(L.pidx), _ptr(L.noff), _ptr(L.nidx),
+                              _i64(self.tree.size), _ptr(self.tree.first), _ptr(self.tree.count),
+                              _ptr(self.ux), _ptr(self.uy), _ptr(self.uz), _ptr(self.m), _ptr(self.M),
+                              _ptr(X0), _ptr(X1), _ptr(X2), _ptr(wx), _ptr(wy), _ptr(wz),
+                              _d(p.G), _d(p.r_cut), _d(p.eps), _ptr(gx), _ptr(gy), _ptr(gz), _ptr(gm))
+        gxs = np.stack([gx, gy, gz], axis=1)
+        out_x = np.empty_like(gxs)
+        out_m = np.empty_like(gm)
+        out_x[self.perm] = gxs
+        out_m[self.perm] = gm
+        return out_x, out_m
+
+    def loss(self, w, ux=None, uy=None, uz=None, m=None):
+        """L = sum_i w_i . a_i with the structure fixed; w in input order."""
+        a = self.force_sorted(ux, uy, uz, m)
+        return float(np.sum(_f64(w)[self.perm] * a))
+
+
+def relative_errors(a, ref):
+    """Per-particle |a - ref| / |ref| over particles with |ref| > 0, and
+    summary statistics (rms, median, p99, max, global L2 ratio)."""
+    a = np.asarray(a, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    nr = np.linalg.norm(ref, axis=1)
+    nz = nr > 0
+    e = np.linalg.norm(a - ref, axis=1)[nz] / nr[nz]
+    if e.size == 0:
+        return e, dict(rms=0.0, median=0.0, p99=0.0, max=0.0, l2=0.0, n_zero_ref=int((~nz).sum()))
+    stats = dict(rms=float(np.sqrt(np.mean(e * e))), median=float(np.median(e)),
+                 p99=float(np.percentile(e, 99)), max=float(e.max()),
+                 l2=float(np.linalg.norm(a - ref) / max(np.linalg.norm(ref), 1e-300)),
+                 n_zero_ref=int((~nz).sum()))
+    return e, stats

@@ -1,0 +1,739 @@
+/*
+ * srf_oracle.c -- plain FP64 CPU reference of the short-range TreePM step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path links, loads or
+ * calls this file: only the tests, the smoke check and the benchmark's CPU
+ * baseline do.  It shares no code, header or constant table with the GPU
+ * library; every rule below is written out again from the paper
+ * (Ishiyama, Nitadori & Makino, SC12, "4.45 Pflops Astrophysical N-Body
+ * Simulation on K computer") and from the readings listed beside each
+ * function where the paper is silent.
+ *
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC.  No FMA
+ * contraction anywhere: the tree decisions must be the literal expressions.
+ *
+ * Conventions
+ *   - box [0,1)^3, periodic; minimum image per axis: d -= rint(d);
+ *   - "sorted" arrays are indexed by sorted position s; perm[s] is the
+ *     original index of the particle at sorted position s;
+ *   - node arrays are in DFS preorder (parent before children, children in
+ *     octant order), i.e. ordered by (first, level) ascending;
+ *   - G multiplies every force and gradient.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define KEY_BITS 21          /* bits per axis of the Morton key */
+#define MAX_LEVEL 21         /* deepest tree level */
+
+int or_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ================================================================== */
+/* Cutoff function and pair kernel                                     */
+/* ================================================================== */
+
+/* g_P3M(xi): Sec. 2, eq. (cutoff).  The degree-8 polynomial on [0,2]
+ * with the zeta = max(0, xi - 1) branch term, and 0 for xi > 2.
+ * Written in expanded monomials, not in the nested form of the paper. */
+double or_gcut(double xi) {
+    if (xi > 2.0) return 0.0;
+    double zeta = xi - 1.0 > 0.0 ? xi - 1.0 : 0.0;
+    double x2 = xi * xi, x3 = x2 * xi, x5 = x3 * x2, x6 = x5 * xi, x7 = x6 * xi, x8 = x7 * xi;
+    double first = 1.0 - (8.0 / 5.0) * x3 + (8.0 / 5.0) * x5 - 0.5 * x6
+                 - (12.0 / 35.0) * x7 + (3.0 / 20.0) * x8;
+    double second = pow(zeta, 6.0) * (3.0 / 35.0 + (18.0 / 35.0) * xi + (1.0 / 5.0) * x2);
+    return first - second;
+}
+
+/* dg/dxi, differentiated term by term from the same monomials. */
+double or_gcut_deriv(double xi) {
+    if (xi > 2.0) return 0.0;
+    double zeta = xi - 1.0 > 0.0 ? xi - 1.0 : 0.0;
+    double x2 = xi * xi, x4 = x2 * x2, x5 = x4 * xi, x6 = x5 * xi, x7 = x6 * xi;
+    double first = -(24.0 / 5.0) * x2 + 8.0 * x4 - 3.0 * x5 - (12.0 / 5.0) * x6 + (6.0 / 5.0) * x7;
+    double q = 3.0 / 35.0 + (18.0 / 35.0) * xi + (1.0 / 5.0) * x2;
+    double dq = 18.0 / 35.0 + (2.0 / 5.0) * xi;
+    return first - (6.0 * pow(zeta, 5.0) * q + pow(zeta, 6.0) * dq);
+}
+
+void or_gcut_vec(int64_t n, const double* xi, double* g, double* dg) {
+    for (int64_t k = 0; k < n; ++k) {
+        g[k] = or_gcut(xi[k]);
+        if (dg) dg[k] = or_gcut_deriv(xi[k]);
+    }
+}
+
+/* phi(r) = (r^2 + eps^2)^(-3/2) * g(2 r / r_cut) for r < r_cut, else 0.
+ * Sec. 2 force sum; the Plummer form replaces the delta function by a small
+ * kernel (the paper's "small softening"), and the cutoff argument uses the
+ * unsoftened distance, as in the force sum. */
+static double phi_of(double r2, double rc, double eps) {
+    if (!(r2 < rc * rc)) return 0.0;
+    double r = sqrt(r2);
+    double s2 = r2 + eps * eps;
+    return or_gcut(2.0 * r / rc) / (s2 * sqrt(s2));
+}
+
+/* (d phi / d r) / r for 0 < r < r_cut (0 beyond).  Only used with r > 0. */
+static double dphi_over_r(double r2, double rc, double eps) {
+    if (!(r2 < rc * rc)) return 0.0;
+    double r = sqrt(r2);
+    double s2 = r2 + eps * eps;
+    double s = sqrt(s2);
+    double xi = 2.0 * r / rc;
+    double dphidr = -3.0 * r / (s2 * s2 * s) * or_gcut(xi) + or_gcut_deriv(xi) * (2.0 / rc) / (s2 * s);
+    return dphidr / r;
+}
+
+/* Pair force F(d) = d * phi(|d|) (the attraction of a unit source at offset d). */
+void or_pair_force(double dx, double dy, double dz, double rc, double eps, double* f) {
+    double p = phi_of(dx * dx + dy * dy + dz * dz, rc, eps);
+    f[0] = dx * p; f[1] = dy * p; f[2] = dz * p;
+}
+
+/* J(d) w with J = dF/dd = phi I + (phi'/r) d d^T; at d = 0 only phi I. */
+static void jac_times(double dx, double dy, double dz, double rc, double eps,
+                      const double* w, double* out) {
+    double r2 = dx * dx + dy * dy + dz * dz;
+    double p = phi_of(r2, rc, eps);
+    out[0] = p * w[0]; out[1] = p * w[1]; out[2] = p * w[2];
+    if (r2 > 0.0) {
+        double q = dphi_over_r(r2, rc, eps) * (dx * w[0] + dy * w[1] + dz * w[2]);
+        out[0] += q * dx; out[1] += q * dy; out[2] += q * dz;
+    }
+}
+
+void or_pair_jac(double dx, double dy, double dz, double rc, double eps, const double* w, double* out) {
+    jac_times(dx, dy, dz, rc, eps, w, out);
+}
+
+/* Minimum image of one coordinate difference (periodic unit box). */
+static double mimage(double d) { return d - rint(d); }
+
+/* ================================================================== */
+/* Brute force (the plain definition of the short-range sum)           */
+/* ================================================================== */
+
+/* O(N^2) minimum-image sum over all pairs; j = i contributes 0 (d = 0). */
+void or_bf_n2(int64_t n, const double* x, const double* y, const double* z, const double* m,
+              double G, double rc, double eps, double* ax, double* ay, double* az) {
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        double a[3] = {0, 0, 0};
+        for (int64_t j = 0; j < n; ++j) {
+            double d[3] = {mimage(x[j] - x[i]), mimage(y[j] - y[i]), mimage(z[j] - z[i])};
+            double p = phi_of(d[0] * d[0] + d[1] * d[1] + d[2] * d[2], rc, eps);
+            a[0] += m[j] * d[0] * p; a[1] += m[j] * d[1] * p; a[2] += m[j] * d[2] * p;
+        }
+        ax[i] = G * a[0]; ay[i] = G * a[1]; az[i] = G * a[2];
+    }
+}
+
+/* Cell list with cell side >= r_cut: every partner within r_cut lies in the
+ * 27 cells around a particle's own cell.  Needs at least 3 cells per axis. */
+typedef struct { int nc; int64_t* start; int64_t* idx; } cells_t;
+
+static int cell_coord(double v, int nc) {
+    double u = v - floor(v);
+    if (u >= 1.0) u = 0.0;
+    int c = (int)floor(u * nc);
+    return c >= nc ? nc - 1 : c;
+}
+
+static int cells_build(int64_t n, const double* x, const double* y, const double* z, double rc, cells_t* cl) {
+    int nc = (int)floor(1.0 / rc);
+    if (nc > 256) nc = 256;
+    if (nc < 3) return 0;
+    int64_t ncell = (int64_t)nc * nc * nc;
+    int64_t* cnt = (int64_t*)calloc((size_t)ncell + 1, sizeof(int64_t));
+    int64_t* cid = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c = ((int64_t)cell_coord(x[i], nc) * nc + cell_coord(y[i], nc)) * nc + cell_coord(z[i], nc);
+        cid[i] = c; cnt[c + 1]++;
+    }
+    for (int64_t c = 0; c < ncell; ++c) cnt[c + 1] += cnt[c];
+    int64_t* fill = (int64_t*)malloc((size_t)ncell * sizeof(int64_t));
+    memcpy(fill, cnt, (size_t)ncell * sizeof(int64_t));
+    int64_t* idx = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i) idx[fill[cid[i]]++] = i;
+    free(fill); free(cid);
+    cl->nc = nc; cl->start = cnt; cl->idx = idx;
+    return 1;
+}
+
+static void cells_free(cells_t* cl) { free(cl->start); free(cl->idx); }
+
+/* Exact short-range accelerations by brute force over the cell list.
+ * Returns 0 on success, 1 if the box has fewer than 3 cells per axis
+ * (then the O(N^2) routine is used instead). */
+int or_bf_cells(int64_t n, const double* x, const double* y, const double* z, const double* m,
+                double G, double rc, double eps, double* ax, double* ay, double* az) {
+    cells_t cl;
+    if (!cells_build(n, x, y, z, rc, &cl)) {
+        or_bf_n2(n, x, y, z, m, G, rc, eps, ax, ay, az);
+        return 1;
+    }
+    int nc = cl.nc;
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        int cx = cell_coord(x[i], nc), cy = cell_coord(y[i], nc), cz = cell_coord(z[i], nc);
+        double a[3] = {0, 0, 0};
+        for (int ox = -1; ox <= 1; ++ox)
+        for (int oy = -1; oy <= 1; ++oy)
+        for (int oz = -1; oz <= 1; ++oz) {
+            int64_t c = ((int64_t)((cx + ox + nc) % nc) * nc + (cy + oy + nc) % nc) * nc + (cz + oz + nc) % nc;
+            for (int64_t q = cl.start[c]; q < cl.start[c + 1]; ++q) {
+                int64_t j = cl.idx[q];
+                double d[3] = {mimage(x[j] - x[i]), mimage(y[j] - y[i]), mimage(z[j] - z[i])};
+                double p = phi_of(d[0] * d[0] + d[1] * d[1] + d[2] * d[2], rc, eps);
+                a[0] += m[j] * d[0] * p; a[1] += m[j] * d[1] * p; a[2] += m[j] * d[2] * p;
+            }
+        }
+        ax[i] = G * a[0]; ay[i] = G * a[1]; az[i] = G * a[2];
+    }
+    cells_free(&cl);
+    return 0;
+}
+
+/* Number of ordered pairs (i, j != i) closer than r_cut (cell list). */
+int64_t or_bf_pair_count(int64_t n, const double* x, const double* y, const double* z, double rc) {
+    cells_t cl;
+    int64_t total = 0;
+    if (!cells_build(n, x, y, z, rc, &cl)) {
+        #pragma omp parallel for reduction(+:total)
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < n; ++j) {
+                if (j == i) continue;
+                double d[3] = {mimage(x[j] - x[i]), mimage(y[j] - y[i]), mimage(z[j] - z[i])};
+                if (d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < rc * rc) total++;
+            }
+        return total;
+    }
+    int nc = cl.nc;
+    #pragma omp parallel for schedule(dynamic, 64) reduction(+:total)
+    for (int64_t i = 0; i < n; ++i) {
+        int cx = cell_coord(x[i], nc), cy = cell_coord(y[i], nc), cz = cell_coord(z[i], nc);
+        for (int ox = -1; ox <= 1; ++ox)
+        for (int oy = -1; oy <= 1; ++oy)
+        for (int oz = -1; oz <= 1; ++oz) {
+            int64_t c = ((int64_t)((cx + ox + nc) % nc) * nc + (cy + oy + nc) % nc) * nc + (cz + oz + nc) % nc;
+            for (int64_t q = cl.start[c]; q < cl.start[c + 1]; ++q) {
+                int64_t j = cl.idx[q];
+                if (j == i) continue;
+                double d[3] = {mimage(x[j] - x[i]), mimage(y[j] - y[i]), mimage(z[j] - z[i])};
+                if (d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < rc * rc) total++;
+            }
+        }
+    }
+    cells_free(&cl);
+    return total;
+}
+
+/* Brute-force gradient of L = sum_i w_i . a_i:
+ *   dL/dx_k = G sum_j J(x_j - x_k) (m_k w_j - m_j w_k)
+ *   dL/dm_k = G sum_i w_i . F(x_k - x_i)
+ * (J is even in d, so both the "i = k" and "j = k" terms use d = x_j - x_k.) */
+void or_bf_adjoint(int64_t n, const double* x, const double* y, const double* z, const double* m,
+                   const double* wx, const double* wy, const double* wz,
+                   double G, double rc, double eps, double* gx, double* gy, double* gz, double* gm) {
+    cells_t cl;
+    int have_cells = cells_build(n, x, y, z, rc, &cl);
+    int nc = have_cells ? cl.nc : 0;
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t k = 0; k < n; ++k) {
+        double g3[3] = {0, 0, 0}, gmk = 0.0;
+        int cx = 0, cy = 0, cz = 0;
+        if (have_cells) { cx = cell_coord(x[k], nc); cy = cell_coord(y[k], nc); cz = cell_coord(z[k], nc); }
+        int span = have_cells ? 1 : 0;
+        for (int ox = -span; ox <= span; ++ox)
+        for (int oy = -span; oy <= span; ++oy)
+        for (int oz = -span; oz <= span; ++oz) {
+            int64_t q0, q1;
+            int64_t c = 0;
+            if (have_cells) {
+                c = ((int64_t)((cx + ox + nc) % nc) * nc + (cy + oy + nc) % nc) * nc + (cz + oz + nc) % nc;
+                q0 = cl.start[c]; q1 = cl.start[c + 1];
+            } else { q0 = 0; q1 = n; }
+            for (int64_t q = q0; q < q1; ++q) {
+                int64_t j = have_cells ? cl.idx[q] : q;
+                double d[3] = {mimage(x[j] - x[k]), mimage(y[j] - y[k]), mimage(z[j] - z[k])};
+                double v[3] = {m[k] * wx[j] - m[j] * wx[k], m[k] * wy[j] - m[j] * wy[k], m[k] * wz[j] - m[j] * wz[k]};
+                double jv[3];
+                jac_times(d[0], d[1], d[2], rc, eps, v, jv);
+                g3[0] += jv[0]; g3[1] += jv[1]; g3[2] += jv[2];
+                /* F(x_k - x_j) = -F(d) */
+                double p = phi_of(d[0] * d[0] + d[1] * d[1] + d[2] * d[2], rc, eps);
+                gmk -= (wx[j] * d[0] + wy[j] * d[1] + wz[j] * d[2]) * p;
+            }
+        }
+        gx[k] = G * g3[0]; gy[k] = G * g3[1]; gz[k] = G * g3[2]; gm[k] = G * gmk;
+    }
+    if (have_cells) cells_free(&cl);
+}
+
+/* ================================================================== */
+/* Morton keys and the stable sort                                     */
+/* ================================================================== */
+
+/* Wrap into [0,1): u = v - floor(v), and u == 1.0 (a tiny negative v)
+ * becomes 0.0. */
+double or_wrap(double v) {
+    double u = v - floor(v);
+    return u == 1.0 ? 0.0 : u;
+}
+
+/* Integer cell coordinate of a wrapped coordinate on the 2^21 grid. */
+static uint32_t grid_coord(double u) {
+    double c = floor(u * 2097152.0);       /* 2^21; the product is exact */
+    if (c > 2097151.0) c = 2097151.0;
+    return (uint32_t)c;
+}
+
+/* 63-bit Morton key: bit 3b+2 is bit b of the x coordinate, 3b+1 of y,
+ * 3b of z (x most significant within each triple).  Written as a plain
+ * loop over the 21 bit positions. */
+uint64_t or_morton3(uint32_t ix, uint32_t iy, uint32_t iz) {
+    uint64_t k = 0;
+    for (int b = 0; b < KEY_BITS; ++b) {
+        k |= (uint64_t)((ix >> b) & 1u) << (3 * b + 2);
+        k |= (uint64_t)((iy >> b) & 1u) << (3 * b + 1);
+        k |= (uint64_t)((iz >> b) & 1u) << (3 * b);
+    }
+    return k;
+}
+
+/* Keys of all particles in input order, and the wrapped positions. */
+void or_morton_keys(int64_t n, const double* x, const double* y, const double* z,
+                    uint64_t* keys, double* ux, double* uy, double* uz) {
+    for (int64_t i = 0; i < n; ++i) {
+        double a = or_wrap(x[i]), b = or_wrap(y[i]), c = or_wrap(z[i]);
+        if (ux) { ux[i] = a; uy[i] = b; uz[i] = c; }
+        keys[i] = or_morton3(grid_coord(a), grid_coord(b), grid_coord(c));
+    }
+}
+
+typedef struct { uint64_t key; int64_t idx; } keyidx_t;
+
+static int cmp_keyidx(const void* a, const void* b) {
+    const keyidx_t* p = (const keyidx_t*)a;
+    const keyidx_t* q = (const keyidx_t*)b;
+    if (p->key != q->key) return p->key < q->key ? -1 : 1;
+    if (p->idx != q->idx) return p->idx < q->idx ? -1 : 1;
+    return 0;
+}
+
+/* Order by (key, original index): a total order, so the permutation is
+ * unique (the same as a stable sort by key). */
+void or_sort(int64_t n, const uint64_t* keys, uint64_t* keys_sorted, int64_t* perm) {
+    keyidx_t* t = (keyidx_t*)malloc((size_t)n * sizeof(keyidx_t));
+    for (int64_t i = 0; i < n; ++i) { t[i].key = keys[i]; t[i].idx = i; }
+    qsort(t, (size_t)n, sizeof(keyidx_t), cmp_keyidx);
+    for (int64_t i = 0; i < n; ++i) { keys_sorted[i] = t[i].key; perm[i] = t[i].idx; }
+    free(t);
+}
+
+/* ================================================================== */
+/* Octree (Barnes-Hut cells over the Morton order)                     */
+/* ================================================================== */
+
+/* A cell at level L is the set of particles whose keys share the top 3L
+ * bits (the prefix).  The root (level 0) is always split; any other cell
+ * is split iff it holds more than n_leaf particles and L < 21.  Children
+ * are the non-empty sub-cells, visited in octant order. */
+typedef struct {
+    const uint64_t* keys;
+    int64_t n_leaf;
+    int64_t next;
+    int fill;
+    int32_t* level; uint64_t* prefix; int64_t* first; int64_t* count;
+    int64_t* parent; int64_t* child; uint8_t* leaf;
+} tree_ctx;
+
+static int64_t tree_rec(tree_ctx* c, int level, uint64_t prefix, int64_t first, int64_t count, int64_t parent) {
+    int64_t id = c->next++;
+    int split = (level == 0) || (level < MAX_LEVEL && count > c->n_leaf);
+    if (c->fill) {
+        c->level[id] = level; c->prefix[id] = prefix; c->first[id] = first; c->count[id] = count;
+        c->parent[id] = parent; c->leaf[id] = (uint8_t)!split;
+        for (int o = 0; o < 8; ++o) c->child[id * 8 + o] = -1;
+    }
+    if (!split) return id;
+    int shift = 3 * (MAX_LEVEL - (level + 1));
+    int64_t s = first, end = first + count;
+    for (int o = 0; o < 8; ++o) {
+        uint64_t cp = prefix * 8 + (uint64_t)o;
+        int64_t e = s;
+        while (e < end && (c->keys[e] >> shift) == cp) ++e;
+        if (e > s) {
+            int64_t cid = tree_rec(c, level + 1, cp, s, e - s, id);
+            if (c->fill) c->child[id * 8 + o] = cid;
+        }
+        s = e;
+    }
+    return id;
+}
+
+int64_t or_tree_count(int64_t n, const uint64_t* keys_sorted, int64_t n_leaf) {
+    tree_ctx c; memset(&c, 0, sizeof c);
+    c.keys = keys_sorted; c.n_leaf = n_leaf;
+    tree_rec(&c, 0, 0, 0, n, -1);
+    return c.next;
+}
+
+void or_tree_fill(int64_t n, const uint64_t* keys_sorted, int64_t n_leaf,
+                  int32_t* level, uint64_t* prefix, int64_t* first, int64_t* count,
+                  int64_t* parent, int64_t* child, uint8_t* leaf) {
+    tree_ctx c; memset(&c, 0, sizeof c);
+    c.keys = keys_sorted; c.n_leaf = n_leaf; c.fill = 1;
+    c.level = level; c.prefix = prefix; c.first = first; c.count = count;
+    c.parent = parent; c.child = child; c.leaf = leaf;
+    tree_rec(&c, 0, 0, 0, n, -1);
+}
+
+/* Monopole moments, directly from the definition: M = sum m, X = sum m x / M
+ * over the particles of the cell (Sec. 1 multipole expansion of a cell,
+ * truncated at the monopole with the centre of mass as expansion point). */
+void or_moments(int64_t nn, const int64_t* first, const int64_t* count,
+                const double* ux, const double* uy, const double* uz, const double* m,
+                double* M, double* X, double* Y, double* Z) {
+    #pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t c = 0; c < nn; ++c) {
+        double sm = 0, sx = 0, sy = 0, sz = 0;
+        for (int64_t s = first[c]; s < first[c] + count[c]; ++s) {
+            sm += m[s]; sx += m[s] * ux[s]; sy += m[s] * uy[s]; sz += m[s] * uz[s];
+        }
+        M[c] = sm; X[c] = sx / sm; Y[c] = sy / sm; Z[c] = sz / sm;
+    }
+}
+
+/* ================================================================== */
+/* Groups (Barnes' modified algorithm: one list per particle group)    */
+/* ================================================================== */
+
+/* A candidate is a cell at level >= 1 with at most n_g particles whose
+ * parent is the root or holds more than n_g.  Under a parent of level >= 1
+ * consecutive candidate children (octant order) are merged while the
+ * running total stays <= n_g; a non-candidate child or an overflow closes
+ * the run.  Under the root every candidate child is its own group.  A
+ * level-21 cell with more than n_g particles is cut into chunks of n_g. */
+typedef struct {
+    const int32_t* level; const int64_t* first; const int64_t* count; const int64_t* child;
+    int64_t n_g;
+    int64_t ng;
+    int64_t* gfirst; int64_t* gcount;
+} group_ctx;
+
+static void emit_group(group_ctx* c, int64_t first, int64_t count) {
+    c->gfirst[c->ng] = first; c->gcount[c->ng] = count; c->ng++;
+}
+
+static void group_rec(group_ctx* c, int64_t node) {
+    if (c->level[node] == MAX_LEVEL) {
+        for (int64_t s = 0; s < c->count[node]; s += c->n_g) {
+            int64_t k = c->count[node] - s < c->n_g ? c->count[node] - s : c->n_g;
+            emit_group(c, c->first[node] + s, k);
+        }
+        return;
+    }
+    int merge = c->level[node] >= 1;
+    int64_t run_first = -1, run_count = 0;
+    for (int o = 0; o < 8; ++o) {
+        int64_t ch = c->child[node * 8 + o];
+        if (ch < 0) continue;
+        if (c->count[ch] <= c->n_g) {
+            if (merge && run_first >= 0 && run_count + c->count[ch] <= c->n_g) {
+                run_count += c->count[ch];
+            } else {
+                if (run_first >= 0) emit_group(c, run_first, run_count);
+                run_first = c->first[ch]; run_count = c->count[ch];
+            }
+        } else {
+            if (run_first >= 0) emit_group(c, run_first, run_count);
+            run_first = -1; run_count = 0;
+            group_rec(c, ch);
+        }
+    }
+    if (run_first >= 0) emit_group(c, run_first, run_count);
+}
+
+/* Groups in order of first; gfirst/gcount need capacity n.  Returns the count. */
+int64_t or_groups(const int32_t* level, const int64_t* first, const int64_t* count, const int64_t* child,
+                  int64_t n_g, int64_t* gfirst, int64_t* gcount) {
+    group_ctx c;
+    c.level = level; c.first = first; c.count = count; c.child = child; c.n_g = n_g;
+    c.ng = 0; c.gfirst = gfirst; c.gcount = gcount;
+    group_rec(&c, 0);
+    return c.ng;
+}
+
+/* Tight bounding box of each group's wrapped positions. */
+void or_group_bbox(int64_t ng, const int64_t* gfirst, const int64_t* gcount,
+                   const double* ux, const double* uy, const double* uz, double* lo, double* hi) {
+    const double* u[3] = {ux, uy, uz};
+    for (int64_t g = 0; g < ng; ++g)
+        for (int a = 0; a < 3; ++a) {
+            double l = u[a][gfirst[g]], h = l;
+            for (int64_t s = gfirst[g]; s < gfirst[g] + gcount[g]; ++s) {
+                if (u[a][s] < l) l = u[a][s];
+                if (u[a][s] > h) h = u[a][s];
+            }
+            lo[3 * g + a] = l; hi[3 * g + a] = h;
+        }
+}
+
+/* ================================================================== */
+/* Interaction lists                                                    */
+/* ================================================================== */
+
+/* Integer coordinates of a cell from its prefix (de-interleave). */
+static void cell_ints(int level, uint64_t prefix, int64_t* ix, int64_t* iy, int64_t* iz) {
+    int64_t a = 0, b = 0, c = 0;
+    for (int l = 0; l < level; ++l) {
+        uint64_t t = (prefix >> (3 * l)) & 7u;
+        a |= (int64_t)((t >> 2) & 1u) << l;
+        b |= (int64_t)((t >> 1) & 1u) << l;
+        c |= (int64_t)(t & 1u) << l;
+    }
+    *ix = a; *iy = b; *iz = c;
+}
+
+/* Geometric centre and side of a cell: exact dyadic numbers. */
+static void cell_geom(int level, uint64_t prefix, double cen[3], double* side) {
+    int64_t i[3];
+    cell_ints(level, prefix, &i[0], &i[1], &i[2]);
+    for (int a = 0; a < 3; ++a) cen[a] = ldexp((double)i[a] + 0.5, -level);
+    *side = ldexp(1.0, -level);
+}
+
+/* Per-axis periodic gap between the cell centre and the group box, less
+ * `half`; squared distance with the association ((x + y) + z). */
+static double gap2(const double cen[3], const double cg[3], const double hg[3], double half_c) {
+    double e[3];
+    for (int a = 0; a < 3; ++a) {
+        double t = fabs(cen[a] - cg[a]);
+        double t2 = 1.0 - t;
+        if (t2 < t) t = t2;
+        double r = t - (half_c + hg[a]);
+        e[a] = r > 0.0 ? r : 0.0;
+    }
+    return (e[0] * e[0] + e[1] * e[1]) + e[2] * e[2];
+}
+
+/* Cutoff pruning (Fig. 2: only sources within r_cut interact): the exact
+ * periodic box-box distance between cell and group box is >= r_cut. */
+static int prune_cell(const double cen[3], double side, const double cg[3], const double hg[3], double rc) {
+    return gap2(cen, cg, hg, side * 0.5) >= rc * rc;
+}
+
+/* Opening criterion: accept the cell as one monopole iff side^2 <
+ * theta^2 d^2, d = distance from the group box to the cell centre. */
+static int accept_cell(const double cen[3], double side, const double cg[3], const double hg[3], double theta) {
+    double d2 = gap2(cen, cg, hg, 0.0);
+    return side * side < (theta * theta) * d2;
+}
+
+typedef struct {
+    const int32_t* level; const uint64_t* prefix; const int64_t* first; const int64_t* count;
+    const int64_t* child; const uint8_t* leaf;
+    double rc, theta;
+    double cg[3], hg[3];
+    int64_t np, nn;
+    int64_t* pidx; int64_t* nidx;     /* NULL in the counting pass */
+} list_ctx;
+
+static void list_rec(list_ctx* c, int64_t node) {
+    double cen[3], side;
+    cell_geom(c->level[node], c->prefix[node], cen, &side);
+    if (prune_cell(cen, side, c->cg, c->hg, c->rc)) return;
+    if (accept_cell(cen, side, c->cg, c->hg, c->theta)) {
+        if (c->nidx) c->nidx[c->nn] = node;
+        c->nn++;
+        return;
+    }
+    if (c->leaf[node]) {
+        for (int64_t s = c->first[node]; s < c->first[node] + c->count[node]; ++s) {
+            if (c->pidx) c->pidx[c->np] = s;
+            c->np++;
+        }
+        return;
+    }
+    for (int o = 0; o < 8; ++o) {
+        int64_t ch = c->child[node * 8 + o];
+        if (ch >= 0) list_rec(c, ch);
+    }
+}
+
+static void group_frame(const double* lo, const double* hi, int64_t g, double cg[3], double hg[3]) {
+    for (int a = 0; a < 3; ++a) {
+        cg[a] = (lo[3 * g + a] + hi[3 * g + a]) * 0.5;
+        hg[a] = (hi[3 * g + a] - lo[3 * g + a]) * 0.5;
+    }
+}
+
+/* Pass 1: particle and node entry counts per group. */
+void or_lists_count(int64_t ng, const double* lo, const double* hi,
+                    const int32_t* level, const uint64_t* prefix, const int64_t* first, const int64_t* count,
+                    const int64_t* child, const uint8_t* leaf, double rc, double theta,
+                    int64_t* np, int64_t* nn) {
+    #pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t g = 0; g < ng; ++g) {
+        list_ctx c;
+        memset(&c, 0, sizeof c);
+        c.level = level; c.prefix = prefix; c.first = first; c.count = count; c.child = child; c.leaf = leaf;
+        c.rc = rc; c.theta = theta;
+        group_frame(lo, hi, g, c.cg, c.hg);
+        list_rec(&c, 0);
+        np[g] = c.np; nn[g] = c.nn;
+    }
+}
+
+/* Pass 2: entries at the given offsets.  DFS order gives the canonical
+ * form directly: particle indices ascending, nodes in preorder. */
+void or_lists_fill(int64_t ng, const double* lo, const double* hi,
+                   const int32_t* level, const uint64_t* prefix, const int64_t* first, const int64_t* count,
+                   const int64_t* child, const uint8_t* leaf, double rc, double theta,
+                   const int64_t* poff, const int64_t* noff, int64_t* pidx, int64_t* nidx) {
+    #pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t g = 0; g < ng; ++g) {
+        list_ctx c;
+        memset(&c, 0, sizeof c);
+        c.level = level; c.prefix = prefix; c.first = first; c.count = count; c.child = child; c.leaf = leaf;
+        c.rc = rc; c.theta = theta;
+        group_frame(lo, hi, g, c.cg, c.hg);
+        c.pidx = pidx + poff[g]; c.nidx = nidx + noff[g];
+        list_rec(&c, 0);
+    }
+}
+
+/* ================================================================== */
+/* Same-list force and its adjoint                                     */
+/* ================================================================== */
+
+/* For every group g and member i: a_i = G [ sum_{j in P_g} m_j F(x_j - x_i)
+ *                                         + sum_{c in M_g} M_c F(X_c - x_i) ].
+ * All arrays are in sorted order; `sel`/`nsel` optionally restrict the
+ * groups evaluated (nsel < 0: all groups). */
+void or_tree_force(int64_t ng, const int64_t* gfirst, const int64_t* gcount,
+                   const int64_t* poff, const int64_t* pidx, const int64_t* noff, const int64_t* nidx,
+                   const double* ux, const double* uy, const double* uz, const double* m,
+                   const double* NM, const double* NX, const double* NY, const double* NZ,
+                   double G, double rc, double eps, const int64_t* sel, int64_t nsel,
+                   double* ax, double* ay, double* az) {
+    int64_t todo = nsel < 0 ? ng : nsel;
+    #pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < todo; ++q) {
+        int64_t g = nsel < 0 ? q : sel[q];
+        for (int64_t i = gfirst[g]; i < gfirst[g] + gcount[g]; ++i) {
+            double a[3] = {0, 0, 0};
+            for (int64_t e = poff[g]; e < poff[g + 1]; ++e) {
+                int64_t j = pidx[e];
+                double d[3] = {mimage(ux[j] - ux[i]), mimage(uy[j] - uy[i]), mimage(uz[j] - uz[i])};
+                double p = phi_of(d[0] * d[0] + d[1] * d[1] + d[2] * d[2], rc, eps);
+                a[0] += m[j] * d[0] * p; a[1] += m[j] * d[1] * p; a[2] += m[j] * d[2] * p;
+            }
+            for (int64_t e = noff[g]; e < noff[g + 1]; ++e) {
+                int64_t c = nidx[e];
+                double d[3] = {mimage(NX[c] - ux[i]), mimage(NY[c] - uy[i]), mimage(NZ[c] - uz[i])};
+                double p = phi_of(d[0] * d[0] + d[1] * d[1] + d[2] * d[2], rc, eps);
+                a[0] += NM[c] * d[0] * p; a[1] += NM[c] * d[1] * p; a[2] += NM[c] * d[2] * p;
+            }
+            ax[i] = G * a[0]; ay[i] = G * a[1]; az[i] = G * a[2];
+        }
+    }
+}
+
+/* Gradient of L = sum_i w_i . a_i with perm, tree, groups and lists held
+ * fixed.  For each pair (i, source s of mass mu at y):
+ *     dL/dx_i -= G mu J w_i,  dL/dy_s += G mu J w_i,  dL/dmu_s += G w_i . F(d).
+ * Node sources then pass their gradients to member particles through
+ * M_c = sum m_k and X_c = sum m_k x_k / M_c:
+ *     dL/dx_k += (m_k / M_c) dL/dX_c,
+ *     dL/dm_k += dL/dM_c + (x_k - X_c) . dL/dX_c / M_c.
+ * Scatter contributions are accumulated per thread and summed afterwards. */
+void or_tree_adjoint(int64_t n, int64_t ng, const int64_t* gfirst, const int64_t* gcount,
+                     const int64_t* poff, const int64_t* pidx, const int64_t* noff, const int64_t* nidx,
+                     int64_t nnodes, const int64_t* nfirst, const int64_t* ncount,
+                     const double* ux, const double* uy, const double* uz, const double* m,
+                     const double* NM, const double* NX, const double* NY, const double* NZ,
+                     const double* wx, const double* wy, const double* wz,
+                     double G, double rc, double eps,
+                     double* gx, double* gy, double* gz, double* gm) {
+    int nt = or_num_threads();
+    /* per-thread scatter buffers: particles (4 per particle) and nodes (4 per node) */
+    double* pbuf = (double*)calloc((size_t)nt * (size_t)n * 4, sizeof(double));
+    double* nbuf = (double*)calloc((size_t)nt * (size_t)nnodes * 4, sizeof(double));
+    #pragma omp parallel
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double* pb = pbuf + (size_t)tid * (size_t)n * 4;
+        double* nb = nbuf + (size_t)tid * (size_t)nnodes * 4;
+        #pragma omp for schedule(dynamic, 4)
+        for (int64_t g = 0; g < ng; ++g) {
+            for (int64_t i = gfirst[g]; i < gfirst[g] + gcount[g]; ++i) {
+                double w[3] = {wx[i], wy[i], wz[i]};
+                for (int64_t e = poff[g]; e < poff[g + 1]; ++e) {
+                    int64_t j = pidx[e];
+                    double d[3] = {mimage(ux[j] - ux[i]), mimage(uy[j] - uy[i]), mimage(uz[j] - uz[i])};
+                    double jw[3];
+                    jac_times(d[0], d[1], d[2], rc, eps, w, jw);
+                    double p = phi_of(d[0] * d[0] + d[1] * d[1] + d[2] * d[2], rc, eps);
+                    for (int a = 0; a < 3; ++a) {
+                        pb[4 * i + a] -= m[j] * jw[a];
+                        pb[4 * j + a] += m[j] * jw[a];
+                    }
+                    pb[4 * j + 3] += (w[0] * d[0] + w[1] * d[1] + w[2] * d[2]) * p;
+                }
+                for (int64_t e = noff[g]; e < noff[g + 1]; ++e) {
+                    int64_t c = nidx[e];
+                    double d[3] = {mimage(NX[c] - ux[i]), mimage(NY[c] - uy[i]), mimage(NZ[c] - uz[i])};
+                    double jw[3];
+                    jac_times(d[0], d[1], d[2], rc, eps, w, jw);
+                    double p = phi_of(d[0] * d[0] + d[1] * d[1] + d[2] * d[2], rc, eps);
+                    for (int a = 0; a < 3; ++a) {
+                        pb[4 * i + a] -= NM[c] * jw[a];
+                        nb[4 * c + a] += NM[c] * jw[a];
+                    }
+                    nb[4 * c + 3] += (w[0] * d[0] + w[1] * d[1] + w[2] * d[2]) * p;
+                }
+            }
+        }
+    }
+    /* sum the per-thread buffers */
+    double* P = (double*)calloc((size_t)n * 4, sizeof(double));
+    double* Q = (double*)calloc((size_t)nnodes * 4, sizeof(double));
+    #pragma omp parallel for
+    for (int64_t k = 0; k < n * 4; ++k)
+        for (int t = 0; t < nt; ++t) P[k] += pbuf[(size_t)t * (size_t)n * 4 + k];
+    #pragma omp parallel for
+    for (int64_t k = 0; k < nnodes * 4; ++k)
+        for (int t = 0; t < nt; ++t) Q[k] += nbuf[(size_t)t * (size_t)nnodes * 4 + k];
+    free(pbuf); free(nbuf);
+    /* node sources -> member particles, node by node over its range */
+    for (int64_t c = 0; c < nnodes; ++c) {
+        double gX[3] = {Q[4 * c], Q[4 * c + 1], Q[4 * c + 2]}, gM = Q[4 * c + 3];
+        if (gX[0] == 0.0 && gX[1] == 0.0 && gX[2] == 0.0 && gM == 0.0) continue;
+        for (int64_t k = nfirst[c]; k < nfirst[c] + ncount[c]; ++k) {
+            double f = m[k] / NM[c];
+            P[4 * k] += f * gX[0]; P[4 * k + 1] += f * gX[1]; P[4 * k + 2] += f * gX[2];
+            P[4 * k + 3] += gM + ((ux[k] - NX[c]) * gX[0] + (uy[k] - NY[c]) * gX[1] + (uz[k] - NZ[c]) * gX[2]) / NM[c];
+        }
+    }
+    for (int64_t k = 0; k < n; ++k) {
+        gx[k] = G * P[4 * k]; gy[k] = G * P[4 * k + 1]; gz[k] = G * P[4 * k + 2]; gm[k] = G * P[4 * k + 3];
+    }
+    free(P); free(Q);
+}
