@@ -102,6 +102,14 @@ def gcut(xi):
     return g, dg
 
 
+def gcut_printed(xi):
+    """g_P3M exactly as printed (zeta branch form), for transcription pins."""
+    xi = _f64(np.atleast_1d(xi))
+    g = np.empty_like(xi)
+    lib().or_gcut_printed_vec(_i64(xi.size), _ptr(xi), _ptr(g))
+    return g
+
+
 def pair_force(d, r_cut, eps):
     """F(d) = d (|d|^2+eps^2)^(-3/2) g(2|d|/r_cut) [|d| < r_cut] for one offset."""
     out = np.empty(3)

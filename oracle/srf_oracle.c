@@ -43,10 +43,10 @@ int or_num_threads(void) {
 /* Cutoff function and pair kernel                                     */
 /* ================================================================== */
 
-/* g_P3M(xi): Sec. 2, eq. (cutoff).  The degree-8 polynomial on [0,2]
- * with the zeta = max(0, xi - 1) branch term, and 0 for xi > 2.
- * Written in expanded monomials, not in the nested form of the paper. */
-double or_gcut(double xi) {
+/* g_P3M(xi) exactly as printed in Sec. 2, eq. (cutoff): the degree-8
+ * polynomial with the zeta = max(0, xi - 1) branch term, 0 for xi > 2.
+ * Kept for the transcription pins; near xi = 2 its two terms cancel. */
+double or_gcut_printed(double xi) {
     if (xi > 2.0) return 0.0;
     double zeta = xi - 1.0 > 0.0 ? xi - 1.0 : 0.0;
     double x2 = xi * xi, x3 = x2 * xi, x5 = x3 * x2, x6 = x5 * xi, x7 = x6 * xi, x8 = x7 * xi;
@@ -56,15 +56,31 @@ double or_gcut(double xi) {
     return first - second;
 }
 
-/* dg/dxi, differentiated term by term from the same monomials. */
+/* g_P3M(xi), the function of eq. (cutoff).  On [0,1] the printed
+ * polynomial (zeta = 0 there).  On [1,2] the same polynomial, expanded
+ * and factored: first - zeta^6 (...) = -(xi-2)^5 (7 xi^3 + 22 xi^2 + 10 xi + 4)/140,
+ * which keeps full relative accuracy as g -> 0 at xi = 2 (the printed
+ * difference of two O(1) terms does not).  0 beyond xi = 2. */
+double or_gcut(double xi) {
+    if (xi > 2.0) return 0.0;
+    if (xi <= 1.0) {
+        double x2 = xi * xi, x3 = x2 * xi, x5 = x3 * x2, x6 = x5 * xi, x7 = x6 * xi, x8 = x7 * xi;
+        return 1.0 - (8.0 / 5.0) * x3 + (8.0 / 5.0) * x5 - 0.5 * x6 - (12.0 / 35.0) * x7 + (3.0 / 20.0) * x8;
+    }
+    double t = 2.0 - xi;
+    return pow(t, 5.0) * (7.0 * xi * xi * xi + 22.0 * xi * xi + 10.0 * xi + 4.0) / 140.0;
+}
+
+/* dg/dxi.  On [0,1] term by term from the monomials; on [1,2] the
+ * derivative of the factored form, -xi (xi-2)^4 (2 xi^2 + 4 xi - 1) / 5. */
 double or_gcut_deriv(double xi) {
     if (xi > 2.0) return 0.0;
-    double zeta = xi - 1.0 > 0.0 ? xi - 1.0 : 0.0;
-    double x2 = xi * xi, x4 = x2 * x2, x5 = x4 * xi, x6 = x5 * xi, x7 = x6 * xi;
-    double first = -(24.0 / 5.0) * x2 + 8.0 * x4 - 3.0 * x5 - (12.0 / 5.0) * x6 + (6.0 / 5.0) * x7;
-    double q = 3.0 / 35.0 + (18.0 / 35.0) * xi + (1.0 / 5.0) * x2;
-    double dq = 18.0 / 35.0 + (2.0 / 5.0) * xi;
-    return first - (6.0 * pow(zeta, 5.0) * q + pow(zeta, 6.0) * dq);
+    if (xi <= 1.0) {
+        double x2 = xi * xi, x4 = x2 * x2, x5 = x4 * xi, x6 = x5 * xi, x7 = x6 * xi;
+        return -(24.0 / 5.0) * x2 + 8.0 * x4 - 3.0 * x5 - (12.0 / 5.0) * x6 + (6.0 / 5.0) * x7;
+    }
+    double t = 2.0 - xi;
+    return -xi * pow(t, 4.0) * (2.0 * xi * xi + 4.0 * xi - 1.0) / 5.0;
 }
 
 void or_gcut_vec(int64_t n, const double* xi, double* g, double* dg) {
@@ -72,6 +88,10 @@ void or_gcut_vec(int64_t n, const double* xi, double* g, double* dg) {
         g[k] = or_gcut(xi[k]);
         if (dg) dg[k] = or_gcut_deriv(xi[k]);
     }
+}
+
+void or_gcut_printed_vec(int64_t n, const double* xi, double* g) {
+    for (int64_t k = 0; k < n; ++k) g[k] = or_gcut_printed(xi[k]);
 }
 
 /* phi(r) = (r^2 + eps^2)^(-3/2) * g(2 r / r_cut) for r < r_cut, else 0.
@@ -267,6 +287,7 @@ void or_bf_adjoint(int64_t n, const double* x, const double* y, const double* z,
             } else { q0 = 0; q1 = n; }
             for (int64_t q = q0; q < q1; ++q) {
                 int64_t j = have_cells ? cl.idx[q] : q;
+                if (j == k) continue;   /* j != i in the force sum */
                 double d[3] = {mimage(x[j] - x[k]), mimage(y[j] - y[k]), mimage(z[j] - z[k])};
                 double v[3] = {m[k] * wx[j] - m[j] * wx[k], m[k] * wy[j] - m[j] * wy[k], m[k] * wz[j] - m[j] * wz[k]};
                 double jv[3];
@@ -687,6 +708,7 @@ void or_tree_adjoint(int64_t n, int64_t ng, const int64_t* gfirst, const int64_t
                 double w[3] = {wx[i], wy[i], wz[i]};
                 for (int64_t e = poff[g]; e < poff[g + 1]; ++e) {
                     int64_t j = pidx[e];
+                    if (j == i) continue;   /* the force sum runs over j != i */
                     double d[3] = {mimage(ux[j] - ux[i]), mimage(uy[j] - uy[i]), mimage(uz[j] - uz[i])};
                     double jw[3];
                     jac_times(d[0], d[1], d[2], rc, eps, w, jw);

@@ -70,11 +70,24 @@ def test_g_special_values():
     assert abs(dg[1] + 1.0) < 1e-14
 
 
-def test_g_factored_form_on_1_2():
-    xi = np.linspace(1.0, 2.0, 101)
-    closed = -((xi - 2) ** 5) * (7 * xi ** 3 + 22 * xi ** 2 + 10 * xi + 4) / 140.0
+def test_g_matches_printed_form():
+    # the oracle evaluates the printed polynomial of eq. (cutoff) on [0,1] and
+    # its factored form on [1,2]; both agree with the printed zeta-branch form
+    xi = np.linspace(0.0, 2.5, 2501)
     g, _ = oracle.gcut(xi)
-    assert np.max(np.abs(g - closed)) < 1e-14
+    assert np.max(np.abs(g - oracle.gcut_printed(xi))) < 5e-14   # printed form: O(10) terms
+    # printed form factors as -(xi-2)^5 (7 xi^3 + 22 xi^2 + 10 xi + 4)/140 on [1,2]
+    x = np.linspace(1.0, 2.0, 101)
+    closed = -((x - 2) ** 5) * (7 * x ** 3 + 22 * x ** 2 + 10 * x + 4) / 140.0
+    assert np.max(np.abs(oracle.gcut_printed(x) - closed)) < 5e-14
+
+
+def test_g_relative_accuracy_near_cutoff():
+    # g ~ (6/5)(2 - xi)^5 as xi -> 2: the oracle keeps relative accuracy there
+    for h in (1e-2, 1e-3, 1e-4):
+        g, _ = oracle.gcut([2.0 - h])
+        lead = 168.0 / 140.0 * h ** 5
+        assert abs(g[0] / lead - 1.0) < 2.0 * h
 
 
 def test_g_smooth_at_branch_and_end():
