@@ -1,0 +1,220 @@
+"""Throughput of the short-range TreePM step on one MI355X.
+
+One step is the whole hot path on one synthetic particle set: the forward
+(tree build, lists, FP32 group-relative force) and the backward of
+L = sum_i w_i . a_i (tree and lists rebuilt from the same inputs, then the
+hand-written adjoint).  Inputs are resident in HBM before timing starts.
+
+    python bench.py [--steps K] [--warmup W] [--workload 3] [--theta 0.5]
+
+Prints one JSON line (metric, value, roofline of the dominant kernel, CPU
+oracle baseline, per-phase times).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# algorithmic FP32 work per pair interaction (flops, FMA = 2).  Force: the
+# paper's count of 51 per interaction (Sec. 2.1: 17 FMA + 17 other ops per
+# two interactions).  Adjoint: the operations of its pair formula as written
+# (force-like terms + k^2 g'/xi + J w and the j-side dot product), 86.
+FLOPS_FORCE = 51
+FLOPS_ADJOINT = 86
+PEAK_FP32 = 157.3e12     # MI355X FP32 vector peak (packed), FLOP/s
+PEAK_FP64 = 78.6e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", type=int, default=3, help="1..5, see synth.CONFIGS")
+    ap.add_argument("--theta", type=float, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-groups", type=int, default=1500)
+    ap.add_argument("--no-fp64", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(ps, sample_groups: int):
+    """The FP64 oracle on the host cores: tree (a1-a5) over the whole set,
+    then lists and same-list force (a6-a7) for a random sample of groups."""
+    if "OMP_NUM_THREADS" not in os.environ:
+        os.environ["OMP_NUM_THREADS"] = str(len(os.sched_getaffinity(0)))
+    import oracle
+
+    p = ps.params
+    t0 = time.perf_counter()
+    keys, ux, uy, uz = oracle.morton_keys(ps.x, ps.y, ps.z)
+    ks, perm = oracle.sort_keys(keys)
+    ux, uy, uz, m = ux[perm], uy[perm], uz[perm], ps.m[perm]
+    tree = oracle.build_tree(ks, p.n_leaf)
+    M, X = oracle.moments(tree, ux, uy, uz, m)
+    gf, gc = oracle.groups(tree, p.n_group, ps.n)
+    lo, hi = oracle.group_bbox(gf, gc, ux, uy, uz)
+    t_tree = time.perf_counter() - t0
+    rng = np.random.default_rng(0)
+    sel = np.sort(rng.choice(gf.size, min(sample_groups, gf.size), replace=False))
+    t1 = time.perf_counter()
+    L = oracle.make_lists(tree, lo[sel], hi[sel], p.r_cut, p.theta)
+    X0, X1, X2 = (np.ascontiguousarray(X[:, k]) for k in range(3))
+    ax, ay, az = (np.zeros(ps.n) for _ in range(3))
+    gfs, gcs = np.ascontiguousarray(gf[sel]), np.ascontiguousarray(gc[sel])
+    _p = oracle._ptr
+    oracle.lib().or_tree_force(oracle._i64(sel.size), _p(gfs), _p(gcs), _p(L.poff), _p(L.pidx), _p(L.noff),
+                               _p(L.nidx), _p(ux), _p(uy), _p(uz), _p(m), _p(M), _p(X0), _p(X1), _p(X2),
+                               oracle._d(p.G), oracle._d(p.r_cut), oracle._d(p.eps), None, oracle._i64(-1),
+                               _p(ax), _p(ay), _p(az))
+    t_sample = time.perf_counter() - t1
+    nj = np.diff(L.poff) + np.diff(L.noff)
+    i_sample = int(np.sum(gcs * nj))
+    frac = sel.size / gf.size
+    t_eff = t_tree * frac + t_sample
+    return dict(value=i_sample / t_eff, unit="interactions/s", cores=oracle.num_threads(), kind="oracle",
+                sample=(f"forward path of the FP64 oracle: tree over all {ps.n} particles "
+                        f"({t_tree:.2f} s, charged pro rata {frac:.4f}) + lists and same-list force for "
+                        f"{sel.size} random groups ({i_sample} interactions, {t_sample:.2f} s)"),
+                t_tree_s=t_tree, t_sample_s=t_sample)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of "
+              "this path is a design, not a build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1211_4406_amd as srf
+    import synth
+
+    t_gen = time.perf_counter()
+    ps = synth.make_config(args.workload, args.theta)
+    t_gen = time.perf_counter() - t_gen
+    p = srf.Params.of(ps.params)
+    dev = torch.device("cuda")
+    x = torch.tensor(ps.positions(), dtype=torch.float64, device=dev)
+    m = torch.tensor(ps.m, dtype=torch.float64, device=dev)
+    w = torch.tensor(synth.loss_weights(ps.n, 2000 + args.workload), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    srf.set_kernel_timing(True)
+
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    phase_names = ("tree_fwd", "lists_fwd", "force", "tree_bwd", "lists_bwd", "adjoint")
+
+    def step(record):
+        e = [ev() for _ in range(7)]
+        e[0].record()
+        tree = srf.tree_build(x, m, p)
+        e[1].record()
+        lists = srf.make_lists(tree, p)
+        e[2].record()
+        a = srf.short_range_force(tree, lists, p)
+        e[3].record()
+        tree2 = srf.tree_build(x, m, p)
+        e[4].record()
+        lists2 = srf.make_lists(tree2, p)
+        e[5].record()
+        gx, gm = srf.short_range_adjoint(tree2, lists2, p, w)
+        e[6].record()
+        if record is not None:
+            record.append((e, lists.info()))
+        return a, gx, gm
+
+    for _ in range(args.warmup):
+        step(None)
+    torch.cuda.synchronize()
+    recs = []
+    k_force, k_adj = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(recs)
+        k_force.append(srf.last_kernel_ms("force"))
+        k_adj.append(srf.last_kernel_ms("adjoint"))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall / args.steps * 1e3
+    phases = {n: float(np.mean([r[0][i].elapsed_time(r[0][i + 1]) for r in recs])) for i, n in enumerate(phase_names)}
+    info = recs[-1][1]
+    I = info["interactions"]
+    value = I / (ms_step * 1e-3)
+    t_fwd = phases["tree_fwd"] + phases["lists_fwd"] + phases["force"]
+    fwd_rate = I / (t_fwd * 1e-3)
+    kf, ka = float(np.mean(k_force)), float(np.mean(k_adj))
+
+    # all-FP64 kernel on the same lists (comparison)
+    fp64 = None
+    if not args.no_fp64:
+        p64 = srf.Params.of(ps.params, srf.FP64)
+        tree = srf.tree_build(x, m, p64)
+        lists = srf.make_lists(tree, p64)
+        srf.short_range_force(tree, lists, p64)
+        times = []
+        for _ in range(3):
+            srf.short_range_force(tree, lists, p64)
+            times.append(srf.last_kernel_ms("force"))
+        torch.cuda.synchronize()
+        k64 = float(np.median(times))
+        fp64 = dict(force_kernel_ms=k64, interactions_per_s=I / (k64 * 1e-3),
+                    speed_ratio_fp32_over_fp64=k64 / kf)
+        del tree, lists
+
+    dominant = "adjoint" if ka >= kf else "force"
+    kd = ka if dominant == "adjoint" else kf
+    flops = (FLOPS_ADJOINT if dominant == "adjoint" else FLOPS_FORCE) * I
+    achieved = flops / (kd * 1e-3)
+    roofline = dict(bound="alu", kernel=f"k_{dominant}<float>", achieved=achieved / 1e12, peak=PEAK_FP32 / 1e12,
+                    unit="TFLOP/s", frac=achieved / PEAK_FP32, traffic=None,
+                    flops_per_interaction=FLOPS_ADJOINT if dominant == "adjoint" else FLOPS_FORCE,
+                    interactions_per_launch=I, kernel_ms=kd)
+    force_roofline = dict(achieved=FLOPS_FORCE * I / (kf * 1e-3) / 1e12, frac=FLOPS_FORCE * I / (kf * 1e-3) / PEAK_FP32,
+                          kernel_ms=kf, interactions_per_s=I / (kf * 1e-3))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(ps, args.cpu_sample_groups)
+
+    out = {
+        "metric": "short-range pair interactions/s (fwd+adjoint step) + % FP32 VALU peak",
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 pairs, f64 positions/moments/accumulation",
+        "data": "synthetic",
+        "config": {"workload": f"{ps.name}: N={ps.n}, r_cut={ps.params.r_cut:.6g}, eps={ps.params.eps:g}, "
+                               f"theta={ps.params.theta}, n_group={ps.params.n_group}, n_leaf={ps.params.n_leaf}",
+                   "recipe": {k: (list(v) if isinstance(v, tuple) else v) for k, v in ps.recipe.items()}},
+        "interactions": I,
+        "n_groups": info["n_groups"],
+        "mean_Ni": ps.n / info["n_groups"],
+        "mean_Nj": (info["n_particle_entries"] + info["n_node_entries"]) / info["n_groups"],
+        "fwd_interactions_per_s": fwd_rate,
+        "phase_ms": phases,
+        "force_kernel": force_roofline,
+        "adjoint_kernel_ms": ka,
+        "fp64_force": fp64,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "gen_s": t_gen,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,181 @@
+/*
+ * srf.h -- C ABI of the short-range TreePM gravity step on MI355X (gfx950).
+ *
+ * The operation (Ishiyama, Nitadori & Makino, SC12, Sec. 2): given
+ * positions r_i, masses m_i, the gravitational constant G, a cutoff
+ * radius r_cut and a softening length eps in a periodic unit box,
+ *
+ *     a_i = sum_{j != i} G m_j d_ij (|d_ij|^2 + eps^2)^(-3/2) g_P3M(2 |d_ij| / r_cut),
+ *
+ * with d_ij the minimum image of r_j - r_i and g_P3M the cutoff function of
+ * eq. (cutoff) (0 beyond r_cut).  The sum is evaluated with Barnes' modified
+ * tree algorithm (Sec. 2): particles are Morton-sorted into an octree, split
+ * into groups of at most n_group particles, and each group shares one
+ * interaction list of particles and monopole cells, pruned by the cutoff
+ * (Fig. 2) and by the opening angle theta.  The adjoint gives dL/dx and
+ * dL/dm of L = sum_i w_i . a_i with the sort order, cells, groups and lists
+ * held fixed.
+ *
+ * Calls are made in this order: srf_tree_build -> srf_make_lists ->
+ * srf_short_range_force and/or srf_short_range_adjoint.
+ *
+ * Memory and streams.  Unless a comment says "host", every pointer is a
+ * device pointer (HIP device memory of the current device) owned by the
+ * caller.  `stream` is a hipStream_t passed as void* (NULL = the null
+ * stream); all device work of a call is ordered on it.  Handles (srf_tree,
+ * srf_lists) own library memory and are released with srf_*_free; a handle
+ * may be used only with the stream it was built on or after synchronising.
+ * Handles are not thread-safe; distinct handles are.
+ *
+ * Errors.  Every int-returning call returns 0 (SRF_OK) or a negative
+ * srf_status.  No C++ exception crosses this boundary.  srf_last_error()
+ * returns a message for the most recent failure on the calling thread.
+ */
+#ifndef SRF_H
+#define SRF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum srf_status {
+    SRF_OK = 0,
+    SRF_EINVAL = -1,     /* invalid argument or parameter                         */
+    SRF_EDOMAIN = -2,    /* non-finite position, or mass not finite and > 0        */
+    SRF_ENOMEM = -3,     /* device allocation failed                               */
+    SRF_EHIP = -4,       /* a HIP runtime call failed (see srf_last_error)         */
+    SRF_EMISMATCH = -5   /* tree, lists and params do not belong together          */
+};
+
+enum srf_precision {
+    SRF_FP32_REL = 0,    /* FP32 pair arithmetic on group-relative coordinates, FP64
+                            positions, moments and per-particle accumulation         */
+    SRF_FP64 = 1         /* all-FP64 pair arithmetic (comparison kernel)             */
+};
+
+/* Parameters.  Valid ranges (else SRF_EINVAL):
+ *   G finite; 0 < r_cut < 0.25; eps > 0 and finite; 0 <= theta <= 1;
+ *   1 <= n_group <= 64; 1 <= n_leaf <= n_group; precision in srf_precision. */
+typedef struct {
+    double G;            /* gravitational constant                                  */
+    double r_cut;        /* cutoff radius, box units (box side = 1)                 */
+    double eps;          /* Plummer softening length of the short-range kernel      */
+    double theta;        /* opening angle; 0 accepts no cell (pure particle sums)   */
+    int32_t n_group;     /* maximum particles per group                             */
+    int32_t n_leaf;      /* a cell with more particles is split (down to level 21)  */
+    int32_t precision;   /* enum srf_precision (force and adjoint kernels)          */
+    int32_t reserved;    /* must be 0                                               */
+} srf_params;
+
+typedef struct srf_tree srf_tree;
+typedef struct srf_lists srf_lists;
+
+/* Steps a1-a5: wrap positions into [0,1)^3, 63-bit Morton keys (21 bits per
+ * axis, x most significant in each triple), stable sort by key (ties by
+ * input index), octree (a cell with more than n_leaf particles is split, the
+ * root always), monopole moments (mass and centre of mass, FP64), and
+ * particle groups with their tight bounding boxes.
+ *   n:          number of particles, 1 <= n < 2^31 - 1.
+ *   x, y, z:    positions; particle i at x[i*pos_stride] (pos_stride >= 1), so
+ *               an [N,3] row-major array is x = p, y = p+1, z = p+2, stride 3.
+ *               Any finite value is accepted and wrapped periodically.
+ *   m:          masses at m[i*m_stride]; must be finite and > 0.
+ *   out:        (host) receives the new handle.
+ * The inputs are copied; they may be reused once `stream` passes this call.
+ * Synchronises `stream` once per tree level (to size the next level).
+ * Errors: SRF_EINVAL, SRF_EDOMAIN (checked on the device, reported here),
+ * SRF_ENOMEM, SRF_EHIP.  On error *out is NULL. */
+int srf_tree_build(int64_t n, const double* x, const double* y, const double* z, int64_t pos_stride,
+                   const double* m, int64_t m_stride, const srf_params* p, void* stream, srf_tree** out);
+
+/* Step a6: per-group interaction lists.  A cell is pruned if its periodic
+ * box-to-box distance to the group's bounding box is >= r_cut, accepted as
+ * one monopole if side^2 < theta^2 d^2 (d: distance from the group box to
+ * the cell centre), expanded to its particles if it is a leaf, and opened
+ * otherwise (the decisions are made in FP64 without fused multiply-add).
+ * p must carry the n_group and n_leaf the tree was built with.
+ * Synchronises `stream` once (to size the list buffer).
+ * Errors: SRF_EINVAL, SRF_EMISMATCH, SRF_ENOMEM, SRF_EHIP. */
+int srf_make_lists(const srf_tree* t, const srf_params* p, void* stream, srf_lists** out);
+
+/* Steps a7-a8: accelerations in input order, a_i = (ax[i*out_stride], ...).
+ * Each group's particles interact with every list entry (particles of mass
+ * m_j, cells as a particle of mass M_c at their centre of mass) through the
+ * cutoff kernel; precision per p->precision.  p->r_cut, theta, n_group and
+ * n_leaf must match the lists; G, eps and precision are free.
+ * Fully asynchronous on `stream`.  The output may not alias the inputs.
+ * Errors: SRF_EINVAL, SRF_EMISMATCH, SRF_EHIP. */
+int srf_short_range_force(const srf_tree* t, const srf_lists* l, const srf_params* p,
+                          double* ax, double* ay, double* az, int64_t out_stride, void* stream);
+
+/* Step a9: gradient of L = sum_i w_i . a_i with the structure fixed:
+ *   dL/dx_i -> (gx, gy, gz)[i*g_stride],  dL/dm_i -> gm[i*gm_stride],
+ * in input order; w_i = (wx, wy, wz)[i*w_stride].  Node sources pass their
+ * gradient to member particles through M_c = sum m_k, X_c = sum m_k x_k / M_c.
+ * Same parameter rules as srf_short_range_force.  Asynchronous on `stream`;
+ * uses FP64 atomics, so the result is reproducible only to rounding.
+ * Errors: SRF_EINVAL, SRF_EMISMATCH, SRF_ENOMEM, SRF_EHIP. */
+int srf_short_range_adjoint(const srf_tree* t, const srf_lists* l, const srf_params* p,
+                            const double* wx, const double* wy, const double* wz, int64_t w_stride,
+                            double* gx, double* gy, double* gz, int64_t g_stride,
+                            double* gm, int64_t gm_stride, void* stream);
+
+/* Release a handle (NULL is ignored).  Memory returns to the library's
+ * device-memory cache; work still queued on the handle's stream stays valid. */
+void srf_tree_free(srf_tree* t);
+void srf_lists_free(srf_lists* l);
+
+/* Return every cached device block to HIP (synchronises the device). */
+void srf_release_cache(void);
+
+const char* srf_strerror(int status);
+const char* srf_last_error(void);
+
+/* ---------------------------------------------------------------------
+ * Inspection (all output pointers are HOST pointers; any may be NULL to
+ * skip it).  These calls synchronise the handle's stream.
+ * ------------------------------------------------------------------- */
+
+/* Sizes: particles, cells, groups, deepest level. */
+int srf_tree_info(const srf_tree* t, int64_t* n, int64_t* n_nodes, int64_t* n_groups, int32_t* max_level);
+
+/* keys_sorted[n] (Morton keys in sorted order), perm[n] (input index of the
+ * particle at each sorted position); cells in DFS preorder (= order of
+ * (first, level)): node_level, node_prefix (top 3*level key bits),
+ * node_first, node_count [n_nodes]; groups in order of first: group_first,
+ * group_count [n_groups], group_lo, group_hi [n_groups*3] (tight box of the
+ * wrapped positions, x,y,z per group). */
+int srf_tree_export(const srf_tree* t, uint64_t* keys_sorted, int64_t* perm,
+                    int32_t* node_level, uint64_t* node_prefix, int64_t* node_first, int64_t* node_count,
+                    int64_t* group_first, int64_t* group_count, double* group_lo, double* group_hi);
+
+/* Monopoles per cell (preorder): mass and centre of mass. */
+int srf_moments_export(const srf_tree* t, double* M, double* X, double* Y, double* Z);
+
+/* Wrapped positions and masses in sorted order [n]. */
+int srf_sorted_export(const srf_tree* t, double* x, double* y, double* z, double* m);
+
+/* List sizes: groups, particle entries, cell entries, and the interaction
+ * count I = sum over groups of N_i * N_j (the paper's count, Table I). */
+int srf_lists_info(const srf_lists* l, int64_t* n_groups, int64_t* n_particle_entries,
+                   int64_t* n_node_entries, int64_t* interactions);
+
+/* Lists in canonical form: per group g, particle entries
+ * pidx[poff[g]..poff[g+1]) as ascending sorted indices and cell entries
+ * nidx[noff[g]..noff[g+1]) as ascending preorder cell ids.  poff and noff
+ * have n_groups + 1 entries. */
+int srf_lists_export(const srf_lists* l, int64_t* poff, int64_t* pidx, int64_t* noff, int64_t* nidx);
+
+/* Kernel timing (host): average duration in milliseconds of the last
+ * `srf_short_range_force` / `srf_short_range_adjoint` pair-kernel launch,
+ * measured with HIP events on the call's stream when timing is enabled. */
+int srf_set_kernel_timing(int enable);
+int srf_last_kernel_ms(const char* which, double* ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SRF_H */

