@@ -257,37 +257,53 @@ __device__ __forceinline__ PairJ<T> pair_jac(const V4& p, T xi, T yi, T zi, T wx
     return o;
 }
 
+struct AdjOut {
+    double *gix, *giy, *giz;            // i-side, sorted order (plain stores)
+    double *gj;                         // j-side on particles: 4 arrays of n (x, y, z, m), atomics
+    double *gn;                         // j-side on cells: 4 arrays of n_nodes, atomics
+    int64_t n, nn;
+};
+
+// Adjoint pair pass.  Lanes hold targets i (S = 1, 2 or 4 streams of
+// N_i lanes); entries are taken in batches of kB.  Each lane
+//   - accumulates its i-side term -mu V in registers, and
+//   - writes V = J w_i and phi (d . w_i) to an LDS row of its entry;
+// the rows are then summed across lanes (8 lanes per entry, each over a
+// strided subset of the entry's stream, then an xor butterfly over the 8),
+// scaled by the source mass and added to the source's gradient with one
+// FP64 atomic per component.
+constexpr int kB = 8;              // entries per reduction batch
+constexpr int kRowSlots = 64 + 1;  // 4-vectors per entry row (one of padding)
+
 template <class T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+__device__ __forceinline__ T xor8_sum(T v) {
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 4, 64);
     return v;
 }
 
-struct AdjOut {
-    double *gix, *giy, *giz;            // i-side, sorted order (plain stores)
-    double *gjx, *gjy, *gjz, *gjm;      // j-side on particles, sorted order (atomics)
-    double *gnx, *gny, *gnz, *gnm;      // j-side on cells (atomics)
-};
-
-template <class T>
-__global__ __launch_bounds__(64) void k_adjoint(GroupArgs ga, Src src, Coef<T> c, const double* __restrict__ wx,
-                                                const double* __restrict__ wy, const double* __restrict__ wz, int64_t ws,
-                                                AdjOut out) {
+template <class T, int S>
+__device__ __forceinline__ void adjoint_group(const GroupArgs& ga, const Src& src, const Coef<T>& c,
+                                              const double* __restrict__ wx, const double* __restrict__ wy,
+                                              const double* __restrict__ wz, int64_t ws, const AdjOut& out,
+                                              int64_t g, int32_t first, int32_t cnt,
+                                              typename Vec4<T>::type* tile, int32_t* tid_,
+                                              typename Vec4<T>::type* red, double* ired) {
     using V4 = typename Vec4<T>::type;
-    __shared__ V4 tile[kTile];
-    __shared__ int32_t tid_[kTile];
     const int lane = threadIdx.x;
-    const int64_t g = blockIdx.x;
-    const int32_t first = ga.gfirst[g], cnt = ga.gcount[g];
-    const bool active = lane < cnt;
+    const int il = lane % cnt, st = lane / cnt;
+    const bool active = st < S;
     const double cx = (ga.glo[g * 3 + 0] + ga.ghi[g * 3 + 0]) * 0.5;
     const double cy = (ga.glo[g * 3 + 1] + ga.ghi[g * 3 + 1]) * 0.5;
     const double cz = (ga.glo[g * 3 + 2] + ga.ghi[g * 3 + 2]) * 0.5;
-    const int32_t me = first + (active ? lane : 0);
+    const int32_t me = first + il;
     const T xi = (T)(src.px[me] - cx), yi = (T)(src.py[me] - cy), zi = (T)(src.pz[me] - cz);
     const int64_t wi = (int64_t)ga.perm[me] * ws;
-    const T w0 = active ? (T)wx[wi] : T(0), w1 = active ? (T)wy[wi] : T(0), w2 = active ? (T)wz[wi] : T(0);
+    const T w0 = (T)wx[wi], w1 = (T)wy[wi], w2 = (T)wz[wi];
+    // reduction role of this lane: entry re of the batch, part rp of 8
+    const int re = lane >> 3, rp = lane & 7;
+    const int rs = re % S;
     double sx = 0, sy = 0, sz = 0;
     const int64_t e0 = ga.off[g], e1 = ga.off[g + 1];
     for (int64_t tb = e0; tb < e1; tb += kTile) {
@@ -300,51 +316,98 @@ __global__ __launch_bounds__(64) void k_adjoint(GroupArgs ga, Src src, Coef<T> c
         }
         __syncthreads();
         T fx = 0, fy = 0, fz = 0;
-        T kx = 0, ky = 0, kz = 0, km = 0;   // reduced sums of the entry this lane owns
-        for (int k = 0; k < len; ++k) {
-            const V4 p = tile[k];
-            PairJ<T> j = pair_jac<T, V4>(p, xi, yi, zi, w0, w1, w2, c);
-            // idle lanes and the self pair (the sum runs over j != i) add nothing
-            if (!active || tid_[k] == me) j.vx = j.vy = j.vz = j.fw = T(0);
-            fx = fma_(-p.w, j.vx, fx);
-            fy = fma_(-p.w, j.vy, fy);
-            fz = fma_(-p.w, j.vz, fz);
-            const T rx = wave_sum(j.vx), ry = wave_sum(j.vy), rz = wave_sum(j.vz), rm = wave_sum(j.fw);
-            if ((k & 63) == lane) {
-                kx = rx * p.w;
-                ky = ry * p.w;
-                kz = rz * p.w;
-                km = rm;
-            }
-            if ((k & 63) == 63 || k == len - 1) {
-                const int kb = k & ~63;
-                const int mine = kb + lane;
-                if (mine <= k) {
-                    const int32_t v = tid_[mine];
-                    if (v >= 0) {
-                        unsafeAtomicAdd(&out.gjx[v], (double)kx);
-                        unsafeAtomicAdd(&out.gjy[v], (double)ky);
-                        unsafeAtomicAdd(&out.gjz[v], (double)kz);
-                        unsafeAtomicAdd(&out.gjm[v], (double)km);
-                    } else {
-                        const int32_t cc = -v - 1;
-                        unsafeAtomicAdd(&out.gnx[cc], (double)kx);
-                        unsafeAtomicAdd(&out.gny[cc], (double)ky);
-                        unsafeAtomicAdd(&out.gnz[cc], (double)kz);
-                        unsafeAtomicAdd(&out.gnm[cc], (double)km);
+        for (int kb = 0; kb < len; kb += kB) {
+            if (active) {
+#pragma unroll
+                for (int q = 0; q < kB / S; ++q) {
+                    const int e = st + q * S;
+                    const int k = kb + e;
+                    if (k < len) {
+                        const V4 p = tile[k];
+                        PairJ<T> j = pair_jac<T, V4>(p, xi, yi, zi, w0, w1, w2, c);
+                        // the force sum runs over j != i: drop the self pair
+                        if (tid_[k] == me) j.vx = j.vy = j.vz = j.fw = T(0);
+                        fx = fma_(-p.w, j.vx, fx);
+                        fy = fma_(-p.w, j.vy, fy);
+                        fz = fma_(-p.w, j.vz, fz);
+                        V4 o;
+                        o.x = j.vx;
+                        o.y = j.vy;
+                        o.z = j.vz;
+                        o.w = j.fw;
+                        red[e * kRowSlots + lane] = o;
                     }
                 }
             }
+            __syncthreads();
+            {
+                const int k = kb + re;
+                T ax = 0, ay = 0, az = 0, am = 0;
+                if (k < len) {
+                    const V4* row = red + re * kRowSlots + rs * cnt;
+                    for (int q = rp; q < cnt; q += 8) {
+                        const V4 v = row[q];
+                        ax += v.x;
+                        ay += v.y;
+                        az += v.z;
+                        am += v.w;
+                    }
+                }
+                ax = xor8_sum(ax);
+                ay = xor8_sum(ay);
+                az = xor8_sum(az);
+                am = xor8_sum(am);
+                if (k < len && rp < 4) {
+                    const int32_t v = tid_[k];
+                    const T mu = tile[k].w;
+                    const T val = rp == 0 ? ax * mu : (rp == 1 ? ay * mu : (rp == 2 ? az * mu : am));
+                    double* dst = v >= 0 ? out.gj + rp * out.n + v : out.gn + rp * out.nn + (-v - 1);
+                    unsafeAtomicAdd(dst, (double)val);
+                }
+            }
+            __syncthreads();
         }
         sx += (double)fx;
         sy += (double)fy;
         sz += (double)fz;
     }
-    if (active) {
-        out.gix[me] = sx;
-        out.giy[me] = sy;
-        out.giz[me] = sz;
+    // sum the streams of each target
+    ired[lane * 3 + 0] = active ? sx : 0.0;
+    ired[lane * 3 + 1] = active ? sy : 0.0;
+    ired[lane * 3 + 2] = active ? sz : 0.0;
+    __syncthreads();
+    if (lane < cnt) {
+        double tx = 0, ty = 0, tz = 0;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const int l = lane + q * cnt;
+            tx += ired[l * 3 + 0];
+            ty += ired[l * 3 + 1];
+            tz += ired[l * 3 + 2];
+        }
+        out.gix[me] = tx;
+        out.giy[me] = ty;
+        out.giz[me] = tz;
     }
+}
+
+template <class T>
+__global__ __launch_bounds__(64) void k_adjoint(GroupArgs ga, Src src, Coef<T> c, const double* __restrict__ wx,
+                                                const double* __restrict__ wy, const double* __restrict__ wz, int64_t ws,
+                                                AdjOut out) {
+    using V4 = typename Vec4<T>::type;
+    __shared__ V4 tile[kTile];
+    __shared__ int32_t tid_[kTile];
+    __shared__ V4 red[kB * kRowSlots];
+    __shared__ double ired[64 * 3];
+    const int64_t g = blockIdx.x;
+    const int32_t first = ga.gfirst[g], cnt = ga.gcount[g];
+    if (cnt > 32)
+        adjoint_group<T, 1>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, tid_, red, ired);
+    else if (cnt > 16)
+        adjoint_group<T, 2>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, tid_, red, ired);
+    else
+        adjoint_group<T, 4>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, tid_, red, ired);
 }
 
 // Node sources -> member particles.  For a cell c0 and its ancestors c
@@ -393,10 +456,12 @@ __global__ void k_adj_final(int64_t n, double G, const int32_t* __restrict__ per
     const double a0 = sax[lf], a1 = say[lf], a2 = saz[lf], b = sb[lf];
     const double m = pm[s];
     const int64_t i = perm[s];
-    gx[i * gs] = G * (o.gix[s] + o.gjx[s] + m * a0);
-    gy[i * gs] = G * (o.giy[s] + o.gjy[s] + m * a1);
-    gz[i * gs] = G * (o.giz[s] + o.gjz[s] + m * a2);
-    gm[i * gms] = G * (o.gjm[s] + b + ((px[s] - nX[lf]) * a0 + (py[s] - nY[lf]) * a1 + (pz[s] - nZ[lf]) * a2));
+    const double* gj = o.gj;
+    const int64_t n_ = o.n;
+    gx[i * gs] = G * (o.gix[s] + gj[s] + m * a0);
+    gy[i * gs] = G * (o.giy[s] + gj[n_ + s] + m * a1);
+    gz[i * gs] = G * (o.giz[s] + gj[2 * n_ + s] + m * a2);
+    gm[i * gms] = G * (gj[3 * n_ + s] + b + ((px[s] - nX[lf]) * a0 + (py[s] - nY[lf]) * a1 + (pz[s] - nZ[lf]) * a2));
 }
 
 GroupArgs group_args(const Tree& t, const Lists& l) {
@@ -450,20 +515,16 @@ void launch_adjoint(const Tree& t, const Lists& l, const srf_params& p, const do
     o.gix = part.get();
     o.giy = o.gix + n;
     o.giz = o.giy + n;
-    o.gjx = o.giz + n;
-    o.gjy = o.gjx + n;
-    o.gjz = o.gjy + n;
-    o.gjm = o.gjz + n;
-    o.gnx = node.get();
-    o.gny = o.gnx + nn;
-    o.gnz = o.gny + nn;
-    o.gnm = o.gnz + nn;
-    double* sax = o.gnm + nn;
+    o.gj = o.giz + n;
+    o.gn = node.get();
+    o.n = n;
+    o.nn = nn;
+    double* sax = o.gn + 4 * nn;
     double* say = sax + nn;
     double* saz = say + nn;
     double* sb = saz + nn;
-    fill_f64(o.gjx, 0.0, 4 * n, st);
-    fill_f64(o.gnx, 0.0, 4 * nn, st);
+    fill_f64(o.gj, 0.0, 4 * n, st);
+    fill_f64(o.gn, 0.0, 4 * nn, st);
     if (ev0) SRF_HIP(hipEventRecord(ev0, st));
     if (p.precision == SRF_FP64) {
         hipLaunchKernelGGL(k_adjoint<double>, dim3((unsigned)ng), dim3(64), 0, st, group_args(t, l), src_args(t),
@@ -475,7 +536,8 @@ void launch_adjoint(const Tree& t, const Lists& l, const srf_params& p, const do
     SRF_HIP(hipGetLastError());
     if (ev1) SRF_HIP(hipEventRecord(ev1, st));
     hipLaunchKernelGGL(k_node_chain, dim3(grid_for(nn, 256, 1 << 30)), dim3(256), 0, st, nn, t.range.get(), t.nM.get(),
-                       t.nX.get(), t.nY.get(), t.nZ.get(), o.gnx, o.gny, o.gnz, o.gnm, sax, say, saz, sb);
+                       t.nX.get(), t.nY.get(), t.nZ.get(), o.gn, o.gn + nn, o.gn + 2 * nn, o.gn + 3 * nn, sax, say,
+                       saz, sb);
     SRF_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_adj_final, dim3(grid_for(n, 256, 1 << 30)), dim3(256), 0, st, n, p.G, t.perm.get(),
                        t.leaf_of.get(), t.px.get(), t.py.get(), t.pz.get(), t.pm.get(), t.nX.get(), t.nY.get(),
