@@ -74,6 +74,11 @@ struct __align__(16) NodeGeo {
 struct __align__(16) NodeRange {
     int32_t first, count, skip, parent;
 };
+// The same cell packed into one 16-byte record for the list traversal:
+//   x = ix | (skip & 0x7ff) << 21,  y = iy | ((skip >> 11) & 0x7ff) << 21,
+//   z = iz | ((skip >> 22) & 0x3ff) << 21,
+//   w = level | leaf << 5 | min(count, kPackCountMax) << 6.
+constexpr uint32_t kPackCountMax = 0x3ffffffu;
 
 struct Tree {
     int64_t n = 0;
@@ -90,6 +95,7 @@ struct Tree {
     // cells, preorder
     DevBuf<NodeGeo> geo;
     DevBuf<NodeRange> range;
+    DevBuf<uint4> pack;        // packed records (see kPackCountMax)
     DevBuf<uint64_t> prefix;
     DevBuf<double> nM, nX, nY, nZ;   // monopoles
     // groups, in order of first

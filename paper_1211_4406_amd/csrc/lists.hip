@@ -1,12 +1,11 @@
 // Step a6: per-group interaction lists (Barnes' modified traversal with the
 // cutoff pruning of the short-range part).
 //
-// One thread walks the preorder cell array for one group without a stack:
-// a cell that is pruned, accepted or a leaf is left through its skip link,
-// any other cell is opened by stepping to the next preorder index (its first
-// child).  A count pass sizes the lists, a scan places them, and a write
-// pass emits the entries in DFS order (particles ascending, cells in
-// preorder).
+// Threads walk the preorder cell array without a stack: a cell that is
+// pruned, accepted or a leaf is left through its skip link, any other cell
+// is opened by stepping to the next preorder index (its first child).  A
+// count pass sizes the lists, a scan places them, and a write pass emits
+// the entries in DFS order (particles ascending, cells in preorder).
 //
 // Compiled with -ffp-contract=off: the decisions are the literal FP64
 // expressions, evaluated in this order:
@@ -42,55 +41,125 @@ __device__ __forceinline__ double axis_gap(double cen, double cg, double half) {
     return r > 0.0 ? r : 0.0;
 }
 
-// 0: pruned, 1: accepted as a monopole, 2: leaf (expand), 3: open.
-__device__ __forceinline__ int classify(const NodeGeo& g, const Frame& f, double rc2, double th2) {
-    const int lv = (int)(g.level_leaf & 0xffu);
-    const double side = ldexp(1.0, -lv);
-    const double hs = side * 0.5;
-    const double cx = ldexp((double)g.ix + 0.5, -lv);
-    const double cy = ldexp((double)g.iy + 0.5, -lv);
-    const double cz = ldexp((double)g.iz + 0.5, -lv);
-    double ex = axis_gap(cx, f.cg[0], hs + f.hg[0]);
-    double ey = axis_gap(cy, f.cg[1], hs + f.hg[1]);
-    double ez = axis_gap(cz, f.cg[2], hs + f.hg[2]);
-    double D2 = (ex * ex + ey * ey) + ez * ez;
-    if (D2 >= rc2) return 0;
-    ex = axis_gap(cx, f.cg[0], f.hg[0]);
-    ey = axis_gap(cy, f.cg[1], f.hg[1]);
-    ez = axis_gap(cz, f.cg[2], f.hg[2]);
-    double d2 = (ex * ex + ey * ey) + ez * ez;
-    if (side * side < th2 * d2) return 1;
-    if ((g.level_leaf >> 8) & 1u) return 2;
-    return 3;
+// Decoded cell: exact centre and side.
+struct Cell {
+    double c[3], side, hs;
+    int level, leaf;
+    uint32_t count;
+    int64_t skip;
+};
+
+__device__ __forceinline__ Cell decode(const uint4 r) {
+    Cell k;
+    k.level = (int)(r.w & 31u);
+    k.leaf = (int)((r.w >> 5) & 1u);
+    k.count = r.w >> 6;
+    k.skip = (int64_t)((r.x >> 21) | ((r.y >> 21) << 11) | ((r.z >> 21) << 22));
+    k.side = ldexp(1.0, -k.level);
+    k.hs = k.side * 0.5;
+    k.c[0] = ldexp((double)(r.x & 0x1fffffu) + 0.5, -k.level);
+    k.c[1] = ldexp((double)(r.y & 0x1fffffu) + 0.5, -k.level);
+    k.c[2] = ldexp((double)(r.z & 0x1fffffu) + 0.5, -k.level);
+    return k;
 }
 
-__global__ __launch_bounds__(128) void k_lists_count(int64_t ng, const double* __restrict__ glo,
-                                                     const double* __restrict__ ghi, const int32_t* __restrict__ gcount,
-                                                     const NodeGeo* __restrict__ geo, const NodeRange* __restrict__ rng,
-                                                     int64_t nn, double rc2, double th2, int64_t* __restrict__ cnt,
-                                                     unsigned long long* __restrict__ totals) {
-    int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    int64_t np = 0, nc = 0;
-    if (g < ng) {
-        Frame f = group_frame(glo, ghi, g);
-        int64_t i = 0;
-        while (i < nn) {
-            NodeGeo ge = geo[i];
-            NodeRange r = rng[i];
-            int k = classify(ge, f, rc2, th2);
-            if (k == 3) {
-                ++i;
-                continue;
-            }
-            if (k == 1) ++nc;
-            else if (k == 2) np += r.count;
-            i = r.skip;
+// 0: pruned, 1: accepted as a monopole, 2: leaf (expand), 3: open.
+__device__ __forceinline__ int classify(const Cell& k, const Frame& f, double rc2, double th2) {
+    double ex = axis_gap(k.c[0], f.cg[0], k.hs + f.hg[0]);
+    double ey = axis_gap(k.c[1], f.cg[1], k.hs + f.hg[1]);
+    double ez = axis_gap(k.c[2], f.cg[2], k.hs + f.hg[2]);
+    double D2 = (ex * ex + ey * ey) + ez * ez;
+    if (D2 >= rc2) return 0;
+    ex = axis_gap(k.c[0], f.cg[0], f.hg[0]);
+    ey = axis_gap(k.c[1], f.cg[1], f.hg[1]);
+    ez = axis_gap(k.c[2], f.cg[2], f.hg[2]);
+    double d2 = (ex * ex + ey * ey) + ez * ez;
+    if (k.side * k.side < th2 * d2) return 1;
+    return k.leaf ? 2 : 3;
+}
+
+// One thread walks the cell array once for G consecutive groups.  A cell
+// is visited while at least one of them opened its parent; mask[L] (G bits
+// per level, packed in one 64-bit word) holds the groups that opened the
+// visited cell's parent at level L - 1.
+template <int G, bool WRITE>
+__global__ __launch_bounds__(128) void k_lists(int64_t ng, const double* __restrict__ glo,
+                                               const double* __restrict__ ghi, const int32_t* __restrict__ gcount,
+                                               const uint4* __restrict__ pack, const NodeRange* __restrict__ rng,
+                                               int64_t nn, double rc2, double th2, int64_t* __restrict__ cnt,
+                                               unsigned long long* __restrict__ totals, const int64_t* __restrict__ off,
+                                               int32_t* __restrict__ ent) {
+    static_assert(G * kLevels <= 64, "level masks must fit one word");
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t g0 = t * G;
+    Frame f[G];
+    int64_t np[G], nc[G], w[G];
+    int32_t* out[G];
+    uint64_t valid = 0;
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+        np[q] = nc[q] = w[q] = 0;
+        out[q] = nullptr;
+        const int64_t g = g0 + q < ng ? g0 + q : ng - 1;
+        f[q] = group_frame(glo, ghi, g);
+        if (g0 + q < ng) {
+            valid |= 1ull << q;
+            if (WRITE) out[q] = ent + off[g];
         }
-        cnt[g] = np + nc;
     }
-    // block sums of particle entries, cell entries and N_i * N_j
-    unsigned long long a = (unsigned long long)np, b = (unsigned long long)nc;
-    unsigned long long c = g < ng ? (unsigned long long)(gcount[g]) * (unsigned long long)(np + nc) : 0ull;
+    const uint64_t full = (1ull << G) - 1ull;
+    uint64_t masks = valid;  // level 0
+    int64_t i = valid ? 0 : nn;
+    while (i < nn) {
+        const Cell k = decode(pack[i]);
+        const uint64_t act = (masks >> (k.level * G)) & full;
+        uint64_t open = 0;
+        if (act) {
+            int32_t lf = -1;
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+                if (!((act >> q) & 1ull)) continue;
+                const int cls = classify(k, f[q], rc2, th2);
+                if (cls == 3) {
+                    open |= 1ull << q;
+                } else if (cls == 1) {
+                    if (WRITE) out[q][w[q]++] = -(int32_t)i - 1;
+                    else ++nc[q];
+                } else if (cls == 2) {
+                    uint32_t m = k.count;
+                    if (WRITE || m == kPackCountMax) {
+                        if (lf < 0 || m == kPackCountMax) {
+                            const NodeRange r = rng[i];
+                            lf = r.first;
+                            m = (uint32_t)r.count;
+                        }
+                    }
+                    if (WRITE) {
+                        for (uint32_t s = 0; s < m; ++s) out[q][w[q]++] = lf + (int32_t)s;
+                    } else {
+                        np[q] += m;
+                    }
+                }
+            }
+        }
+        if (open) {
+            const int sh = (k.level + 1) * G;
+            masks = (masks & ~(full << sh)) | (open << sh);
+            ++i;
+        } else {
+            i = k.skip;
+        }
+    }
+    if (WRITE) return;
+    unsigned long long a = 0, b = 0, c = 0;
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+        if (!((valid >> q) & 1ull)) continue;
+        cnt[g0 + q] = np[q] + nc[q];
+        a += (unsigned long long)np[q];
+        b += (unsigned long long)nc[q];
+        c += (unsigned long long)gcount[g0 + q] * (unsigned long long)(np[q] + nc[q]);
+    }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
         a += __shfl_xor(a, o, 64);
@@ -104,33 +173,7 @@ __global__ __launch_bounds__(128) void k_lists_count(int64_t ng, const double* _
     }
 }
 
-__global__ __launch_bounds__(128) void k_lists_write(int64_t ng, const double* __restrict__ glo,
-                                                     const double* __restrict__ ghi, const NodeGeo* __restrict__ geo,
-                                                     const NodeRange* __restrict__ rng, int64_t nn, double rc2,
-                                                     double th2, const int64_t* __restrict__ off,
-                                                     int32_t* __restrict__ ent) {
-    int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (g >= ng) return;
-    Frame f = group_frame(glo, ghi, g);
-    int32_t* out = ent + off[g];
-    int64_t w = 0;
-    int64_t i = 0;
-    while (i < nn) {
-        NodeGeo ge = geo[i];
-        NodeRange r = rng[i];
-        int k = classify(ge, f, rc2, th2);
-        if (k == 3) {
-            ++i;
-            continue;
-        }
-        if (k == 1) {
-            out[w++] = -(int32_t)i - 1;
-        } else if (k == 2) {
-            for (int32_t s = r.first; s < r.first + r.count; ++s) out[w++] = s;
-        }
-        i = r.skip;
-    }
-}
+constexpr int kGroupsPerThread = 2;
 
 }  // namespace
 
@@ -143,8 +186,11 @@ void build_lists(const Tree& t, Lists& l, hipStream_t st) {
     DevBuf<unsigned long long> totals(4, st);
     SRF_HIP(hipMemsetAsync(totals.get(), 0, 4 * sizeof(unsigned long long), st));
     const int B = 128;
-    hipLaunchKernelGGL(k_lists_count, dim3(grid_for(ng, B, 1 << 30)), dim3(B), 0, st, ng, t.glo.get(), t.ghi.get(),
-                       t.gcount.get(), t.geo.get(), t.range.get(), t.n_nodes, rc2, th2, l.off.get(), totals.get());
+    constexpr int G = kGroupsPerThread;
+    const int64_t nthreads = (ng + G - 1) / G;
+    hipLaunchKernelGGL((k_lists<G, false>), dim3(grid_for(nthreads, B, 1 << 30)), dim3(B), 0, st, ng, t.glo.get(),
+                       t.ghi.get(), t.gcount.get(), t.pack.get(), t.range.get(), t.n_nodes, rc2, th2, l.off.get(),
+                       totals.get(), (const int64_t*)nullptr, (int32_t*)nullptr);
     SRF_HIP(hipGetLastError());
     exclusive_scan_i64(l.off.get(), ng, true, st);
     unsigned long long h[3];
@@ -155,8 +201,9 @@ void build_lists(const Tree& t, Lists& l, hipStream_t st) {
     l.n_entries = (int64_t)(h[0] + h[1]);
     l.interactions = (int64_t)h[2];
     l.ent.alloc(l.n_entries > 0 ? l.n_entries : 1, st);
-    hipLaunchKernelGGL(k_lists_write, dim3(grid_for(ng, B, 1 << 30)), dim3(B), 0, st, ng, t.glo.get(), t.ghi.get(),
-                       t.geo.get(), t.range.get(), t.n_nodes, rc2, th2, l.off.get(), l.ent.get());
+    hipLaunchKernelGGL((k_lists<G, true>), dim3(grid_for(nthreads, B, 1 << 30)), dim3(B), 0, st, ng, t.glo.get(),
+                       t.ghi.get(), t.gcount.get(), t.pack.get(), t.range.get(), t.n_nodes, rc2, th2,
+                       (int64_t*)nullptr, (unsigned long long*)nullptr, (const int64_t*)l.off.get(), l.ent.get());
     SRF_HIP(hipGetLastError());
 }
 

@@ -76,6 +76,30 @@ __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
 __device__ __forceinline__ float sat_(float x) { return fminf(fmaxf(x, 0.0f), 1.0f); }
 __device__ __forceinline__ double sat_(double x) { return fmin(fmax(x, 0.0), 1.0); }
 
+// Keep a loop-invariant value in a vector register: the empty asm makes it
+// opaque, so the compiler neither folds it back to a scalar operand nor
+// re-materialises it inside the pair loops (a VALU op may read at most one
+// scalar operand, so scalar constants would otherwise cost moves per pair).
+__device__ __forceinline__ float pin_(float x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+__device__ __forceinline__ double pin_(double x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+template <class T>
+__device__ __forceinline__ Coef<T> pinned(const Coef<T>& a) {
+    Coef<T> c;
+    c.A3 = pin_(a.A3); c.A5 = pin_(a.A5); c.A6 = pin_(a.A6); c.A7 = pin_(a.A7); c.A8 = pin_(a.A8);
+    c.R0 = pin_(a.R0); c.R1 = pin_(a.R1); c.R2 = pin_(a.R2); c.R3 = pin_(a.R3);
+    c.C1 = pin_(a.C1); c.C3 = pin_(a.C3); c.C4 = pin_(a.C4); c.C5 = pin_(a.C5); c.C6 = pin_(a.C6);
+    c.E0 = pin_(a.E0); c.E1 = pin_(a.E1); c.E2 = pin_(a.E2);
+    c.k = pin_(a.k); c.eps2 = pin_(a.eps2); c.rh2 = pin_(a.rh2);
+    return c;
+}
+
 template <class T>
 struct Vec4 {};
 template <>
@@ -157,16 +181,14 @@ struct GroupArgs {
 };
 
 // ------------------------------------------------------------------ force
-template <class T>
-__global__ __launch_bounds__(64) void k_force(GroupArgs ga, Src src, Coef<T> c, double G, double* __restrict__ ax,
-                                              double* __restrict__ ay, double* __restrict__ az, int64_t os) {
+template <class T, int S>
+__device__ __forceinline__ void force_group(const GroupArgs& ga, const Src& src, const Coef<T>& c0, double G,
+                                            double* __restrict__ ax, double* __restrict__ ay,
+                                            double* __restrict__ az, int64_t os, int64_t g, int32_t first,
+                                            int32_t cnt, typename Vec4<T>::type* tile, double* red) {
     using V4 = typename Vec4<T>::type;
-    __shared__ V4 tile[kTile];
-    __shared__ double red[64 * 3];
+    const Coef<T> c = pinned(c0);
     const int lane = threadIdx.x;
-    const int64_t g = blockIdx.x;
-    const int32_t first = ga.gfirst[g], cnt = ga.gcount[g];
-    const int S = 64 / cnt;
     const int il = lane % cnt, st = lane / cnt;
     const bool active = st < S;
     const double cx = (ga.glo[g * 3 + 0] + ga.ghi[g * 3 + 0]) * 0.5;
@@ -183,15 +205,16 @@ __global__ __launch_bounds__(64) void k_force(GroupArgs ga, Src src, Coef<T> c, 
         __syncthreads();
         T fx = 0, fy = 0, fz = 0;
         if (active) {
+            const V4* tp = tile + st;
             int k = st;
-            for (; k + 3 * S < len; k += 4 * S) {
-                const V4 p0 = tile[k], p1 = tile[k + S], p2 = tile[k + 2 * S], p3 = tile[k + 3 * S];
+            for (; k + 3 * S < len; k += 4 * S, tp += 4 * S) {
+                const V4 p0 = tp[0], p1 = tp[S], p2 = tp[2 * S], p3 = tp[3 * S];
                 pair_force<T, V4>(p0, xi, yi, zi, c, fx, fy, fz);
                 pair_force<T, V4>(p1, xi, yi, zi, c, fx, fy, fz);
                 pair_force<T, V4>(p2, xi, yi, zi, c, fx, fy, fz);
                 pair_force<T, V4>(p3, xi, yi, zi, c, fx, fy, fz);
             }
-            for (; k < len; k += S) pair_force<T, V4>(tile[k], xi, yi, zi, c, fx, fy, fz);
+            for (; k < len; k += S, tp += S) pair_force<T, V4>(tp[0], xi, yi, zi, c, fx, fy, fz);
         }
         sx += (double)fx;
         sy += (double)fy;
@@ -203,6 +226,7 @@ __global__ __launch_bounds__(64) void k_force(GroupArgs ga, Src src, Coef<T> c, 
     __syncthreads();
     if (lane < cnt) {
         double tx = 0, ty = 0, tz = 0;
+#pragma unroll
         for (int q = 0; q < S; ++q) {
             const int l = lane + q * cnt;
             tx += red[l * 3 + 0];
@@ -216,6 +240,22 @@ __global__ __launch_bounds__(64) void k_force(GroupArgs ga, Src src, Coef<T> c, 
     }
 }
 
+// Streams per group: the largest of 1, 2, 3, 4, 8 with S * N_i <= 64.
+template <class T>
+__global__ __launch_bounds__(64) void k_force(GroupArgs ga, Src src, Coef<T> c, double G, double* __restrict__ ax,
+                                              double* __restrict__ ay, double* __restrict__ az, int64_t os) {
+    using V4 = typename Vec4<T>::type;
+    __shared__ V4 tile[kTile];
+    __shared__ double red[64 * 3];
+    const int64_t g = blockIdx.x;
+    const int32_t first = ga.gfirst[g], cnt = ga.gcount[g];
+    if (cnt > 32) force_group<T, 1>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
+    else if (cnt > 21) force_group<T, 2>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
+    else if (cnt > 16) force_group<T, 3>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
+    else if (cnt > 8) force_group<T, 4>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
+    else force_group<T, 8>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
+}
+
 // ---------------------------------------------------------------- adjoint
 // For a pair (target i with weight w, source of mass mu at offset d):
 //   V = J(d) w = phi w + psi (d . w) d,  psi = phi'(r) / r,
@@ -226,11 +266,15 @@ struct PairJ {
     T vx, vy, vz, fw;
 };
 
+// `self` marks the pair of a particle with itself, which the force sum
+// (over j != i) leaves out: its inverse distance is set to 0, so phi and
+// psi vanish.
 template <class T, class V4>
-__device__ __forceinline__ PairJ<T> pair_jac(const V4& p, T xi, T yi, T zi, T wx, T wy, T wz, const Coef<T>& c) {
+__device__ __forceinline__ PairJ<T> pair_jac(const V4& p, T xi, T yi, T zi, T wx, T wy, T wz, const Coef<T>& c,
+                                             bool self) {
     const T dx = p.x - xi, dy = p.y - yi, dz = p.z - zi;
     const T r2 = fma_(dz, dz, fma_(dy, dy, dx * dx));
-    const T rinv = rsqrt_(r2 + c.eps2);
+    const T rinv = self ? T(0) : rsqrt_(r2 + c.eps2);
     const T r = sqrt_(r2);
     T t;
     const T g = cutoff_g(r, r2, c, t);
@@ -264,7 +308,7 @@ struct AdjOut {
     int64_t n, nn;
 };
 
-// Adjoint pair pass.  Lanes hold targets i (S = 1, 2 or 4 streams of
+// Adjoint pair pass.  Lanes hold targets i (S = 1, 2, 4 or 8 streams of
 // N_i lanes); entries are taken in batches of kB.  Each lane
 //   - accumulates its i-side term -mu V in registers, and
 //   - writes V = J w_i and phi (d . w_i) to an LDS row of its entry;
@@ -284,13 +328,14 @@ __device__ __forceinline__ T xor8_sum(T v) {
 }
 
 template <class T, int S>
-__device__ __forceinline__ void adjoint_group(const GroupArgs& ga, const Src& src, const Coef<T>& c,
+__device__ __forceinline__ void adjoint_group(const GroupArgs& ga, const Src& src, const Coef<T>& c0,
                                               const double* __restrict__ wx, const double* __restrict__ wy,
                                               const double* __restrict__ wz, int64_t ws, const AdjOut& out,
                                               int64_t g, int32_t first, int32_t cnt,
                                               typename Vec4<T>::type* tile, int32_t* tid_,
-                                              typename Vec4<T>::type* red, double* ired) {
+                                              typename Vec4<T>::type* red, double* ired, int32_t* selfpos) {
     using V4 = typename Vec4<T>::type;
+    const Coef<T> c = pinned(c0);
     const int lane = threadIdx.x;
     const int il = lane % cnt, st = lane / cnt;
     const bool active = st < S;
@@ -309,12 +354,16 @@ __device__ __forceinline__ void adjoint_group(const GroupArgs& ga, const Src& sr
     for (int64_t tb = e0; tb < e1; tb += kTile) {
         const int len = (int)((e1 - tb) < kTile ? (e1 - tb) : kTile);
         __syncthreads();
+        selfpos[lane] = -1;
+        __syncthreads();
         for (int k = lane; k < len; k += 64) {
             const int32_t v = ga.ent[tb + k];
             tile[k] = load_entry<T, V4>(v, src, cx, cy, cz);
             tid_[k] = v;
+            if (v >= first && v < first + cnt) selfpos[v - first] = k;
         }
         __syncthreads();
+        const int sp = selfpos[il];   // tile slot of this lane's own particle, or -1
         T fx = 0, fy = 0, fz = 0;
         for (int kb = 0; kb < len; kb += kB) {
             if (active) {
@@ -324,9 +373,7 @@ __device__ __forceinline__ void adjoint_group(const GroupArgs& ga, const Src& sr
                     const int k = kb + e;
                     if (k < len) {
                         const V4 p = tile[k];
-                        PairJ<T> j = pair_jac<T, V4>(p, xi, yi, zi, w0, w1, w2, c);
-                        // the force sum runs over j != i: drop the self pair
-                        if (tid_[k] == me) j.vx = j.vy = j.vz = j.fw = T(0);
+                        const PairJ<T> j = pair_jac<T, V4>(p, xi, yi, zi, w0, w1, w2, c, k == sp);
                         fx = fma_(-p.w, j.vx, fx);
                         fy = fma_(-p.w, j.vy, fy);
                         fz = fma_(-p.w, j.vz, fz);
@@ -400,14 +447,17 @@ __global__ __launch_bounds__(64) void k_adjoint(GroupArgs ga, Src src, Coef<T> c
     __shared__ int32_t tid_[kTile];
     __shared__ V4 red[kB * kRowSlots];
     __shared__ double ired[64 * 3];
+    __shared__ int32_t selfpos[64];
     const int64_t g = blockIdx.x;
     const int32_t first = ga.gfirst[g], cnt = ga.gcount[g];
     if (cnt > 32)
-        adjoint_group<T, 1>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, tid_, red, ired);
+        adjoint_group<T, 1>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, tid_, red, ired, selfpos);
     else if (cnt > 16)
-        adjoint_group<T, 2>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, tid_, red, ired);
+        adjoint_group<T, 2>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, tid_, red, ired, selfpos);
+    else if (cnt > 8)
+        adjoint_group<T, 4>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, tid_, red, ired, selfpos);
     else
-        adjoint_group<T, 4>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, tid_, red, ired);
+        adjoint_group<T, 8>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, tid_, red, ired, selfpos);
 }
 
 // Node sources -> member particles.  For a cell c0 and its ancestors c

@@ -202,6 +202,7 @@ __global__ void k_pre_scatter(int64_t nn, int64_t n, const int32_t* __restrict__
                               const int32_t* __restrict__ start, const double* __restrict__ M,
                               const double* __restrict__ SX, const double* __restrict__ SY,
                               const double* __restrict__ SZ, NodeGeo* __restrict__ geo, NodeRange* __restrict__ rng,
+                              uint4* __restrict__ pack,
                               uint64_t* __restrict__ opre, double* __restrict__ oM, double* __restrict__ oX,
                               double* __restrict__ oY, double* __restrict__ oZ, int32_t* __restrict__ leaf_of) {
     int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -223,6 +224,13 @@ __global__ void k_pre_scatter(int64_t nn, int64_t n, const int32_t* __restrict__
     r.skip = start[f + cnt];
     r.parent = parent[c] >= 0 ? bfs2pre[parent[c]] : -1;
     rng[p] = r;
+    const uint32_t sk = (uint32_t)r.skip;
+    uint4 pk;
+    pk.x = g.ix | ((sk & 0x7ffu) << 21);
+    pk.y = g.iy | (((sk >> 11) & 0x7ffu) << 21);
+    pk.z = g.iz | (((sk >> 22) & 0x3ffu) << 21);
+    pk.w = (uint32_t)lv | (leaf ? 0x20u : 0u) | ((uint32_t)(cnt < (int32_t)kPackCountMax ? cnt : (int32_t)kPackCountMax) << 6);
+    pack[p] = pk;
     opre[p] = pf;
     double mm = M[c];
     oM[p] = mm;
@@ -400,6 +408,7 @@ void build_cells_and_groups(Tree& t, int32_t* d_flag, hipStream_t st) {
     SRF_HIP(hipGetLastError());
     t.geo.alloc(nn, st);
     t.range.alloc(nn, st);
+    t.pack.alloc(nn, st);
     t.prefix.alloc(nn, st);
     t.nM.alloc(nn, st);
     t.nX.alloc(nn, st);
@@ -408,7 +417,8 @@ void build_cells_and_groups(Tree& t, int32_t* d_flag, hipStream_t st) {
     t.leaf_of.alloc(n, st);
     hipLaunchKernelGGL(k_pre_scatter, dim3(grid_for(nn, B, 1 << 30)), dim3(B), 0, st, nn, n, bfs2pre.get(),
                        b.level.get(), b.first.get(), b.count.get(), b.parent.get(), b.child_cnt.get(), b.prefix.get(),
-                       cntf.get(), M.get(), SX.get(), SY.get(), SZ.get(), t.geo.get(), t.range.get(), t.prefix.get(),
+                       cntf.get(), M.get(), SX.get(), SY.get(), SZ.get(), t.geo.get(), t.range.get(), t.pack.get(),
+                       t.prefix.get(),
                        t.nM.get(), t.nX.get(), t.nY.get(), t.nZ.get(), t.leaf_of.get());
     SRF_HIP(hipGetLastError());
 
