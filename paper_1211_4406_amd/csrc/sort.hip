@@ -66,16 +66,22 @@ __global__ __launch_bounds__(kThreads) void k_hist(int64_t n, const uint64_t* __
     counts[(int64_t)threadIdx.x * tiles + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter: the keys of a tile are taken in rounds of 256 (position
+// Stable scatter.  The keys of a tile are taken in rounds of 256 (position
 // round*256 + tid); a key's rank among equal digits is the count of that
 // digit in earlier rounds plus the count among lower threads this round.
+// The tile is then reordered by digit in LDS, so that the global writes of
+// each digit's run are contiguous.
 __global__ __launch_bounds__(kThreads) void k_scatter(int64_t n, const uint64_t* __restrict__ kin,
                                                       const int32_t* __restrict__ vin, uint64_t* __restrict__ kout,
                                                       int32_t* __restrict__ vout, int shift, int64_t tiles,
                                                       const int32_t* __restrict__ offsets) {
     __shared__ int32_t base[kDigits];
     __shared__ int32_t run[kDigits];
+    __shared__ int32_t toff[kDigits];
     __shared__ int32_t wc[kThreads / 64][kDigits];
+    __shared__ uint64_t skey[kTile];
+    __shared__ int32_t sval[kTile];
+    __shared__ int32_t wsum[kThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     base[tid] = offsets[(int64_t)tid * tiles + blockIdx.x];
     run[tid] = 0;
@@ -84,31 +90,34 @@ __global__ __launch_bounds__(kThreads) void k_scatter(int64_t n, const uint64_t*
     __syncthreads();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int64_t tbase = blockIdx.x * (int64_t)kTile;
+    uint64_t key[kItems];
+    int32_t val[kItems], dig[kItems], rank[kItems];
+#pragma unroll
     for (int r = 0; r < kItems; ++r) {
-        int64_t i = tbase + r * kThreads + tid;
-        bool valid = i < n;
-        uint64_t key = valid ? kin[i] : 0;
-        int32_t val = valid ? vin[i] : 0;
-        int d = valid ? (int)((key >> shift) & 0xff) : -1;
+        const int64_t i = tbase + r * kThreads + tid;
+        const bool valid = i < n;
+        key[r] = valid ? kin[i] : 0;
+        val[r] = valid ? vin[i] : 0;
+        const int d = valid ? (int)((key[r] >> shift) & 0xff) : -1;
+        dig[r] = d;
         // lanes holding the same digit (invalid lanes match nobody valid)
         uint64_t peers = __ballot(valid);
         if (!valid) peers = ~peers;
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            uint64_t bal = __ballot(valid && ((d >> b) & 1));
-            peers &= (valid && ((d >> b) & 1)) ? bal : ~bal;
+            const bool bit = valid && ((d >> b) & 1);
+            const uint64_t bal = __ballot(bit);
+            peers &= bit ? bal : ~bal;
         }
-        int lower = __popcll(peers & lt);
-        int wcount = __popcll(peers);
-        bool leader = valid && lower == 0;
-        if (leader) wc[wid][d] = wcount;
+        const int lower = __popcll(peers & lt);
+        if (valid && lower == 0) wc[wid][d] = __popcll(peers);
         __syncthreads();
         if (valid) {
-            int rank = run[d] + lower;
-            for (int w = 0; w < wid; ++w) rank += wc[w][d];
-            int64_t dst = (int64_t)base[d] + rank;
-            kout[dst] = key;
-            vout[dst] = val;
+            int rk = run[d] + lower;
+            for (int w = 0; w < wid; ++w) rk += wc[w][d];
+            rank[r] = rk;
+        } else {
+            rank[r] = 0;
         }
         __syncthreads();
         int tot = 0;
@@ -119,6 +128,42 @@ __global__ __launch_bounds__(kThreads) void k_scatter(int64_t n, const uint64_t*
         }
         run[tid] += tot;
         __syncthreads();
+    }
+    // exclusive scan of the tile's digit counts (one digit per thread)
+    {
+        const int v = run[tid];
+        int incl = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += u;
+        }
+        if (lane == 63) wsum[wid] = incl;
+        __syncthreads();
+        int off = incl - v;
+        for (int w = 0; w < wid; ++w) off += wsum[w];
+        toff[tid] = off;
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        if (dig[r] < 0) continue;
+        const int p = toff[dig[r]] + rank[r];
+        skey[p] = key[r];
+        sval[p] = val[r];
+    }
+    __syncthreads();
+    const int cnt = (int)((n - tbase) < kTile ? (n - tbase) : kTile);
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const int p = r * kThreads + tid;
+        if (p < cnt) {
+            const uint64_t k = skey[p];
+            const int d = (int)((k >> shift) & 0xff);
+            const int64_t dst = (int64_t)base[d] + (p - toff[d]);
+            kout[dst] = k;
+            vout[dst] = sval[p];
+        }
     }
 }
 
