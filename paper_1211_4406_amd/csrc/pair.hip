@@ -172,6 +172,15 @@ __device__ __forceinline__ V4 load_entry(int32_t v, const Src& s, double cx, dou
     return o;
 }
 
+// Workgroups are handed to the 8 XCDs (each with its own L2) round-robin
+// in launch order.  Give each XCD one contiguous run of groups instead, so
+// that the groups sharing an L2 are spatial neighbours whose lists overlap.
+__device__ __forceinline__ int64_t xcd_group(int64_t b, int64_t nb) {
+    const int64_t x = b & 7, y = b >> 3;
+    const int64_t q = nb >> 3, r = nb & 7;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + y;
+}
+
 struct GroupArgs {
     const int32_t *gfirst, *gcount;
     const double *glo, *ghi;
@@ -247,7 +256,7 @@ __global__ __launch_bounds__(64) void k_force(GroupArgs ga, Src src, Coef<T> c, 
     using V4 = typename Vec4<T>::type;
     __shared__ V4 tile[kTile];
     __shared__ double red[64 * 3];
-    const int64_t g = blockIdx.x;
+    const int64_t g = xcd_group(blockIdx.x, gridDim.x);
     const int32_t first = ga.gfirst[g], cnt = ga.gcount[g];
     if (cnt > 32) force_group<T, 1>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
     else if (cnt > 21) force_group<T, 2>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
@@ -303,8 +312,8 @@ __device__ __forceinline__ PairJ<T> pair_jac(const V4& p, T xi, T yi, T zi, T wx
 
 struct AdjOut {
     double *gix, *giy, *giz;            // i-side, sorted order (plain stores)
-    double *gj;                         // j-side on particles: 4 arrays of n (x, y, z, m), atomics
-    double *gn;                         // j-side on cells: 4 arrays of n_nodes, atomics
+    double *gj;                         // j-side on particles: [n][4] = (x, y, z, m), atomics
+    double *gn;                         // j-side on cells: [n_nodes][4], atomics
     int64_t n, nn;
 };
 
@@ -408,7 +417,8 @@ __device__ __forceinline__ void adjoint_group(const GroupArgs& ga, const Src& sr
                     const int32_t v = tid_[k];
                     const T mu = tile[k].w;
                     const T val = rp == 0 ? ax * mu : (rp == 1 ? ay * mu : (rp == 2 ? az * mu : am));
-                    double* dst = v >= 0 ? out.gj + rp * out.n + v : out.gn + rp * out.nn + (-v - 1);
+                    // the four components of one source are adjacent (one 32-byte line)
+                    double* dst = v >= 0 ? out.gj + 4 * (int64_t)v + rp : out.gn + 4 * (int64_t)(-v - 1) + rp;
                     unsafeAtomicAdd(dst, (double)val);
                 }
             }
@@ -448,7 +458,7 @@ __global__ __launch_bounds__(64) void k_adjoint(GroupArgs ga, Src src, Coef<T> c
     __shared__ V4 red[kB * kRowSlots];
     __shared__ double ired[64 * 3];
     __shared__ int32_t selfpos[64];
-    const int64_t g = blockIdx.x;
+    const int64_t g = xcd_group(blockIdx.x, gridDim.x);
     const int32_t first = ga.gfirst[g], cnt = ga.gcount[g];
     if (cnt > 32)
         adjoint_group<T, 1>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, tid_, red, ired, selfpos);
@@ -469,9 +479,8 @@ __global__ __launch_bounds__(64) void k_adjoint(GroupArgs ga, Src src, Coef<T> c
 // positions formed before it is multiplied (no cancellation of large terms).
 __global__ void k_node_chain(int64_t nn, const NodeRange* __restrict__ rng, const double* __restrict__ M,
                              const double* __restrict__ X, const double* __restrict__ Y, const double* __restrict__ Z,
-                             const double* __restrict__ gnx, const double* __restrict__ gny,
-                             const double* __restrict__ gnz, const double* __restrict__ gnm, double* __restrict__ sax,
-                             double* __restrict__ say, double* __restrict__ saz, double* __restrict__ sb) {
+                             const double4* __restrict__ gn, double* __restrict__ sax, double* __restrict__ say,
+                             double* __restrict__ saz, double* __restrict__ sb) {
     int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (c >= nn) return;
     const double x0 = X[c], y0 = Y[c], z0 = Z[c];
@@ -479,11 +488,12 @@ __global__ void k_node_chain(int64_t nn, const NodeRange* __restrict__ rng, cons
     int32_t p = (int32_t)c;
     while (p >= 0) {
         const double inv = 1.0 / M[p];
-        const double a0 = gnx[p] * inv, a1 = gny[p] * inv, a2 = gnz[p] * inv;
+        const double4 q = gn[p];
+        const double a0 = q.x * inv, a1 = q.y * inv, a2 = q.z * inv;
         ax += a0;
         ay += a1;
         az += a2;
-        b += gnm[p] + ((x0 - X[p]) * a0 + (y0 - Y[p]) * a1 + (z0 - Z[p]) * a2);
+        b += q.w + ((x0 - X[p]) * a0 + (y0 - Y[p]) * a1 + (z0 - Z[p]) * a2);
         p = rng[p].parent;
     }
     sax[c] = ax;
@@ -506,12 +516,11 @@ __global__ void k_adj_final(int64_t n, double G, const int32_t* __restrict__ per
     const double a0 = sax[lf], a1 = say[lf], a2 = saz[lf], b = sb[lf];
     const double m = pm[s];
     const int64_t i = perm[s];
-    const double* gj = o.gj;
-    const int64_t n_ = o.n;
-    gx[i * gs] = G * (o.gix[s] + gj[s] + m * a0);
-    gy[i * gs] = G * (o.giy[s] + gj[n_ + s] + m * a1);
-    gz[i * gs] = G * (o.giz[s] + gj[2 * n_ + s] + m * a2);
-    gm[i * gms] = G * (gj[3 * n_ + s] + b + ((px[s] - nX[lf]) * a0 + (py[s] - nY[lf]) * a1 + (pz[s] - nZ[lf]) * a2));
+    const double4 gj = reinterpret_cast<const double4*>(o.gj)[s];
+    gx[i * gs] = G * (o.gix[s] + gj.x + m * a0);
+    gy[i * gs] = G * (o.giy[s] + gj.y + m * a1);
+    gz[i * gs] = G * (o.giz[s] + gj.z + m * a2);
+    gm[i * gms] = G * (gj.w + b + ((px[s] - nX[lf]) * a0 + (py[s] - nY[lf]) * a1 + (pz[s] - nZ[lf]) * a2));
 }
 
 GroupArgs group_args(const Tree& t, const Lists& l) {
@@ -562,10 +571,10 @@ void launch_adjoint(const Tree& t, const Lists& l, const srf_params& p, const do
     const int64_t n = t.n, nn = t.n_nodes, ng = t.n_groups;
     DevBuf<double> part(7 * n, st), node(8 * nn, st);
     AdjOut o;
-    o.gix = part.get();
+    o.gj = part.get();          // [n][4], 32-byte aligned at the block start
+    o.gix = o.gj + 4 * n;
     o.giy = o.gix + n;
     o.giz = o.giy + n;
-    o.gj = o.giz + n;
     o.gn = node.get();
     o.n = n;
     o.nn = nn;
@@ -586,8 +595,7 @@ void launch_adjoint(const Tree& t, const Lists& l, const srf_params& p, const do
     SRF_HIP(hipGetLastError());
     if (ev1) SRF_HIP(hipEventRecord(ev1, st));
     hipLaunchKernelGGL(k_node_chain, dim3(grid_for(nn, 256, 1 << 30)), dim3(256), 0, st, nn, t.range.get(), t.nM.get(),
-                       t.nX.get(), t.nY.get(), t.nZ.get(), o.gn, o.gn + nn, o.gn + 2 * nn, o.gn + 3 * nn, sax, say,
-                       saz, sb);
+                       t.nX.get(), t.nY.get(), t.nZ.get(), reinterpret_cast<const double4*>(o.gn), sax, say, saz, sb);
     SRF_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_adj_final, dim3(grid_for(n, 256, 1 << 30)), dim3(256), 0, st, n, p.G, t.perm.get(),
                        t.leaf_of.get(), t.px.get(), t.py.get(), t.pz.get(), t.pm.get(), t.nX.get(), t.nY.get(),
