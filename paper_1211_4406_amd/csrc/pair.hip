@@ -317,22 +317,38 @@ struct AdjOut {
     int64_t n, nn;
 };
 
-// Adjoint pair pass.  Lanes hold targets i (S = 1, 2, 4 or 8 streams of
+// Adjoint pair pass.  Lanes hold targets i (S = 1, 2 or 4 streams of
 // N_i lanes); entries are taken in batches of kB.  Each lane
 //   - accumulates its i-side term -mu V in registers, and
 //   - writes V = J w_i and phi (d . w_i) to an LDS row of its entry;
-// the rows are then summed across lanes (8 lanes per entry, each over a
-// strided subset of the entry's stream, then an xor butterfly over the 8),
+// the rows are then summed across lanes (16 lanes per entry, each over a
+// strided subset of the entry's stream, then a DPP reduction over the 16),
 // scaled by the source mass and added to the source's gradient with one
 // FP64 atomic per component.
-constexpr int kB = 8;              // entries per reduction batch
+constexpr int kB = 4;              // entries per reduction batch
 constexpr int kRowSlots = 64 + 1;  // 4-vectors per entry row (one of padding)
 
-template <class T>
-__device__ __forceinline__ T xor8_sum(T v) {
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
-    v += __shfl_xor(v, 4, 64);
+// Sum over the 16 lanes of a row (lanes 16r..16r+15) with DPP moves, which
+// stay in the vector ALU: xor 1 and xor 2 within quads, then the
+// half-row and row mirrors pair up the quads and the half-rows.
+__device__ __forceinline__ float dpp_f(float v, int ctrl) {
+    switch (ctrl) {
+        case 0: return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xf, 0xf, false));
+        case 1: return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4E, 0xf, 0xf, false));
+        case 2: return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x141, 0xf, 0xf, false));
+        default: return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x140, 0xf, 0xf, false));
+    }
+}
+__device__ __forceinline__ float row16_sum(float v) {
+    v += dpp_f(v, 0);   // quad_perm [1,0,3,2]
+    v += dpp_f(v, 1);   // quad_perm [2,3,0,1]
+    v += dpp_f(v, 2);   // row_half_mirror
+    v += dpp_f(v, 3);   // row_mirror
+    return v;
+}
+__device__ __forceinline__ double row16_sum(double v) {
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
 
@@ -355,8 +371,8 @@ __device__ __forceinline__ void adjoint_group(const GroupArgs& ga, const Src& sr
     const T xi = (T)(src.px[me] - cx), yi = (T)(src.py[me] - cy), zi = (T)(src.pz[me] - cz);
     const int64_t wi = (int64_t)ga.perm[me] * ws;
     const T w0 = (T)wx[wi], w1 = (T)wy[wi], w2 = (T)wz[wi];
-    // reduction role of this lane: entry re of the batch, part rp of 8
-    const int re = lane >> 3, rp = lane & 7;
+    // reduction role of this lane: entry re of the batch, part rp of 16
+    const int re = lane >> 4, rp = lane & 15;
     const int rs = re % S;
     double sx = 0, sy = 0, sz = 0;
     const int64_t e0 = ga.off[g], e1 = ga.off[g + 1];
@@ -401,7 +417,7 @@ __device__ __forceinline__ void adjoint_group(const GroupArgs& ga, const Src& sr
                 T ax = 0, ay = 0, az = 0, am = 0;
                 if (k < len) {
                     const V4* row = red + re * kRowSlots + rs * cnt;
-                    for (int q = rp; q < cnt; q += 8) {
+                    for (int q = rp; q < cnt; q += 16) {
                         const V4 v = row[q];
                         ax += v.x;
                         ay += v.y;
@@ -409,10 +425,10 @@ __device__ __forceinline__ void adjoint_group(const GroupArgs& ga, const Src& sr
                         am += v.w;
                     }
                 }
-                ax = xor8_sum(ax);
-                ay = xor8_sum(ay);
-                az = xor8_sum(az);
-                am = xor8_sum(am);
+                ax = row16_sum(ax);
+                ay = row16_sum(ay);
+                az = row16_sum(az);
+                am = row16_sum(am);
                 if (k < len && rp < 4) {
                     const int32_t v = tid_[k];
                     const T mu = tile[k].w;
@@ -455,19 +471,20 @@ __global__ __launch_bounds__(64) void k_adjoint(GroupArgs ga, Src src, Coef<T> c
     using V4 = typename Vec4<T>::type;
     __shared__ V4 tile[kTile];
     __shared__ int32_t tid_[kTile];
-    __shared__ V4 red[kB * kRowSlots];
-    __shared__ double ired[64 * 3];
+    __shared__ V4 red[kB * kRowSlots];   // also holds the final stream sums
+    static_assert(sizeof(V4) * kB * kRowSlots >= sizeof(double) * 64 * 3, "stream sums must fit");
+    double* ired = reinterpret_cast<double*>(red);
     __shared__ int32_t selfpos[64];
     const int64_t g = xcd_group(blockIdx.x, gridDim.x);
     const int32_t first = ga.gfirst[g], cnt = ga.gcount[g];
+    // at most kB streams: each stream takes at least one entry of a batch
+    static_assert(kB % 4 == 0, "the batch must split evenly over 4 streams");
     if (cnt > 32)
         adjoint_group<T, 1>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, tid_, red, ired, selfpos);
     else if (cnt > 16)
         adjoint_group<T, 2>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, tid_, red, ired, selfpos);
-    else if (cnt > 8)
-        adjoint_group<T, 4>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, tid_, red, ired, selfpos);
     else
-        adjoint_group<T, 8>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, tid_, red, ired, selfpos);
+        adjoint_group<T, 4>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, tid_, red, ired, selfpos);
 }
 
 // Node sources -> member particles.  For a cell c0 and its ancestors c
