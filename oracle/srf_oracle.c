@@ -226,6 +226,43 @@ int or_bf_cells(int64_t n, const double* x, const double* y, const double* z, co
     return 0;
 }
 
+/* The same brute-force sum for a subset of target particles sel[0..nsel). */
+int or_bf_cells_sel(int64_t n, const double* x, const double* y, const double* z, const double* m,
+                    double G, double rc, double eps, const int64_t* sel, int64_t nsel,
+                    double* ax, double* ay, double* az) {
+    cells_t cl;
+    int have = cells_build(n, x, y, z, rc, &cl);
+    int nc = have ? cl.nc : 0;
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < nsel; ++q) {
+        int64_t i = sel[q];
+        double a[3] = {0, 0, 0};
+        if (have) {
+            int cx = cell_coord(x[i], nc), cy = cell_coord(y[i], nc), cz = cell_coord(z[i], nc);
+            for (int ox = -1; ox <= 1; ++ox)
+            for (int oy = -1; oy <= 1; ++oy)
+            for (int oz = -1; oz <= 1; ++oz) {
+                int64_t c = ((int64_t)((cx + ox + nc) % nc) * nc + (cy + oy + nc) % nc) * nc + (cz + oz + nc) % nc;
+                for (int64_t t = cl.start[c]; t < cl.start[c + 1]; ++t) {
+                    int64_t j = cl.idx[t];
+                    double d[3] = {mimage(x[j] - x[i]), mimage(y[j] - y[i]), mimage(z[j] - z[i])};
+                    double p = phi_of(d[0] * d[0] + d[1] * d[1] + d[2] * d[2], rc, eps);
+                    a[0] += m[j] * d[0] * p; a[1] += m[j] * d[1] * p; a[2] += m[j] * d[2] * p;
+                }
+            }
+        } else {
+            for (int64_t j = 0; j < n; ++j) {
+                double d[3] = {mimage(x[j] - x[i]), mimage(y[j] - y[i]), mimage(z[j] - z[i])};
+                double p = phi_of(d[0] * d[0] + d[1] * d[1] + d[2] * d[2], rc, eps);
+                a[0] += m[j] * d[0] * p; a[1] += m[j] * d[1] * p; a[2] += m[j] * d[2] * p;
+            }
+        }
+        ax[q] = G * a[0]; ay[q] = G * a[1]; az[q] = G * a[2];
+    }
+    if (have) cells_free(&cl);
+    return have ? 0 : 1;
+}
+
 /* Number of ordered pairs (i, j != i) closer than r_cut (cell list). */
 int64_t or_bf_pair_count(int64_t n, const double* x, const double* y, const double* z, double rc) {
     cells_t cl;

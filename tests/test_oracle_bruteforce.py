@@ -97,3 +97,12 @@ def test_pair_count_matches_direct_count():
     r2 = np.sum(d * d, axis=2)
     direct = int(np.sum(r2 < ps.params.r_cut ** 2)) - ps.n
     assert oracle.pair_count(ps.x, ps.y, ps.z, ps.params.r_cut) == direct
+
+
+def test_selected_targets_match_full_sum():
+    ps = synth.small_clustered(5000, 77, r_cut=0.07, eps=3e-4, theta=0.5, per_halo=500)
+    p = ps.params
+    full = oracle.brute_force(ps.x, ps.y, ps.z, ps.m, p.G, p.r_cut, p.eps)
+    sel = np.random.default_rng(2).choice(ps.n, 300, replace=False)
+    part = oracle.brute_force_sel(ps.x, ps.y, ps.z, ps.m, p.G, p.r_cut, p.eps, sel)
+    assert np.array_equal(part, full[sel])
