@@ -13,8 +13,10 @@ oracle baseline, per-phase times).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -31,12 +33,45 @@ FLOPS_FORCE = 51
 FLOPS_ADJOINT = 86
 PEAK_FP32 = 157.3e12     # MI355X FP32 vector peak (packed), FLOP/s
 PEAK_FP64 = 78.6e12
+METRIC = "short-range pair interactions/s + % FP32 VALU peak; fwd and fwd+adjoint, N=2^24"
+
+# HBM traffic and executed-instruction counts of the pair kernels come from
+# rocprofv3 counter runs, summarised in this file; they are used only while
+# the kernel sources still hash to the value recorded with them.
+COUNTER_PROFILE = os.path.join(ROOT, "profiles", "pair_kernels_zeldovich256_counters.md")
+KERNEL_SOURCES = ("paper_1211_4406_amd/csrc/pair.hip", "paper_1211_4406_amd/csrc/common.h",
+                  "paper_1211_4406_amd/build.py")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_counters(workload: int, theta: float):
+    """The `bench-counters:` JSON line of the counter summary, if it was taken
+    on this workload and on the current kernel sources; else None."""
+    try:
+        with open(COUNTER_PROFILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    m = re.search(r"^bench-counters: (\{.*\})\s*$", text, re.M)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    if d.get("source_hash") != kernel_source_hash() or d.get("workload") != workload or d.get("theta") != theta:
+        return None
+    return d
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", type=int, default=3, help="1..5, see synth.CONFIGS")
     ap.add_argument("--theta", type=float, default=None)
@@ -169,7 +204,7 @@ def main():
     value = I / (ms_step * 1e-3)
     t_fwd = phases["tree_fwd"] + phases["lists_fwd"] + phases["force"]
     fwd_rate = I / (t_fwd * 1e-3)
-    kf, ka = float(np.mean(k_force)), float(np.mean(k_adj))
+    kf, ka = float(np.median(k_force)), float(np.median(k_adj))
 
     # all-FP64 kernel on the same lists (comparison)
     fp64 = None
@@ -190,21 +225,32 @@ def main():
 
     dominant = "adjoint" if ka >= kf else "force"
     kd = ka if dominant == "adjoint" else kf
-    flops = (FLOPS_ADJOINT if dominant == "adjoint" else FLOPS_FORCE) * I
-    achieved = flops / (kd * 1e-3)
-    roofline = dict(bound="alu", kernel=f"k_{dominant}<float>", achieved=achieved / 1e12, peak=PEAK_FP32 / 1e12,
-                    unit="TFLOP/s", frac=achieved / PEAK_FP32, traffic=None,
-                    flops_per_interaction=FLOPS_ADJOINT if dominant == "adjoint" else FLOPS_FORCE,
-                    interactions_per_launch=I, kernel_ms=kd)
+    fpi = FLOPS_ADJOINT if dominant == "adjoint" else FLOPS_FORCE
+    achieved = fpi * I / (kd * 1e-3)
+    prof = profiled_counters(args.workload, ps.params.theta)
+    kname = f"k_{dominant}<float>"
+    traffic = None
+    executed = {}
+    if prof is not None and prof.get("interactions") == I:
+        traffic = prof["kernels"][kname]["hbm_bytes"]
+        for k, tag in (("k_force<float>", "force"), ("k_adjoint<float>", "adjoint")):
+            fl = prof["kernels"][k]["fp32_flops"]
+            executed[tag] = dict(flops_per_interaction=fl / I,
+                                 frac=fl / ((kf if tag == "force" else ka) * 1e-3) / PEAK_FP32)
+    roofline = dict(bound="alu", kernel=kname, achieved=achieved / 1e12, peak=PEAK_FP32 / 1e12,
+                    unit="TFLOP/s", frac=achieved / PEAK_FP32, traffic=traffic,
+                    traffic_unit="bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated)",
+                    flops_per_interaction=fpi, interactions_per_launch=I, kernel_ms=kd,
+                    executed=executed.get(dominant))
     force_roofline = dict(achieved=FLOPS_FORCE * I / (kf * 1e-3) / 1e12, frac=FLOPS_FORCE * I / (kf * 1e-3) / PEAK_FP32,
-                          kernel_ms=kf, interactions_per_s=I / (kf * 1e-3))
+                          kernel_ms=kf, interactions_per_s=I / (kf * 1e-3), executed=executed.get("force"))
 
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(ps, args.cpu_sample_groups)
 
     out = {
-        "metric": "short-range pair interactions/s (fwd+adjoint step) + % FP32 VALU peak",
+        "metric": METRIC,
         "value": value,
         "unit": "interactions/s",
         "n_gpus": 1,
