@@ -6,7 +6,9 @@
 // (in FP64) to the offset x_j - c_g - rint(x_j - c_g) and stored with its
 // mass.  With N_i particles in the group, the wave runs S = floor(64/N_i)
 // independent j-streams (lane = i + N_i * stream), whose FP64 partial sums
-// are added at the end.
+// are added at the end.  Each staged tile is split into near entries (some
+// target may lie within r_cut/2 of them) and far entries (none can); far
+// pairs take only the [1,2] form of the cutoff function.
 //
 // Pair kernel (Sec. 2 force sum with the cutoff function of eq. (cutoff)):
 //   phi(r) = (r^2 + eps^2)^(-3/2) g(2 r / r_cut),
@@ -35,6 +37,8 @@ struct Coef {
     T C1, C3, C4, C5, C6;      // k^2 g'(xi)/xi on [0,1], in r
     T E0, E1, E2;              // k^2 g'(xi)/xi on [1,2] = -t^4 (E2 r^2 + E1 r + E0)
     T k, eps2, rh2;            // k = 2/r_cut, eps^2, (r_cut/2)^2
+    T m3;                      // -3 (not an inline constant of the ISA)
+    double far2;               // (r_cut/2)^2 in FP64, for the near/far split of a tile
 };
 
 template <class T>
@@ -64,6 +68,8 @@ Coef<T> make_coef(double rc, double eps) {
     c.k = (T)k;
     c.eps2 = (T)(eps * eps);
     c.rh2 = (T)(0.25 * rc * rc);
+    c.m3 = (T)(-3.0);
+    c.far2 = 0.25 * rc * rc;
     return c;
 }
 
@@ -96,7 +102,8 @@ __device__ __forceinline__ Coef<T> pinned(const Coef<T>& a) {
     c.R0 = pin_(a.R0); c.R1 = pin_(a.R1); c.R2 = pin_(a.R2); c.R3 = pin_(a.R3);
     c.C1 = pin_(a.C1); c.C3 = pin_(a.C3); c.C4 = pin_(a.C4); c.C5 = pin_(a.C5); c.C6 = pin_(a.C6);
     c.E0 = pin_(a.E0); c.E1 = pin_(a.E1); c.E2 = pin_(a.E2);
-    c.k = pin_(a.k); c.eps2 = pin_(a.eps2); c.rh2 = pin_(a.rh2);
+    c.k = pin_(a.k); c.eps2 = pin_(a.eps2); c.rh2 = pin_(a.rh2); c.m3 = pin_(a.m3);
+    c.far2 = a.far2;
     return c;
 }
 
@@ -124,16 +131,26 @@ __device__ __forceinline__ T cutoff_g(T r, T r2, const Coef<T>& c, T& t) {
 }
 
 // Force of one source (offset p.xyz, mass p.w) on one target (xi, yi, zi),
-// accumulated into (ax, ay, az).
-template <class T, class V4>
+// accumulated into (ax, ay, az).  NEAR selects the full cutoff function;
+// otherwise the source lies at xi >= 1 from the target, g = t^5 R, and the
+// factor m s^-3 t^5 R is formed as m (q^2)(q t)(t R) with q = t s^-1.
+template <class T, class V4, bool NEAR = true>
 __device__ __forceinline__ void pair_force(const V4& p, T xi, T yi, T zi, const Coef<T>& c, T& ax, T& ay, T& az) {
     const T dx = p.x - xi, dy = p.y - yi, dz = p.z - zi;
     const T r2 = fma_(dz, dz, fma_(dy, dy, dx * dx));
     const T rinv = rsqrt_(r2 + c.eps2);
     const T r = sqrt_(r2);
-    T t;
-    const T g = cutoff_g(r, r2, c, t);
-    const T f = (p.w * rinv) * (rinv * rinv) * g;
+    T f;
+    if (NEAR) {
+        T t;
+        const T g = cutoff_g(r, r2, c, t);
+        f = (p.w * rinv) * (rinv * rinv) * g;
+    } else {
+        const T t = sat_(fma_(r, -c.k, T(2)));
+        const T R = fma_(fma_(fma_(r, c.R3, c.R2), r, c.R1), r, c.R0);
+        const T q = t * rinv;
+        f = p.w * ((q * q) * ((q * t) * (t * R)));
+    }
     ax = fma_(f, dx, ax);
     ay = fma_(f, dy, ay);
     az = fma_(f, dz, az);
@@ -145,8 +162,15 @@ struct Src {
     const double *nX, *nY, *nZ, *nM;
 };
 
+// Load one list entry (particle v >= 0, or cell -v-1 as its monopole) as
+// the FP32 offset x_j - c - rint(x_j - c) from the group centre c, with its
+// mass, and classify it: far when its distance to the group's box (half
+// extents h) is at least r_cut/2, so that xi >= 1 holds for every target of
+// the group.  The distance is the FP64 distance from the source point
+// (particle or centre of mass) to the box.
 template <class T, class V4>
-__device__ __forceinline__ V4 load_entry(int32_t v, const Src& s, double cx, double cy, double cz) {
+__device__ __forceinline__ V4 load_entry_cls(int32_t v, const Src& s, double cx, double cy, double cz, double hx,
+                                             double hy, double hz, double far2, bool& far) {
     double X, Y, Z, M;
     if (v >= 0) {
         X = s.px[v];
@@ -164,12 +188,75 @@ __device__ __forceinline__ V4 load_entry(int32_t v, const Src& s, double cx, dou
     rx -= rint(rx);
     ry -= rint(ry);
     rz -= rint(rz);
+    const double ex = fmax(fabs(rx) - hx, 0.0), ey = fmax(fabs(ry) - hy, 0.0), ez = fmax(fabs(rz) - hz, 0.0);
+    far = ex * ex + ey * ey + ez * ez >= far2;
     V4 o;
     o.x = (T)rx;
     o.y = (T)ry;
     o.z = (T)rz;
     o.w = (T)M;
     return o;
+}
+
+// Stage one tile of a group's list in LDS, near entries first (slots
+// [0, n_near)) and far entries after them (filled from the end).  Returns
+// n_near; the order within each class is fixed by the list, so the result
+// is deterministic.  An entry that is one of the group's own particles is
+// near.  `ids`, if given, receives the entries' list values.  The PAD
+// slots after the last entry are set to zero mass at the origin (list value
+// -1), so that a read past the end of a segment stays finite.
+template <class T, class V4, int PAD = 0>
+__device__ __forceinline__ int stage_tile(const int32_t* __restrict__ ent, int len, const Src& src, double cx,
+                                          double cy, double cz, double hx, double hy, double hz, double far2,
+                                          V4* tile, int32_t* ids) {
+    const int lane = threadIdx.x;
+    if (PAD > 0 && lane < PAD) {
+        V4 z;
+        z.x = z.y = z.z = z.w = T(0);
+        tile[len + lane] = z;
+        if (ids) ids[len + lane] = -1;
+    }
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int nnear = 0, nfar = 0;
+    for (int k0 = 0; k0 < len; k0 += 64) {
+        const int k = k0 + lane;
+        const bool valid = k < len;
+        bool far = false;
+        V4 e;
+        int32_t v = 0;
+        if (valid) {
+            v = ent[k];
+            e = load_entry_cls<T, V4>(v, src, cx, cy, cz, hx, hy, hz, far2, far);
+        }
+        const uint64_t mn = __ballot(valid && !far), mf = __ballot(valid && far);
+        if (valid) {
+            const int pos = far ? len - 1 - (nfar + __popcll(mf & lt)) : nnear + __popcll(mn & lt);
+            tile[pos] = e;
+            if (ids) ids[pos] = v;
+        }
+        nnear += __popcll(mn);
+        nfar += __popcll(mf);
+    }
+    return nnear;
+}
+
+// Pairs of this lane's stream with the entries [a, b) of a staged tile
+// (entries a + st, a + st + S, ...).  The unrolled loop runs while all
+// streams have four entries left, so its trip count is the same for every
+// lane.
+template <class T, class V4, int S, bool NEAR>
+__device__ __forceinline__ void force_segment(const V4* tile, int a, int b, int st, T xi, T yi, T zi,
+                                              const Coef<T>& c, T& fx, T& fy, T& fz) {
+    const V4* tp = tile + a + st;
+    int kk = a;
+    for (; kk + 4 * S <= b; kk += 4 * S, tp += 4 * S) {
+        const V4 p0 = tp[0], p1 = tp[S], p2 = tp[2 * S], p3 = tp[3 * S];
+        pair_force<T, V4, NEAR>(p0, xi, yi, zi, c, fx, fy, fz);
+        pair_force<T, V4, NEAR>(p1, xi, yi, zi, c, fx, fy, fz);
+        pair_force<T, V4, NEAR>(p2, xi, yi, zi, c, fx, fy, fz);
+        pair_force<T, V4, NEAR>(p3, xi, yi, zi, c, fx, fy, fz);
+    }
+    for (int k = kk + st; k < b; k += S, tp += S) pair_force<T, V4, NEAR>(tp[0], xi, yi, zi, c, fx, fy, fz);
 }
 
 // Workgroups are handed to the 8 XCDs (each with its own L2) round-robin
@@ -203,6 +290,9 @@ __device__ __forceinline__ void force_group(const GroupArgs& ga, const Src& src,
     const double cx = (ga.glo[g * 3 + 0] + ga.ghi[g * 3 + 0]) * 0.5;
     const double cy = (ga.glo[g * 3 + 1] + ga.ghi[g * 3 + 1]) * 0.5;
     const double cz = (ga.glo[g * 3 + 2] + ga.ghi[g * 3 + 2]) * 0.5;
+    const double hx = (ga.ghi[g * 3 + 0] - ga.glo[g * 3 + 0]) * 0.5;
+    const double hy = (ga.ghi[g * 3 + 1] - ga.glo[g * 3 + 1]) * 0.5;
+    const double hz = (ga.ghi[g * 3 + 2] - ga.glo[g * 3 + 2]) * 0.5;
     const int32_t me = first + il;
     const T xi = (T)(src.px[me] - cx), yi = (T)(src.py[me] - cy), zi = (T)(src.pz[me] - cz);
     double sx = 0, sy = 0, sz = 0;
@@ -210,20 +300,12 @@ __device__ __forceinline__ void force_group(const GroupArgs& ga, const Src& src,
     for (int64_t tb = e0; tb < e1; tb += kTile) {
         const int len = (int)((e1 - tb) < kTile ? (e1 - tb) : kTile);
         __syncthreads();
-        for (int k = lane; k < len; k += 64) tile[k] = load_entry<T, V4>(ga.ent[tb + k], src, cx, cy, cz);
+        const int nnear = stage_tile<T, V4>(ga.ent + tb, len, src, cx, cy, cz, hx, hy, hz, c0.far2, tile, nullptr);
         __syncthreads();
         T fx = 0, fy = 0, fz = 0;
         if (active) {
-            const V4* tp = tile + st;
-            int k = st;
-            for (; k + 3 * S < len; k += 4 * S, tp += 4 * S) {
-                const V4 p0 = tp[0], p1 = tp[S], p2 = tp[2 * S], p3 = tp[3 * S];
-                pair_force<T, V4>(p0, xi, yi, zi, c, fx, fy, fz);
-                pair_force<T, V4>(p1, xi, yi, zi, c, fx, fy, fz);
-                pair_force<T, V4>(p2, xi, yi, zi, c, fx, fy, fz);
-                pair_force<T, V4>(p3, xi, yi, zi, c, fx, fy, fz);
-            }
-            for (; k < len; k += S, tp += S) pair_force<T, V4>(tp[0], xi, yi, zi, c, fx, fy, fz);
+            force_segment<T, V4, S, true>(tile, 0, nnear, st, xi, yi, zi, c, fx, fy, fz);
+            force_segment<T, V4, S, false>(tile, nnear, len, st, xi, yi, zi, c, fx, fy, fz);
         }
         sx += (double)fx;
         sy += (double)fy;
@@ -251,7 +333,7 @@ __device__ __forceinline__ void force_group(const GroupArgs& ga, const Src& src,
 
 // Streams per group: the largest of 1, 2, 3, 4, 8 with S * N_i <= 64.
 template <class T>
-__global__ __launch_bounds__(64) void k_force(GroupArgs ga, Src src, Coef<T> c, double G, double* __restrict__ ax,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 4))) void k_force(GroupArgs ga, Src src, Coef<T> c, double G, double* __restrict__ ax,
                                               double* __restrict__ ay, double* __restrict__ az, int64_t os) {
     using V4 = typename Vec4<T>::type;
     __shared__ V4 tile[kTile];
@@ -277,29 +359,41 @@ struct PairJ {
 
 // `self` marks the pair of a particle with itself, which the force sum
 // (over j != i) leaves out: its inverse distance is set to 0, so phi and
-// psi vanish.
-template <class T, class V4>
+// psi vanish.  Without NEAR the source lies at xi >= 1 from the target
+// (never the target itself) and only the [1,2] forms of g and g' are taken.
+template <class T, class V4, bool NEAR = true>
 __device__ __forceinline__ PairJ<T> pair_jac(const V4& p, T xi, T yi, T zi, T wx, T wy, T wz, const Coef<T>& c,
                                              bool self) {
     const T dx = p.x - xi, dy = p.y - yi, dz = p.z - zi;
     const T r2 = fma_(dz, dz, fma_(dy, dy, dx * dx));
-    const T rinv = self ? T(0) : rsqrt_(r2 + c.eps2);
+    const T rinv = (NEAR && self) ? T(0) : rsqrt_(r2 + c.eps2);
     const T r = sqrt_(r2);
-    T t;
-    const T g = cutoff_g(r, r2, c, t);
-    // h = k^2 g'(xi) / xi on each branch (no division by r needed)
-    T u = fma_(r, c.C6, c.C5);
-    u = fma_(r, u, c.C4);
-    u = fma_(r, u, c.C3);
-    u = fma_(r2, u, c.C1);
-    const T h1 = u * r;
-    const T t2 = t * t;
-    const T h2 = -(t2 * t2) * fma_(r2, c.E2, fma_(r, c.E1, c.E0));
-    const T h = r2 < c.rh2 ? h1 : h2;
-    const T rinv2 = rinv * rinv;
-    const T s3 = rinv2 * rinv;
-    const T phi = s3 * g;
-    const T psi = s3 * fma_(T(-3) * rinv2, g, h);
+    const T u = rinv * rinv;
+    const T s3 = u * rinv;
+    T phi, psi;
+    if (NEAR) {
+        T t;
+        const T g = cutoff_g(r, r2, c, t);
+        // h = k^2 g'(xi) / xi on each branch (no division by r needed)
+        T v = fma_(r, c.C6, c.C5);
+        v = fma_(r, v, c.C4);
+        v = fma_(r, v, c.C3);
+        v = fma_(r2, v, c.C1);
+        const T h1 = v * r;
+        const T t2 = t * t;
+        const T h2 = -(t2 * t2) * fma_(r2, c.E2, fma_(r, c.E1, c.E0));
+        const T h = r2 < c.rh2 ? h1 : h2;
+        phi = s3 * g;
+        psi = s3 * fma_(c.m3 * u, g, h);
+    } else {
+        // g = t^4 (t R), h = -t^4 P; with a = s^-3 t^4:
+        // phi = a (t R), psi = s^-3 (h - 3 u g) = -3 u phi - a P
+        const T t = sat_(fma_(r, -c.k, T(2)));
+        const T R = fma_(fma_(fma_(r, c.R3, c.R2), r, c.R1), r, c.R0);
+        const T a = s3 * ((t * t) * (t * t));
+        phi = a * (t * R);
+        psi = fma_(c.m3 * u, phi, -(a * fma_(r2, c.E2, fma_(r, c.E1, c.E0))));
+    }
     const T dw = fma_(dz, wz, fma_(dy, wy, dx * wx));
     const T s = psi * dw;
     PairJ<T> o;
@@ -317,20 +411,25 @@ struct AdjOut {
     int64_t n, nn;
 };
 
-// Adjoint pair pass.  Lanes hold targets i (S = 1, 2 or 4 streams of
-// N_i lanes); entries are taken in batches of kB.  Each lane
-//   - accumulates its i-side term -mu V in registers, and
-//   - writes V = J w_i and phi (d . w_i) to an LDS row of its entry;
-// the rows are then summed across lanes (16 lanes per entry, each over a
-// strided subset of the entry's stream, then a DPP reduction over the 16),
-// scaled by the source mass and added to the source's gradient with one
-// FP64 atomic per component.
-constexpr int kB = 4;              // entries per reduction batch
-constexpr int kRowSlots = 64 + 1;  // 4-vectors per entry row (one of padding)
+// Adjoint pair pass.  The wave is laid out as 4 rows of 16 lanes: lane
+// (a, b) = (lane & 15, lane >> 4).  Targets are taken in NB blocks of 16
+// (target 16 ib + a in block ib, NB = ceil(N_i / 16)), entries in blocks of
+// 4 (entry b of the block on row b).  For one entry block a lane evaluates
+// its entry against its target of each of the NB target blocks:
+//   - the i-side term -mu V goes to the lane's FP32 accumulator of that
+//     target (summed over rows once per tile, in FP64),
+//   - V = J w_i and phi (d . w_i) are summed in registers over the NB
+//     blocks, then over the 16 lanes of the row with DPP moves; four lanes
+//     of the row scale by the source mass and add the totals to the
+//     source's gradient with one FP64 atomic per component.
+// Targets past N_i carry zero weight, so they add nothing to either side.
+constexpr int kRow = 16;   // lanes per row: targets per block
+constexpr int kRows = 4;   // rows: entries per block
 
 // Sum over the 16 lanes of a row (lanes 16r..16r+15) with DPP moves, which
 // stay in the vector ALU: xor 1 and xor 2 within quads, then the
-// half-row and row mirrors pair up the quads and the half-rows.
+// half-row and row mirrors pair up the quads and the half-rows.  Every lane
+// of the row ends with the total.
 __device__ __forceinline__ float dpp_f(float v, int ctrl) {
     switch (ctrl) {
         case 0: return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xf, 0xf, false));
@@ -352,139 +451,152 @@ __device__ __forceinline__ double row16_sum(double v) {
     return v;
 }
 
-template <class T, int S>
+// Targets of one lane: block ib holds target 16 ib + a.
+template <class T, int NB>
+struct Targets {
+    T x[NB], y[NB], z[NB], wx[NB], wy[NB], wz[NB];
+    T fx[NB], fy[NB], fz[NB];
+    int32_t id[NB];     // sorted particle index, for the self test
+};
+
+// Entry blocks [a, b) of a staged tile (all near or all far).
+template <class T, class V4, int NB, bool NEAR>
+__device__ __forceinline__ void adjoint_entries(int a, int b, const V4* tile, const int32_t* ids, int lane,
+                                                Targets<T, NB>& tg, const Coef<T>& c, const AdjOut& out) {
+    const int ra = lane & (kRow - 1), rb = lane >> 4;
+    for (int eb = a; eb < b; eb += kRows) {
+        // slots up to b + kRows - 1 hold entries of the next segment or the
+        // zero padding; past b the mass is taken as zero
+        const int e = eb + rb;
+        const bool valid = e < b;
+        V4 p = tile[e];
+        const int32_t v = ids[e];
+        p.w = valid ? p.w : T(0);
+        T jx, jy, jz, jm;
+#pragma unroll
+        for (int ib = 0; ib < NB; ++ib) {
+            const PairJ<T> j = pair_jac<T, V4, NEAR>(p, tg.x[ib], tg.y[ib], tg.z[ib], tg.wx[ib], tg.wy[ib], tg.wz[ib],
+                                                     c, NEAR && v == tg.id[ib]);
+            tg.fx[ib] = fma_(-p.w, j.vx, tg.fx[ib]);
+            tg.fy[ib] = fma_(-p.w, j.vy, tg.fy[ib]);
+            tg.fz[ib] = fma_(-p.w, j.vz, tg.fz[ib]);
+            if (ib == 0) {
+                jx = j.vx;
+                jy = j.vy;
+                jz = j.vz;
+                jm = j.fw;
+            } else {
+                jx += j.vx;
+                jy += j.vy;
+                jz += j.vz;
+                jm += j.fw;
+            }
+        }
+        jx = row16_sum(jx);
+        jy = row16_sum(jy);
+        jz = row16_sum(jz);
+        jm = row16_sum(jm);
+        if (valid && ra < 4) {
+            // component ra of (mu V_x, mu V_y, mu V_z, sum phi (d . w))
+            const T lo = (ra & 1) ? jy : jx;
+            const T hi = (ra & 1) ? jm : jz;
+            const T val = ((ra & 2) ? hi : lo) * (ra == 3 ? T(1) : p.w);
+            // the four components of one source are adjacent (one 32-byte line)
+            double* dst = v >= 0 ? out.gj + 4 * (int64_t)v + ra : out.gn + 4 * (int64_t)(-v - 1) + ra;
+            unsafeAtomicAdd(dst, (double)val);
+        }
+    }
+}
+
+template <class T, int NB>
 __device__ __forceinline__ void adjoint_group(const GroupArgs& ga, const Src& src, const Coef<T>& c0,
                                               const double* __restrict__ wx, const double* __restrict__ wy,
                                               const double* __restrict__ wz, int64_t ws, const AdjOut& out,
                                               int64_t g, int32_t first, int32_t cnt,
-                                              typename Vec4<T>::type* tile, int32_t* tid_,
-                                              typename Vec4<T>::type* red, double* ired, int32_t* selfpos) {
+                                              typename Vec4<T>::type* tile, int32_t* ids, double* ired) {
     using V4 = typename Vec4<T>::type;
     const Coef<T> c = pinned(c0);
     const int lane = threadIdx.x;
-    const int il = lane % cnt, st = lane / cnt;
-    const bool active = st < S;
+    const int ra = lane & (kRow - 1);
     const double cx = (ga.glo[g * 3 + 0] + ga.ghi[g * 3 + 0]) * 0.5;
     const double cy = (ga.glo[g * 3 + 1] + ga.ghi[g * 3 + 1]) * 0.5;
     const double cz = (ga.glo[g * 3 + 2] + ga.ghi[g * 3 + 2]) * 0.5;
-    const int32_t me = first + il;
-    const T xi = (T)(src.px[me] - cx), yi = (T)(src.py[me] - cy), zi = (T)(src.pz[me] - cz);
-    const int64_t wi = (int64_t)ga.perm[me] * ws;
-    const T w0 = (T)wx[wi], w1 = (T)wy[wi], w2 = (T)wz[wi];
-    // reduction role of this lane: entry re of the batch, part rp of 16
-    const int re = lane >> 4, rp = lane & 15;
-    const int rs = re % S;
-    double sx = 0, sy = 0, sz = 0;
+    const double hx = (ga.ghi[g * 3 + 0] - ga.glo[g * 3 + 0]) * 0.5;
+    const double hy = (ga.ghi[g * 3 + 1] - ga.glo[g * 3 + 1]) * 0.5;
+    const double hz = (ga.ghi[g * 3 + 2] - ga.glo[g * 3 + 2]) * 0.5;
+    Targets<T, NB> tg;
+#pragma unroll
+    for (int ib = 0; ib < NB; ++ib) {
+        const int i = ib * kRow + ra;
+        const int32_t me = first + (i < cnt ? i : 0);
+        tg.x[ib] = (T)(src.px[me] - cx);
+        tg.y[ib] = (T)(src.py[me] - cy);
+        tg.z[ib] = (T)(src.pz[me] - cz);
+        const int64_t wi = (int64_t)ga.perm[me] * ws;
+        const bool on = i < cnt;
+        tg.wx[ib] = on ? (T)wx[wi] : T(0);
+        tg.wy[ib] = on ? (T)wy[wi] : T(0);
+        tg.wz[ib] = on ? (T)wz[wi] : T(0);
+        tg.id[ib] = on ? first + i : INT32_MIN;   // INT32_MIN is no list value
+        ired[(ib * 64 + lane) * 3 + 0] = 0.0;
+        ired[(ib * 64 + lane) * 3 + 1] = 0.0;
+        ired[(ib * 64 + lane) * 3 + 2] = 0.0;
+    }
     const int64_t e0 = ga.off[g], e1 = ga.off[g + 1];
     for (int64_t tb = e0; tb < e1; tb += kTile) {
         const int len = (int)((e1 - tb) < kTile ? (e1 - tb) : kTile);
         __syncthreads();
-        selfpos[lane] = -1;
+        const int nnear = stage_tile<T, V4, kRows>(ga.ent + tb, len, src, cx, cy, cz, hx, hy, hz, c0.far2, tile, ids);
         __syncthreads();
-        for (int k = lane; k < len; k += 64) {
-            const int32_t v = ga.ent[tb + k];
-            tile[k] = load_entry<T, V4>(v, src, cx, cy, cz);
-            tid_[k] = v;
-            if (v >= first && v < first + cnt) selfpos[v - first] = k;
-        }
-        __syncthreads();
-        const int sp = selfpos[il];   // tile slot of this lane's own particle, or -1
-        T fx = 0, fy = 0, fz = 0;
-        for (int kb = 0; kb < len; kb += kB) {
-            if (active) {
 #pragma unroll
-                for (int q = 0; q < kB / S; ++q) {
-                    const int e = st + q * S;
-                    const int k = kb + e;
-                    if (k < len) {
-                        const V4 p = tile[k];
-                        const PairJ<T> j = pair_jac<T, V4>(p, xi, yi, zi, w0, w1, w2, c, k == sp);
-                        fx = fma_(-p.w, j.vx, fx);
-                        fy = fma_(-p.w, j.vy, fy);
-                        fz = fma_(-p.w, j.vz, fz);
-                        V4 o;
-                        o.x = j.vx;
-                        o.y = j.vy;
-                        o.z = j.vz;
-                        o.w = j.fw;
-                        red[e * kRowSlots + lane] = o;
-                    }
-                }
-            }
-            __syncthreads();
-            {
-                const int k = kb + re;
-                T ax = 0, ay = 0, az = 0, am = 0;
-                if (k < len) {
-                    const V4* row = red + re * kRowSlots + rs * cnt;
-                    for (int q = rp; q < cnt; q += 16) {
-                        const V4 v = row[q];
-                        ax += v.x;
-                        ay += v.y;
-                        az += v.z;
-                        am += v.w;
-                    }
-                }
-                ax = row16_sum(ax);
-                ay = row16_sum(ay);
-                az = row16_sum(az);
-                am = row16_sum(am);
-                if (k < len && rp < 4) {
-                    const int32_t v = tid_[k];
-                    const T mu = tile[k].w;
-                    const T val = rp == 0 ? ax * mu : (rp == 1 ? ay * mu : (rp == 2 ? az * mu : am));
-                    // the four components of one source are adjacent (one 32-byte line)
-                    double* dst = v >= 0 ? out.gj + 4 * (int64_t)v + rp : out.gn + 4 * (int64_t)(-v - 1) + rp;
-                    unsafeAtomicAdd(dst, (double)val);
-                }
-            }
-            __syncthreads();
+        for (int ib = 0; ib < NB; ++ib) tg.fx[ib] = tg.fy[ib] = tg.fz[ib] = T(0);
+        adjoint_entries<T, V4, NB, true>(0, nnear, tile, ids, lane, tg, c, out);
+        adjoint_entries<T, V4, NB, false>(nnear, len, tile, ids, lane, tg, c, out);
+        // FP32 tile partials into this lane's FP64 slots
+#pragma unroll
+        for (int ib = 0; ib < NB; ++ib) {
+            ired[(ib * 64 + lane) * 3 + 0] += (double)tg.fx[ib];
+            ired[(ib * 64 + lane) * 3 + 1] += (double)tg.fy[ib];
+            ired[(ib * 64 + lane) * 3 + 2] += (double)tg.fz[ib];
         }
-        sx += (double)fx;
-        sy += (double)fy;
-        sz += (double)fz;
     }
-    // sum the streams of each target
-    ired[lane * 3 + 0] = active ? sx : 0.0;
-    ired[lane * 3 + 1] = active ? sy : 0.0;
-    ired[lane * 3 + 2] = active ? sz : 0.0;
     __syncthreads();
+    // target i = 16 ib + a: sum its four rows
     if (lane < cnt) {
+        const int ib = lane >> 4, a = lane & (kRow - 1);
         double tx = 0, ty = 0, tz = 0;
 #pragma unroll
-        for (int q = 0; q < S; ++q) {
-            const int l = lane + q * cnt;
+        for (int r = 0; r < kRows; ++r) {
+            const int l = ib * 64 + r * kRow + a;
             tx += ired[l * 3 + 0];
             ty += ired[l * 3 + 1];
             tz += ired[l * 3 + 2];
         }
-        out.gix[me] = tx;
-        out.giy[me] = ty;
-        out.giz[me] = tz;
+        out.gix[first + lane] = tx;
+        out.giy[first + lane] = ty;
+        out.giz[first + lane] = tz;
     }
 }
 
 template <class T>
-__global__ __launch_bounds__(64) void k_adjoint(GroupArgs ga, Src src, Coef<T> c, const double* __restrict__ wx,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) void k_adjoint(GroupArgs ga, Src src, Coef<T> c, const double* __restrict__ wx,
                                                 const double* __restrict__ wy, const double* __restrict__ wz, int64_t ws,
                                                 AdjOut out) {
     using V4 = typename Vec4<T>::type;
-    __shared__ V4 tile[kTile];
-    __shared__ int32_t tid_[kTile];
-    __shared__ V4 red[kB * kRowSlots];   // also holds the final stream sums
-    static_assert(sizeof(V4) * kB * kRowSlots >= sizeof(double) * 64 * 3, "stream sums must fit");
-    double* ired = reinterpret_cast<double*>(red);
-    __shared__ int32_t selfpos[64];
+    __shared__ V4 tile[kTile + kRows];
+    __shared__ int32_t ids[kTile + kRows];
+    __shared__ double ired[4 * 64 * 3];   // per target block and lane: FP64 i-side sums
     const int64_t g = xcd_group(blockIdx.x, gridDim.x);
     const int32_t first = ga.gfirst[g], cnt = ga.gcount[g];
-    // at most kB streams: each stream takes at least one entry of a batch
-    static_assert(kB % 4 == 0, "the batch must split evenly over 4 streams");
-    if (cnt > 32)
-        adjoint_group<T, 1>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, tid_, red, ired, selfpos);
+    static_assert(kRow * kRows == 64, "one wave is kRows rows of kRow lanes");
+    if (cnt > 48)
+        adjoint_group<T, 4>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, ids, ired);
+    else if (cnt > 32)
+        adjoint_group<T, 3>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, ids, ired);
     else if (cnt > 16)
-        adjoint_group<T, 2>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, tid_, red, ired, selfpos);
+        adjoint_group<T, 2>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, ids, ired);
     else
-        adjoint_group<T, 4>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, tid_, red, ired, selfpos);
+        adjoint_group<T, 1>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, ids, ired);
 }
 
 // Node sources -> member particles.  For a cell c0 and its ancestors c
