@@ -115,7 +115,6 @@ struct Lists {
     hipStream_t stream = nullptr;
     DevBuf<int64_t> off;       // [ng+1] entry offsets per group
     DevBuf<int32_t> ent;       // entries: s >= 0 particle (sorted index), -(c+1) cell c
-    DevBuf<int32_t> order;     // groups in descending cost order (launch order)
 };
 
 // ------------------------------------------------------------------ scan
@@ -145,6 +144,7 @@ void launch_adjoint(const Tree& t, const Lists& l, const srf_params& p, const do
 // Fill helpers (kernels, safe under stream capture).
 void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 void fill_f64(double* p, double v, int64_t n, hipStream_t s);
+void fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t s);
 
 inline int grid_for(int64_t n, int block, int cap = 1 << 20) {
     int64_t g = (n + block - 1) / block;

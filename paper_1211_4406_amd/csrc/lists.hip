@@ -5,7 +5,9 @@
 // pruned, accepted or a leaf is left through its skip link, any other cell
 // is opened by stepping to the next preorder index (its first child).  A
 // count pass sizes the lists, a scan places them, and a write pass emits
-// the entries in DFS order (particles ascending, cells in preorder).
+// one item per leaf or accepted cell in DFS order; an expansion pass then
+// writes the entries (a leaf's particles ascending, cells in preorder) with
+// one wave per group, so that the list memory is written in whole lines.
 //
 // Compiled with -ffp-contract=off: the decisions are the literal FP64
 // expressions, evaluated in this order:
@@ -87,8 +89,8 @@ __global__ __launch_bounds__(128) void k_lists(int64_t ng, const double* __restr
                                                const double* __restrict__ ghi, const int32_t* __restrict__ gcount,
                                                const uint4* __restrict__ pack, const NodeRange* __restrict__ rng,
                                                int64_t nn, double rc2, double th2, int64_t* __restrict__ cnt,
-                                               unsigned long long* __restrict__ totals, const int64_t* __restrict__ off,
-                                               int32_t* __restrict__ ent) {
+                                               int64_t* __restrict__ icnt, unsigned long long* __restrict__ totals,
+                                               const int64_t* __restrict__ ioff, int32_t* __restrict__ items) {
     static_assert(G * kLevels <= 64, "level masks must fit one word");
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t g0 = t * G;
@@ -104,7 +106,7 @@ __global__ __launch_bounds__(128) void k_lists(int64_t ng, const double* __restr
         f[q] = group_frame(glo, ghi, g);
         if (g0 + q < ng) {
             valid |= 1ull << q;
-            if (WRITE) out[q] = ent + off[g];
+            if (WRITE) out[q] = items + ioff[g];
         }
     }
     const uint64_t full = (1ull << G) - 1ull;
@@ -115,7 +117,6 @@ __global__ __launch_bounds__(128) void k_lists(int64_t ng, const double* __restr
         const uint64_t act = (masks >> (k.level * G)) & full;
         uint64_t open = 0;
         if (act) {
-            int32_t lf = -1;
 #pragma unroll
             for (int q = 0; q < G; ++q) {
                 if (!((act >> q) & 1ull)) continue;
@@ -126,18 +127,13 @@ __global__ __launch_bounds__(128) void k_lists(int64_t ng, const double* __restr
                     if (WRITE) out[q][w[q]++] = -(int32_t)i - 1;
                     else ++nc[q];
                 } else if (cls == 2) {
-                    uint32_t m = k.count;
-                    if (WRITE || m == kPackCountMax) {
-                        if (lf < 0 || m == kPackCountMax) {
-                            const NodeRange r = rng[i];
-                            lf = r.first;
-                            m = (uint32_t)r.count;
-                        }
-                    }
                     if (WRITE) {
-                        for (uint32_t s = 0; s < m; ++s) out[q][w[q]++] = lf + (int32_t)s;
+                        out[q][w[q]++] = (int32_t)i;
                     } else {
+                        uint32_t m = k.count;
+                        if (m == kPackCountMax) m = (uint32_t)rng[i].count;
                         np[q] += m;
+                        ++w[q];
                     }
                 }
             }
@@ -156,6 +152,7 @@ __global__ __launch_bounds__(128) void k_lists(int64_t ng, const double* __restr
     for (int q = 0; q < G; ++q) {
         if (!((valid >> q) & 1ull)) continue;
         cnt[g0 + q] = np[q] + nc[q];
+        icnt[g0 + q] = w[q] + nc[q];   // leaves + accepted cells
         a += (unsigned long long)np[q];
         b += (unsigned long long)nc[q];
         c += (unsigned long long)gcount[g0 + q] * (unsigned long long)(np[q] + nc[q]);
@@ -173,6 +170,51 @@ __global__ __launch_bounds__(128) void k_lists(int64_t ng, const double* __restr
     }
 }
 
+// Expansion: one wave per group turns its items into entries.  Items are
+// taken 64 at a time (one per lane); a leaf item stands for its particles
+// first..first+count-1, a cell item for itself.  An inclusive scan of the
+// item sizes places each item, and the lanes write their items in rounds
+// (round s writes the s-th entry of every item that has one), so a round
+// fills a contiguous stretch of the list.
+__global__ __launch_bounds__(64) void k_expand(int64_t ng, const int64_t* __restrict__ ioff,
+                                               const int32_t* __restrict__ items, const NodeRange* __restrict__ rng,
+                                               const int64_t* __restrict__ off, int32_t* __restrict__ ent) {
+    const int64_t g = blockIdx.x;
+    if (g >= ng) return;
+    const int lane = threadIdx.x;
+    const int64_t i0 = ioff[g], i1 = ioff[g + 1];
+    int64_t base = off[g];
+    for (int64_t c0 = i0; c0 < i1; c0 += 64) {
+        const int64_t ii = c0 + lane;
+        int32_t v = 0, first = 0, n = 0;
+        if (ii < i1) {
+            v = items[ii];
+            if (v >= 0) {
+                const NodeRange r = rng[v];
+                first = r.first;
+                n = r.count;
+            } else {
+                first = v;
+                n = 1;
+            }
+        }
+        int incl = n;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += u;
+        }
+        const int total = __shfl(incl, 63, 64);
+        int maxn = n;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) maxn = max(maxn, __shfl_xor(maxn, o, 64));
+        int32_t* dst = ent + base + (incl - n);
+        for (int s2 = 0; s2 < maxn; ++s2)
+            if (s2 < n) dst[s2] = v >= 0 ? first + s2 : first;
+        base += total;
+    }
+}
+
 constexpr int kGroupsPerThread = 2;
 
 }  // namespace
@@ -183,28 +225,39 @@ void build_lists(const Tree& t, Lists& l, hipStream_t st) {
     const double th2 = l.theta * l.theta;
     l.n_groups = ng;
     l.off.alloc(ng + 1, st);
+    DevBuf<int64_t> ioff(ng + 1, st);
     DevBuf<unsigned long long> totals(4, st);
-    SRF_HIP(hipMemsetAsync(totals.get(), 0, 4 * sizeof(unsigned long long), st));
+    fill_u64(totals.get(), 0ull, 4, st);
     const int B = 128;
     constexpr int G = kGroupsPerThread;
     const int64_t nthreads = (ng + G - 1) / G;
     hipLaunchKernelGGL((k_lists<G, false>), dim3(grid_for(nthreads, B, 1 << 30)), dim3(B), 0, st, ng, t.glo.get(),
                        t.ghi.get(), t.gcount.get(), t.pack.get(), t.range.get(), t.n_nodes, rc2, th2, l.off.get(),
-                       totals.get(), (const int64_t*)nullptr, (int32_t*)nullptr);
+                       ioff.get(), totals.get(), (const int64_t*)nullptr, (int32_t*)nullptr);
     SRF_HIP(hipGetLastError());
     exclusive_scan_i64(l.off.get(), ng, true, st);
+    exclusive_scan_i64(ioff.get(), ng, true, st);
     unsigned long long h[3];
+    int64_t n_items = 0;
     SRF_HIP(hipMemcpyAsync(h, totals.get(), 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    SRF_HIP(hipMemcpyAsync(&n_items, ioff.get() + ng, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     SRF_HIP(hipStreamSynchronize(st));
     l.n_particle_entries = (int64_t)h[0];
     l.n_node_entries = (int64_t)h[1];
     l.n_entries = (int64_t)(h[0] + h[1]);
     l.interactions = (int64_t)h[2];
     l.ent.alloc(l.n_entries > 0 ? l.n_entries : 1, st);
+    DevBuf<int32_t> items(n_items > 0 ? n_items : 1, st);
     hipLaunchKernelGGL((k_lists<G, true>), dim3(grid_for(nthreads, B, 1 << 30)), dim3(B), 0, st, ng, t.glo.get(),
                        t.ghi.get(), t.gcount.get(), t.pack.get(), t.range.get(), t.n_nodes, rc2, th2,
-                       (int64_t*)nullptr, (unsigned long long*)nullptr, (const int64_t*)l.off.get(), l.ent.get());
+                       (int64_t*)nullptr, (int64_t*)nullptr, (unsigned long long*)nullptr, (const int64_t*)ioff.get(),
+                       items.get());
     SRF_HIP(hipGetLastError());
+    if (ng > 0) {
+        hipLaunchKernelGGL(k_expand, dim3((unsigned)ng), dim3(64), 0, st, ng, ioff.get(), items.get(), t.range.get(),
+                           l.off.get(), l.ent.get());
+        SRF_HIP(hipGetLastError());
+    }
 }
 
 }  // namespace srf

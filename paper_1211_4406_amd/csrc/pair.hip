@@ -241,20 +241,21 @@ __device__ __forceinline__ int stage_tile(const int32_t* __restrict__ ent, int l
 }
 
 // Pairs of this lane's stream with the entries [a, b) of a staged tile
-// (entries a + st, a + st + S, ...).  The unrolled loop runs while all
-// streams have four entries left, so its trip count is the same for every
-// lane.
+// (entries a + st, a + st + S, ...).  The unrolled loop takes U entries
+// per stream (8 for the shorter far pairs, 4 for near pairs) while all
+// streams have U left, so its trip count is the same for every lane.
 template <class T, class V4, int S, bool NEAR>
 __device__ __forceinline__ void force_segment(const V4* tile, int a, int b, int st, T xi, T yi, T zi,
                                               const Coef<T>& c, T& fx, T& fy, T& fz) {
+    constexpr int U = NEAR ? 4 : 8;
     const V4* tp = tile + a + st;
     int kk = a;
-    for (; kk + 4 * S <= b; kk += 4 * S, tp += 4 * S) {
-        const V4 p0 = tp[0], p1 = tp[S], p2 = tp[2 * S], p3 = tp[3 * S];
-        pair_force<T, V4, NEAR>(p0, xi, yi, zi, c, fx, fy, fz);
-        pair_force<T, V4, NEAR>(p1, xi, yi, zi, c, fx, fy, fz);
-        pair_force<T, V4, NEAR>(p2, xi, yi, zi, c, fx, fy, fz);
-        pair_force<T, V4, NEAR>(p3, xi, yi, zi, c, fx, fy, fz);
+    for (; kk + U * S <= b; kk += U * S, tp += U * S) {
+        V4 pp[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) pp[u] = tp[u * S];
+#pragma unroll
+        for (int u = 0; u < U; ++u) pair_force<T, V4, NEAR>(pp[u], xi, yi, zi, c, fx, fy, fz);
     }
     for (int k = kk + st; k < b; k += S, tp += S) pair_force<T, V4, NEAR>(tp[0], xi, yi, zi, c, fx, fy, fz);
 }
@@ -333,7 +334,7 @@ __device__ __forceinline__ void force_group(const GroupArgs& ga, const Src& src,
 
 // Streams per group: the largest of 1, 2, 3, 4, 8 with S * N_i <= 64.
 template <class T>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 4))) void k_force(GroupArgs ga, Src src, Coef<T> c, double G, double* __restrict__ ax,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_force(GroupArgs ga, Src src, Coef<T> c, double G, double* __restrict__ ax,
                                               double* __restrict__ ay, double* __restrict__ az, int64_t os) {
     using V4 = typename Vec4<T>::type;
     __shared__ V4 tile[kTile];
@@ -351,30 +352,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
 // For a pair (target i with weight w, source of mass mu at offset d):
 //   V = J(d) w = phi w + psi (d . w) d,  psi = phi'(r) / r,
 //   dL/dx_i -= mu V,   dL/dy_src += mu V,   dL/dmu_src += phi (d . w).
-// phi = s^-3 g, psi = s^-3 (k^2 g'(xi)/xi - 3 s^-2 g), s^2 = r^2 + eps^2.
-template <class T>
-struct PairJ {
-    T vx, vy, vz, fw;
-};
-
-// `self` marks the pair of a particle with itself, which the force sum
-// (over j != i) leaves out: its inverse distance is set to 0, so phi and
-// psi vanish.  Without NEAR the source lies at xi >= 1 from the target
-// (never the target itself) and only the [1,2] forms of g and g' are taken.
-template <class T, class V4, bool NEAR = true>
-__device__ __forceinline__ PairJ<T> pair_jac(const V4& p, T xi, T yi, T zi, T wx, T wy, T wz, const Coef<T>& c,
-                                             bool self) {
-    const T dx = p.x - xi, dy = p.y - yi, dz = p.z - zi;
-    const T r2 = fma_(dz, dz, fma_(dy, dy, dx * dx));
-    const T rinv = (NEAR && self) ? T(0) : rsqrt_(r2 + c.eps2);
-    const T r = sqrt_(r2);
+// A self pair (the target itself in its list; the force sum is over j != i)
+// gets s^-1 = 0, so phi and psi vanish.
+// phi = s^-3 g and psi = phi'(r) / r = s^-3 (h - 3 s^-2 g), h = k^2 g'(xi)/xi,
+// from r^2, r and s^-1 (s^2 = r^2 + eps^2).  Without NEAR the source lies
+// at xi >= 1 from the target and only the [1,2] forms of g and g' are taken.
+template <class T, bool NEAR>
+__device__ __forceinline__ void jac_coefs(T r2, T r, T rinv, const Coef<T>& c, T& phi, T& psi) {
     const T u = rinv * rinv;
     const T s3 = u * rinv;
-    T phi, psi;
     if (NEAR) {
         T t;
         const T g = cutoff_g(r, r2, c, t);
-        // h = k^2 g'(xi) / xi on each branch (no division by r needed)
+        // h on each branch (no division by r needed)
         T v = fma_(r, c.C6, c.C5);
         v = fma_(r, v, c.C4);
         v = fma_(r, v, c.C3);
@@ -387,21 +377,13 @@ __device__ __forceinline__ PairJ<T> pair_jac(const V4& p, T xi, T yi, T zi, T wx
         psi = s3 * fma_(c.m3 * u, g, h);
     } else {
         // g = t^4 (t R), h = -t^4 P; with a = s^-3 t^4:
-        // phi = a (t R), psi = s^-3 (h - 3 u g) = -3 u phi - a P
+        // phi = a (t R), psi = -3 u phi - a P
         const T t = sat_(fma_(r, -c.k, T(2)));
         const T R = fma_(fma_(fma_(r, c.R3, c.R2), r, c.R1), r, c.R0);
         const T a = s3 * ((t * t) * (t * t));
         phi = a * (t * R);
         psi = fma_(c.m3 * u, phi, -(a * fma_(r2, c.E2, fma_(r, c.E1, c.E0))));
     }
-    const T dw = fma_(dz, wz, fma_(dy, wy, dx * wx));
-    const T s = psi * dw;
-    PairJ<T> o;
-    o.vx = fma_(phi, wx, s * dx);
-    o.vy = fma_(phi, wy, s * dy);
-    o.vz = fma_(phi, wz, s * dz);
-    o.fw = phi * dw;
-    return o;
 }
 
 struct AdjOut {
@@ -455,7 +437,9 @@ __device__ __forceinline__ double row16_sum(double v) {
 template <class T, int NB>
 struct Targets {
     T x[NB], y[NB], z[NB], wx[NB], wy[NB], wz[NB];
-    T fx[NB], fy[NB], fz[NB];
+    // i-side partial sums over the tile: A = sum mu phi, B = sum mu psi (d . w) d,
+    // so that -sum mu V = -(A w + B)
+    T A[NB], Bx[NB], By[NB], Bz[NB];
     int32_t id[NB];     // sorted particle index, for the self test
 };
 
@@ -475,32 +459,42 @@ __device__ __forceinline__ void adjoint_entries(int a, int b, const V4* tile, co
         T jx, jy, jz, jm;
 #pragma unroll
         for (int ib = 0; ib < NB; ++ib) {
-            const PairJ<T> j = pair_jac<T, V4, NEAR>(p, tg.x[ib], tg.y[ib], tg.z[ib], tg.wx[ib], tg.wy[ib], tg.wz[ib],
-                                                     c, NEAR && v == tg.id[ib]);
-            tg.fx[ib] = fma_(-p.w, j.vx, tg.fx[ib]);
-            tg.fy[ib] = fma_(-p.w, j.vy, tg.fy[ib]);
-            tg.fz[ib] = fma_(-p.w, j.vz, tg.fz[ib]);
+            const T dx = p.x - tg.x[ib], dy = p.y - tg.y[ib], dz = p.z - tg.z[ib];
+            const T r2 = fma_(dz, dz, fma_(dy, dy, dx * dx));
+            const T rinv = (NEAR && v == tg.id[ib]) ? T(0) : rsqrt_(r2 + c.eps2);
+            const T r = sqrt_(r2);
+            T phi, psi;
+            jac_coefs<T, NEAR>(r2, r, rinv, c, phi, psi);
+            const T dw = fma_(dz, tg.wz[ib], fma_(dy, tg.wy[ib], dx * tg.wx[ib]));
+            const T s = psi * dw;
+            const T ms = p.w * s;
+            tg.A[ib] = fma_(p.w, phi, tg.A[ib]);
+            tg.Bx[ib] = fma_(ms, dx, tg.Bx[ib]);
+            tg.By[ib] = fma_(ms, dy, tg.By[ib]);
+            tg.Bz[ib] = fma_(ms, dz, tg.Bz[ib]);
+            // j-side: V = phi w + s d and phi (d . w), summed over the targets
             if (ib == 0) {
-                jx = j.vx;
-                jy = j.vy;
-                jz = j.vz;
-                jm = j.fw;
+                jx = fma_(s, dx, phi * tg.wx[ib]);
+                jy = fma_(s, dy, phi * tg.wy[ib]);
+                jz = fma_(s, dz, phi * tg.wz[ib]);
+                jm = phi * dw;
             } else {
-                jx += j.vx;
-                jy += j.vy;
-                jz += j.vz;
-                jm += j.fw;
+                jx = fma_(s, dx, fma_(phi, tg.wx[ib], jx));
+                jy = fma_(s, dy, fma_(phi, tg.wy[ib], jy));
+                jz = fma_(s, dz, fma_(phi, tg.wz[ib], jz));
+                jm = fma_(phi, dw, jm);
             }
         }
         jx = row16_sum(jx);
         jy = row16_sum(jy);
         jz = row16_sum(jz);
         jm = row16_sum(jm);
-        if (valid && ra < 4) {
-            // component ra of (mu V_x, mu V_y, mu V_z, sum phi (d . w))
-            const T lo = (ra & 1) ? jy : jx;
-            const T hi = (ra & 1) ? jm : jz;
-            const T val = ((ra & 2) ? hi : lo) * (ra == 3 ? T(1) : p.w);
+        // component ra of (mu V_x, mu V_y, mu V_z, sum phi (d . w)); a zero
+        // (every pair of the entry beyond r_cut) is not added
+        const T lo = (ra & 1) ? jy : jx;
+        const T hi = (ra & 1) ? jm : jz;
+        const T val = ((ra & 2) ? hi : lo) * (ra == 3 ? T(1) : p.w);
+        if (valid && ra < 4 && val != T(0)) {
             // the four components of one source are adjacent (one 32-byte line)
             double* dst = v >= 0 ? out.gj + 4 * (int64_t)v + ra : out.gn + 4 * (int64_t)(-v - 1) + ra;
             unsafeAtomicAdd(dst, (double)val);
@@ -549,15 +543,15 @@ __device__ __forceinline__ void adjoint_group(const GroupArgs& ga, const Src& sr
         const int nnear = stage_tile<T, V4, kRows>(ga.ent + tb, len, src, cx, cy, cz, hx, hy, hz, c0.far2, tile, ids);
         __syncthreads();
 #pragma unroll
-        for (int ib = 0; ib < NB; ++ib) tg.fx[ib] = tg.fy[ib] = tg.fz[ib] = T(0);
+        for (int ib = 0; ib < NB; ++ib) tg.A[ib] = tg.Bx[ib] = tg.By[ib] = tg.Bz[ib] = T(0);
         adjoint_entries<T, V4, NB, true>(0, nnear, tile, ids, lane, tg, c, out);
         adjoint_entries<T, V4, NB, false>(nnear, len, tile, ids, lane, tg, c, out);
         // FP32 tile partials into this lane's FP64 slots
 #pragma unroll
         for (int ib = 0; ib < NB; ++ib) {
-            ired[(ib * 64 + lane) * 3 + 0] += (double)tg.fx[ib];
-            ired[(ib * 64 + lane) * 3 + 1] += (double)tg.fy[ib];
-            ired[(ib * 64 + lane) * 3 + 2] += (double)tg.fz[ib];
+            ired[(ib * 64 + lane) * 3 + 0] -= (double)fma_(tg.A[ib], tg.wx[ib], tg.Bx[ib]);
+            ired[(ib * 64 + lane) * 3 + 1] -= (double)fma_(tg.A[ib], tg.wy[ib], tg.By[ib]);
+            ired[(ib * 64 + lane) * 3 + 2] -= (double)fma_(tg.A[ib], tg.wz[ib], tg.Bz[ib]);
         }
     }
     __syncthreads();

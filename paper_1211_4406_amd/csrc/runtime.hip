@@ -122,6 +122,11 @@ void fill_f64(double* p, double v, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, p, v, n);
     SRF_HIP(hipGetLastError());
 }
+void fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, p, v, n);
+    SRF_HIP(hipGetLastError());
+}
 
 // ------------------------------------------------------------------- scan
 // Blocks of 256 threads scan 2048 consecutive values (8 per thread); block
