@@ -80,6 +80,39 @@ __device__ __forceinline__ int classify(const Cell& k, const Frame& f, double rc
     return k.leaf ? 2 : 3;
 }
 
+// Items of one group pass through a 16-slot LDS buffer of the thread and go
+// to memory as aligned 64-byte chunks (the partial chunks at the two ends of
+// a group's items are written item by item), so that the item array is
+// written in whole lines rather than by scattered 4-byte stores.
+constexpr int kWc = 16;          // items per chunk
+constexpr int kWcStride = 17;    // LDS slots per thread (padding against bank conflicts)
+
+struct ItemWriter {
+    int32_t* buf;      // this thread's LDS slots
+    int32_t* dst;      // the item array
+    int64_t start;     // index of the group's first item
+    int64_t pos;       // index of the next item
+    __device__ __forceinline__ void put(int32_t v) {
+        buf[pos & (kWc - 1)] = v;
+        ++pos;
+        if ((pos & (kWc - 1)) == 0) {
+            const int64_t c0 = pos - kWc;
+            if (c0 >= start) {
+                int4* d = reinterpret_cast<int4*>(dst + c0);
+#pragma unroll
+                for (int k = 0; k < kWc / 4; ++k) d[k] = make_int4(buf[4 * k], buf[4 * k + 1], buf[4 * k + 2], buf[4 * k + 3]);
+            } else {
+                for (int64_t k = start; k < pos; ++k) dst[k] = buf[k & (kWc - 1)];
+            }
+        }
+    }
+    __device__ __forceinline__ void finish() {
+        int64_t k = pos & ~(int64_t)(kWc - 1);
+        if (k < start) k = start;
+        for (; k < pos; ++k) dst[k] = buf[k & (kWc - 1)];
+    }
+};
+
 // One thread walks the cell array once for G consecutive groups.  A cell
 // is visited while at least one of them opened its parent; mask[L] (G bits
 // per level, packed in one 64-bit word) holds the groups that opened the
@@ -94,19 +127,21 @@ __global__ __launch_bounds__(128) void k_lists(int64_t ng, const double* __restr
     static_assert(G * kLevels <= 64, "level masks must fit one word");
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t g0 = t * G;
+    __shared__ int32_t wbuf[WRITE ? 128 * G * kWcStride : 1];
     Frame f[G];
     int64_t np[G], nc[G], w[G];
-    int32_t* out[G];
+    ItemWriter out[G];
     uint64_t valid = 0;
 #pragma unroll
     for (int q = 0; q < G; ++q) {
         np[q] = nc[q] = w[q] = 0;
-        out[q] = nullptr;
         const int64_t g = g0 + q < ng ? g0 + q : ng - 1;
         f[q] = group_frame(glo, ghi, g);
-        if (g0 + q < ng) {
-            valid |= 1ull << q;
-            if (WRITE) out[q] = items + ioff[g];
+        if (g0 + q < ng) valid |= 1ull << q;
+        if (WRITE) {
+            out[q].buf = wbuf + (threadIdx.x * G + q) * kWcStride;
+            out[q].dst = items;
+            out[q].start = out[q].pos = ioff[g];
         }
     }
     const uint64_t full = (1ull << G) - 1ull;
@@ -124,11 +159,11 @@ __global__ __launch_bounds__(128) void k_lists(int64_t ng, const double* __restr
                 if (cls == 3) {
                     open |= 1ull << q;
                 } else if (cls == 1) {
-                    if (WRITE) out[q][w[q]++] = -(int32_t)i - 1;
+                    if (WRITE) out[q].put(-(int32_t)i - 1);
                     else ++nc[q];
                 } else if (cls == 2) {
                     if (WRITE) {
-                        out[q][w[q]++] = (int32_t)i;
+                        out[q].put((int32_t)i);
                     } else {
                         uint32_t m = k.count;
                         if (m == kPackCountMax) m = (uint32_t)rng[i].count;
@@ -146,7 +181,12 @@ __global__ __launch_bounds__(128) void k_lists(int64_t ng, const double* __restr
             i = k.skip;
         }
     }
-    if (WRITE) return;
+    if (WRITE) {
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+            if ((valid >> q) & 1ull) out[q].finish();
+        return;
+    }
     unsigned long long a = 0, b = 0, c = 0;
 #pragma unroll
     for (int q = 0; q < G; ++q) {
@@ -215,7 +255,7 @@ __global__ __launch_bounds__(64) void k_expand(int64_t ng, const int64_t* __rest
     }
 }
 
-constexpr int kGroupsPerThread = 2;
+constexpr int kGroupsPerThread = 1;
 
 }  // namespace
 
