@@ -57,7 +57,8 @@ enum srf_precision {
 
 /* Parameters.  Valid ranges (else SRF_EINVAL):
  *   G finite; 0 < r_cut < 0.25; eps > 0 and finite; 0 <= theta <= 1;
- *   1 <= n_group <= 64; 1 <= n_leaf <= n_group; precision in srf_precision. */
+ *   1 <= n_group <= 64; 1 <= n_leaf <= n_group; precision in srf_precision;
+ *   compensated in {0, 1}. */
 typedef struct {
     double G;            /* gravitational constant                                  */
     double r_cut;        /* cutoff radius, box units (box side = 1)                 */
@@ -66,7 +67,9 @@ typedef struct {
     int32_t n_group;     /* maximum particles per group                             */
     int32_t n_leaf;      /* a cell with more particles is split (down to level 21)  */
     int32_t precision;   /* enum srf_precision (force and adjoint kernels)          */
-    int32_t reserved;    /* must be 0                                               */
+    int32_t compensated; /* 1: compensated (Kahan) FP32 partial sums over each list
+                            tile of the SRF_FP32_REL force kernel; 0: plain FP32.
+                            No effect on the FP64 kernel or on the adjoint.       */
 } srf_params;
 
 typedef struct srf_tree srf_tree;

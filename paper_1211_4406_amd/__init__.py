@@ -41,7 +41,7 @@ class SrfError(RuntimeError):
 
 class _CParams(C.Structure):
     _fields_ = [("G", C.c_double), ("r_cut", C.c_double), ("eps", C.c_double), ("theta", C.c_double),
-                ("n_group", C.c_int32), ("n_leaf", C.c_int32), ("precision", C.c_int32), ("reserved", C.c_int32)]
+                ("n_group", C.c_int32), ("n_leaf", C.c_int32), ("precision", C.c_int32), ("compensated", C.c_int32)]
 
 
 @dataclass(frozen=True)
@@ -54,16 +54,18 @@ class Params:
     n_group: int = 64
     n_leaf: int = 16
     precision: int = FP32_REL
+    compensated: int = 0
 
     def c(self) -> _CParams:
         return _CParams(float(self.G), float(self.r_cut), float(self.eps), float(self.theta), int(self.n_group),
-                        int(self.n_leaf), int(self.precision), 0)
+                        int(self.n_leaf), int(self.precision), int(self.compensated))
 
     @staticmethod
-    def of(p, precision: int | None = None) -> "Params":
+    def of(p, precision: int | None = None, compensated: int | None = None) -> "Params":
         """Convert any object with G, r_cut, eps, theta, n_group, n_leaf."""
         prec = getattr(p, "precision", FP32_REL) if precision is None else precision
-        return Params(p.G, p.r_cut, p.eps, p.theta, p.n_group, p.n_leaf, prec)
+        comp = getattr(p, "compensated", 0) if compensated is None else compensated
+        return Params(p.G, p.r_cut, p.eps, p.theta, p.n_group, p.n_leaf, prec, comp)
 
 
 _lib = None

@@ -47,7 +47,7 @@ void validate(const srf_params* p) {
     if (p->n_group < 1 || p->n_group > 64) srf::fail(SRF_EINVAL, "n_group must lie in [1, 64]");
     if (p->n_leaf < 1 || p->n_leaf > p->n_group) srf::fail(SRF_EINVAL, "n_leaf must lie in [1, n_group]");
     if (p->precision != SRF_FP32_REL && p->precision != SRF_FP64) srf::fail(SRF_EINVAL, "unknown precision");
-    if (p->reserved != 0) srf::fail(SRF_EINVAL, "reserved must be 0");
+    if (p->compensated != 0 && p->compensated != 1) srf::fail(SRF_EINVAL, "compensated must be 0 or 1");
 }
 
 void check_pair(const srf_tree* t, const srf_lists* l, const srf_params* p) {

@@ -130,12 +130,41 @@ __device__ __forceinline__ T cutoff_g(T r, T r2, const Coef<T>& c, T& t) {
     return r2 < c.rh2 ? g1 : g2;
 }
 
+// FP32 partial sums of one target over a tile.  With COMP each component
+// carries a Kahan compensation term (sum = a - c).
+template <class T, bool COMP>
+struct Acc {
+    T x = 0, y = 0, z = 0;
+    T cx = 0, cy = 0, cz = 0;
+    __device__ __forceinline__ static void add1(T& a, T& c, T v) {
+        if (COMP) {
+            const T y = v - c;
+            const T t = a + y;
+            c = (t - a) - y;
+            a = t;
+        } else {
+            a += v;
+        }
+    }
+    __device__ __forceinline__ void add(T f, T dx, T dy, T dz) {
+        if (COMP) {
+            add1(x, cx, f * dx);
+            add1(y, cy, f * dy);
+            add1(z, cz, f * dz);
+        } else {
+            x = fma_(f, dx, x);
+            y = fma_(f, dy, y);
+            z = fma_(f, dz, z);
+        }
+    }
+};
+
 // Force of one source (offset p.xyz, mass p.w) on one target (xi, yi, zi),
-// accumulated into (ax, ay, az).  NEAR selects the full cutoff function;
-// otherwise the source lies at xi >= 1 from the target, g = t^5 R, and the
-// factor m s^-3 t^5 R is formed as m (q^2)(q t)(t R) with q = t s^-1.
-template <class T, class V4, bool NEAR = true>
-__device__ __forceinline__ void pair_force(const V4& p, T xi, T yi, T zi, const Coef<T>& c, T& ax, T& ay, T& az) {
+// accumulated into acc.  NEAR selects the full cutoff function; otherwise
+// the source lies at xi >= 1 from the target, g = t^5 R, and the factor
+// m s^-3 t^5 R is formed as m (q^2)(q t)(t R) with q = t s^-1.
+template <class T, class V4, bool NEAR, bool COMP>
+__device__ __forceinline__ void pair_force(const V4& p, T xi, T yi, T zi, const Coef<T>& c, Acc<T, COMP>& acc) {
     const T dx = p.x - xi, dy = p.y - yi, dz = p.z - zi;
     const T r2 = fma_(dz, dz, fma_(dy, dy, dx * dx));
     const T rinv = rsqrt_(r2 + c.eps2);
@@ -151,9 +180,7 @@ __device__ __forceinline__ void pair_force(const V4& p, T xi, T yi, T zi, const 
         const T q = t * rinv;
         f = p.w * ((q * q) * ((q * t) * (t * R)));
     }
-    ax = fma_(f, dx, ax);
-    ay = fma_(f, dy, ay);
-    az = fma_(f, dz, az);
+    acc.add(f, dx, dy, dz);
 }
 
 // ------------------------------------------------------------ tile loading
@@ -244,9 +271,9 @@ __device__ __forceinline__ int stage_tile(const int32_t* __restrict__ ent, int l
 // (entries a + st, a + st + S, ...).  The unrolled loop takes U entries
 // per stream (8 for the shorter far pairs, 4 for near pairs) while all
 // streams have U left, so its trip count is the same for every lane.
-template <class T, class V4, int S, bool NEAR>
+template <class T, class V4, int S, bool NEAR, bool COMP>
 __device__ __forceinline__ void force_segment(const V4* tile, int a, int b, int st, T xi, T yi, T zi,
-                                              const Coef<T>& c, T& fx, T& fy, T& fz) {
+                                              const Coef<T>& c, Acc<T, COMP>& acc) {
     constexpr int U = NEAR ? 4 : 8;
     const V4* tp = tile + a + st;
     int kk = a;
@@ -255,9 +282,9 @@ __device__ __forceinline__ void force_segment(const V4* tile, int a, int b, int 
 #pragma unroll
         for (int u = 0; u < U; ++u) pp[u] = tp[u * S];
 #pragma unroll
-        for (int u = 0; u < U; ++u) pair_force<T, V4, NEAR>(pp[u], xi, yi, zi, c, fx, fy, fz);
+        for (int u = 0; u < U; ++u) pair_force<T, V4, NEAR, COMP>(pp[u], xi, yi, zi, c, acc);
     }
-    for (int k = kk + st; k < b; k += S, tp += S) pair_force<T, V4, NEAR>(tp[0], xi, yi, zi, c, fx, fy, fz);
+    for (int k = kk + st; k < b; k += S, tp += S) pair_force<T, V4, NEAR, COMP>(tp[0], xi, yi, zi, c, acc);
 }
 
 // Workgroups are handed to the 8 XCDs (each with its own L2) round-robin
@@ -278,7 +305,7 @@ struct GroupArgs {
 };
 
 // ------------------------------------------------------------------ force
-template <class T, int S>
+template <class T, int S, bool COMP>
 __device__ __forceinline__ void force_group(const GroupArgs& ga, const Src& src, const Coef<T>& c0, double G,
                                             double* __restrict__ ax, double* __restrict__ ay,
                                             double* __restrict__ az, int64_t os, int64_t g, int32_t first,
@@ -303,14 +330,14 @@ __device__ __forceinline__ void force_group(const GroupArgs& ga, const Src& src,
         __syncthreads();
         const int nnear = stage_tile<T, V4>(ga.ent + tb, len, src, cx, cy, cz, hx, hy, hz, c0.far2, tile, nullptr);
         __syncthreads();
-        T fx = 0, fy = 0, fz = 0;
+        Acc<T, COMP> acc;
         if (active) {
-            force_segment<T, V4, S, true>(tile, 0, nnear, st, xi, yi, zi, c, fx, fy, fz);
-            force_segment<T, V4, S, false>(tile, nnear, len, st, xi, yi, zi, c, fx, fy, fz);
+            force_segment<T, V4, S, true, COMP>(tile, 0, nnear, st, xi, yi, zi, c, acc);
+            force_segment<T, V4, S, false, COMP>(tile, nnear, len, st, xi, yi, zi, c, acc);
         }
-        sx += (double)fx;
-        sy += (double)fy;
-        sz += (double)fz;
+        sx += COMP ? (double)acc.x - (double)acc.cx : (double)acc.x;
+        sy += COMP ? (double)acc.y - (double)acc.cy : (double)acc.y;
+        sz += COMP ? (double)acc.z - (double)acc.cz : (double)acc.z;
     }
     red[lane * 3 + 0] = sx;
     red[lane * 3 + 1] = sy;
@@ -333,19 +360,20 @@ __device__ __forceinline__ void force_group(const GroupArgs& ga, const Src& src,
 }
 
 // Streams per group: the largest of 1, 2, 3, 4, 8 with S * N_i <= 64.
-template <class T>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_force(GroupArgs ga, Src src, Coef<T> c, double G, double* __restrict__ ax,
-                                              double* __restrict__ ay, double* __restrict__ az, int64_t os) {
+template <class T, bool COMP>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_force(
+    GroupArgs ga, Src src, Coef<T> c, double G, double* __restrict__ ax, double* __restrict__ ay,
+    double* __restrict__ az, int64_t os) {
     using V4 = typename Vec4<T>::type;
     __shared__ V4 tile[kTile];
     __shared__ double red[64 * 3];
     const int64_t g = xcd_group(blockIdx.x, gridDim.x);
     const int32_t first = ga.gfirst[g], cnt = ga.gcount[g];
-    if (cnt > 32) force_group<T, 1>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
-    else if (cnt > 21) force_group<T, 2>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
-    else if (cnt > 16) force_group<T, 3>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
-    else if (cnt > 8) force_group<T, 4>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
-    else force_group<T, 8>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
+    if (cnt > 32) force_group<T, 1, COMP>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
+    else if (cnt > 21) force_group<T, 2, COMP>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
+    else if (cnt > 16) force_group<T, 3, COMP>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
+    else if (cnt > 8) force_group<T, 4, COMP>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
+    else force_group<T, 8, COMP>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
 }
 
 // ---------------------------------------------------------------- adjoint
@@ -678,11 +706,14 @@ void launch_force(const Tree& t, const Lists& l, const srf_params& p, double* ax
     const int64_t ng = t.n_groups;
     if (ev0) SRF_HIP(hipEventRecord(ev0, st));
     if (p.precision == SRF_FP64) {
-        hipLaunchKernelGGL(k_force<double>, dim3((unsigned)ng), dim3(64), 0, st, group_args(t, l), src_args(t),
-                           make_coef<double>(p.r_cut, p.eps), p.G, ax, ay, az, os);
+        hipLaunchKernelGGL((k_force<double, false>), dim3((unsigned)ng), dim3(64), 0, st, group_args(t, l),
+                           src_args(t), make_coef<double>(p.r_cut, p.eps), p.G, ax, ay, az, os);
+    } else if (p.compensated) {
+        hipLaunchKernelGGL((k_force<float, true>), dim3((unsigned)ng), dim3(64), 0, st, group_args(t, l),
+                           src_args(t), make_coef<float>(p.r_cut, p.eps), p.G, ax, ay, az, os);
     } else {
-        hipLaunchKernelGGL(k_force<float>, dim3((unsigned)ng), dim3(64), 0, st, group_args(t, l), src_args(t),
-                           make_coef<float>(p.r_cut, p.eps), p.G, ax, ay, az, os);
+        hipLaunchKernelGGL((k_force<float, false>), dim3((unsigned)ng), dim3(64), 0, st, group_args(t, l),
+                           src_args(t), make_coef<float>(p.r_cut, p.eps), p.G, ax, ay, az, os);
     }
     SRF_HIP(hipGetLastError());
     if (ev1) SRF_HIP(hipEventRecord(ev1, st));

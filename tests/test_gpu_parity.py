@@ -177,6 +177,31 @@ def test_edge_cases():
         assert s32["l2"] <= 1e-5 and s32["median"] <= 1e-5
 
 
+def test_compensated_force_option():
+    """compensated = 1 selects Kahan FP32 partial sums over each tile: the
+    result stays within the FP32 tolerance, is no less accurate than plain
+    FP32 sums, and is not the plain path's result."""
+    ps = case_sets()["clustered-20000"]
+    say(f"[gpu] compensated FP32 partials n={ps.n}")
+    ot = oracle.OracleTree(ps.x, ps.y, ps.z, ps.m, ps.params)
+    ref = ot.force()
+    x, m = dev_inputs(ps)
+    p0 = srf.Params.of(ps.params, srf.FP32_REL, 0)
+    p1 = srf.Params.of(ps.params, srf.FP32_REL, 1)
+    tree = srf.tree_build(x, m, p0)
+    lists = srf.make_lists(tree, p0)
+    a0 = srf.short_range_force(tree, lists, p0).cpu().numpy()
+    a1 = srf.short_range_force(tree, lists, p1).cpu().numpy()
+    s0, s1 = rel_stats(a0, ref), rel_stats(a1, ref)
+    say(f"    plain: {s0}\n    compensated: {s1}")
+    assert s1["rms"] <= FP32_TOL and s0["rms"] <= FP32_TOL
+    assert s1["rms"] <= 1.05 * s0["rms"]
+    assert not np.array_equal(a0, a1)
+    with pytest.raises(srf.SrfError) as e:
+        srf.short_range_force(tree, lists, srf.Params.of(ps.params, srf.FP32_REL, 2))
+    assert e.value.status == -1
+
+
 def test_domain_errors_reported():
     p = srf.Params(r_cut=0.1, eps=1e-3)
     x = torch.rand((100, 3), dtype=torch.float64, device="cuda")

@@ -69,7 +69,11 @@ def forward_accuracy(k, theta):
     sel = np.arange(ps.n) if ps.n <= 4096 else np.sort(rng.choice(ps.n, 3000, replace=False))
     bf = oracle.brute_force_sel(ps.x, ps.y, ps.z, ps.m, ps.params.G, ps.params.r_cut, ps.params.eps, sel)
     _, st_tree = oracle.relative_errors(a32[sel], bf)
+    # momentum: not conserved by the tree for theta > 0 (accepted cells act
+    # on targets without the reverse action); reported, not bounded
+    mom = float(np.linalg.norm((ps.m[:, None] * a32).sum(0)) / np.sum(ps.m * np.linalg.norm(a32, axis=1)))
     rec = dict(workload=k, name=ps.name, n=ps.n, theta=ps.params.theta, interactions=info["interactions"],
+               momentum_residual=mom,
                n_groups=info["n_groups"], mean_Ni=ps.n / info["n_groups"],
                mean_Nj=(info["n_particle_entries"] + info["n_node_entries"]) / info["n_groups"],
                fp32_vs_same_list=s32, fp64_vs_same_list=s64,

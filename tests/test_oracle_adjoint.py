@@ -127,3 +127,51 @@ def test_two_particle_gradient():
     v = m[1] * w[0] - m[0] * w[1]
     jv = oracle.pair_jac(d, v, rc, eps)
     assert np.allclose(gx[1], jv, rtol=1e-13) and np.allclose(gx[0], -jv, rtol=1e-13)
+
+
+def _same_structure(a, b):
+    if not np.array_equal(a.perm, b.perm):
+        return False
+    for k in ("level", "prefix", "first", "count"):
+        if not np.array_equal(getattr(a.tree, k), getattr(b.tree, k)):
+            return False
+    if not (np.array_equal(a.gfirst, b.gfirst) and np.array_equal(a.gcount, b.gcount)):
+        return False
+    return all(np.array_equal(getattr(a.lists, k), getattr(b.lists, k)) for k in ("poff", "pidx", "noff", "nidx"))
+
+
+def test_finite_differences_with_structure_rebuilt():
+    """Central differences with the whole structure rebuilt from the moved
+    positions (sort, cells, groups, lists): where the structure of both moved
+    sets equals the original one the result is the fixed-structure gradient;
+    the steps that change it (list flips) are counted and must be rare.  The
+    forces are differenced before the dot product with w, and the error is
+    taken relative to max(|dL/dx_k|, rms of dL/dx) (the rebuilt group boxes
+    move the group-relative coordinates at the rounding level)."""
+    ps, w = _set()
+    ot = oracle.OracleTree(ps.x, ps.y, ps.z, ps.m, ps.params)
+    gx, _ = ot.adjoint(w)
+    rms = float(np.sqrt(np.mean(gx ** 2)))
+    X = np.stack([ps.x, ps.y, ps.z], axis=1)
+    rng = np.random.default_rng(11)
+    h = 1e-6
+    errs, flips, total = [], 0, 0
+    for k in rng.choice(ps.n, 24, replace=False):
+        for a in range(3):
+            forces, same = [], True
+            for sgn in (1.0, -1.0):
+                Y = X.copy()
+                Y[k, a] += sgn * h
+                o2 = oracle.OracleTree(Y[:, 0], Y[:, 1], Y[:, 2], ps.m, ps.params)
+                same = same and _same_structure(ot, o2)
+                forces.append(o2.force())
+            total += 1
+            if not same:
+                flips += 1
+                continue
+            fd = float(np.sum(w * (forces[0] - forces[1]))) / (2 * h)
+            errs.append(abs(fd - gx[k, a]) / max(np.abs(gx[k]).max(), rms))
+    print(f"structure changed in {flips} of {total} steps; agreement elsewhere: median {np.median(errs):.2e}, "
+          f"max {max(errs):.2e}")
+    assert flips <= total // 4
+    assert np.median(errs) < 1e-6 and max(errs) < 1e-4
