@@ -228,12 +228,13 @@ def main():
     fpi = FLOPS_ADJOINT if dominant == "adjoint" else FLOPS_FORCE
     achieved = fpi * I / (kd * 1e-3)
     prof = profiled_counters(args.workload, ps.params.theta)
-    kname = f"k_{dominant}<float>"
+    kernel_names = {"force": "k_force<float, false>", "adjoint": "k_adjoint<float>"}
+    kname = kernel_names[dominant]
     traffic = None
     executed = {}
     if prof is not None and prof.get("interactions") == I:
         traffic = prof["kernels"][kname]["hbm_bytes"]
-        for k, tag in (("k_force<float>", "force"), ("k_adjoint<float>", "adjoint")):
+        for tag, k in kernel_names.items():
             fl = prof["kernels"][k]["fp32_flops"]
             executed[tag] = dict(flops_per_interaction=fl / I,
                                  frac=fl / ((kf if tag == "force" else ka) * 1e-3) / PEAK_FP32)

@@ -117,6 +117,17 @@ struct Lists {
     DevBuf<int32_t> ent;       // entries: s >= 0 particle (sorted index), -(c+1) cell c
 };
 
+// Workgroups are handed to the 8 XCDs (each with its own L2) round-robin in
+// launch order.  This maps launch index b of nb to a logical block index so
+// that each XCD runs one contiguous run of logical blocks: for work ordered
+// in space (groups in Morton order) the blocks sharing an L2 are spatial
+// neighbours whose data overlap.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+    const int64_t x = b & 7, y = b >> 3;
+    const int64_t q = nb >> 3, r = nb & 7;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + y;
+}
+
 // ------------------------------------------------------------------ scan
 // Exclusive prefix sum of n int64 values in place on `stream`; returns
 // nothing (the total is out[n] if the caller allocated n+1 entries and

@@ -125,7 +125,7 @@ __global__ __launch_bounds__(128) void k_lists(int64_t ng, const double* __restr
                                                int64_t* __restrict__ icnt, unsigned long long* __restrict__ totals,
                                                const int64_t* __restrict__ ioff, int32_t* __restrict__ items) {
     static_assert(G * kLevels <= 64, "level masks must fit one word");
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int64_t g0 = t * G;
     __shared__ int32_t wbuf[WRITE ? 128 * G * kWcStride : 1];
     Frame f[G];
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(128) void k_lists(int64_t ng, const double* __restr
 __global__ __launch_bounds__(64) void k_expand(int64_t ng, const int64_t* __restrict__ ioff,
                                                const int32_t* __restrict__ items, const NodeRange* __restrict__ rng,
                                                const int64_t* __restrict__ off, int32_t* __restrict__ ent) {
-    const int64_t g = blockIdx.x;
+    const int64_t g = xcd_block(blockIdx.x, gridDim.x);
     if (g >= ng) return;
     const int lane = threadIdx.x;
     const int64_t i0 = ioff[g], i1 = ioff[g + 1];

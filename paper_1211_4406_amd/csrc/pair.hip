@@ -287,15 +287,6 @@ __device__ __forceinline__ void force_segment(const V4* tile, int a, int b, int 
     for (int k = kk + st; k < b; k += S, tp += S) pair_force<T, V4, NEAR, COMP>(tp[0], xi, yi, zi, c, acc);
 }
 
-// Workgroups are handed to the 8 XCDs (each with its own L2) round-robin
-// in launch order.  Give each XCD one contiguous run of groups instead, so
-// that the groups sharing an L2 are spatial neighbours whose lists overlap.
-__device__ __forceinline__ int64_t xcd_group(int64_t b, int64_t nb) {
-    const int64_t x = b & 7, y = b >> 3;
-    const int64_t q = nb >> 3, r = nb & 7;
-    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + y;
-}
-
 struct GroupArgs {
     const int32_t *gfirst, *gcount;
     const double *glo, *ghi;
@@ -367,7 +358,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     using V4 = typename Vec4<T>::type;
     __shared__ V4 tile[kTile];
     __shared__ double red[64 * 3];
-    const int64_t g = xcd_group(blockIdx.x, gridDim.x);
+    const int64_t g = xcd_block(blockIdx.x, gridDim.x);
     const int32_t first = ga.gfirst[g], cnt = ga.gcount[g];
     if (cnt > 32) force_group<T, 1, COMP>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
     else if (cnt > 21) force_group<T, 2, COMP>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
@@ -608,7 +599,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     __shared__ V4 tile[kTile + kRows];
     __shared__ int32_t ids[kTile + kRows];
     __shared__ double ired[4 * 64 * 3];   // per target block and lane: FP64 i-side sums
-    const int64_t g = xcd_group(blockIdx.x, gridDim.x);
+    const int64_t g = xcd_block(blockIdx.x, gridDim.x);
     const int32_t first = ga.gfirst[g], cnt = ga.gcount[g];
     static_assert(kRow * kRows == 64, "one wave is kRows rows of kRow lanes");
     if (cnt > 48)
