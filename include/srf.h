@@ -119,7 +119,8 @@ int srf_short_range_force(const srf_tree* t, const srf_lists* l, const srf_param
  * gradient to member particles through M_c = sum m_k, X_c = sum m_k x_k / M_c.
  * Same parameter rules as srf_short_range_force.  Asynchronous on `stream`;
  * uses FP64 atomics, so the result is reproducible only to rounding.
- * Errors: SRF_EINVAL, SRF_EMISMATCH, SRF_ENOMEM, SRF_EHIP. */
+ * Errors: SRF_EINVAL (also when n + number of cells exceeds 2^31 - 1),
+ * SRF_EMISMATCH, SRF_ENOMEM, SRF_EHIP. */
 int srf_short_range_adjoint(const srf_tree* t, const srf_lists* l, const srf_params* p,
                             const double* wx, const double* wy, const double* wz, int64_t w_stride,
                             double* gx, double* gy, double* gz, int64_t g_stride,

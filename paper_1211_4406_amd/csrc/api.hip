@@ -171,6 +171,8 @@ int srf_short_range_adjoint(const srf_tree* t, const srf_lists* l, const srf_par
         check_pair(t, l, p);
         if (!wx || !wy || !wz || !gx || !gy || !gz || !gm) srf::fail(SRF_EINVAL, "NULL pointer");
         if (w_stride < 1 || g_stride < 1 || gm_stride < 1) srf::fail(SRF_EINVAL, "strides must be >= 1");
+        if (t->t.n + t->t.n_nodes > INT32_MAX)
+            srf::fail(SRF_EINVAL, "the adjoint indexes particles and cells with 32-bit rows: n + n_cells too large");
         hipEvent_t e0, e1;
         timing_events(1, &e0, &e1);
         srf::launch_adjoint(t->t, l->l, *p, wx, wy, wz, w_stride, gx, gy, gz, g_stride, gm, gm_stride,

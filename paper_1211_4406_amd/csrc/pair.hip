@@ -229,13 +229,14 @@ __device__ __forceinline__ V4 load_entry_cls(int32_t v, const Src& s, double cx,
 // [0, n_near)) and far entries after them (filled from the end).  Returns
 // n_near; the order within each class is fixed by the list, so the result
 // is deterministic.  An entry that is one of the group's own particles is
-// near.  `ids`, if given, receives the entries' list values.  The PAD
-// slots after the last entry are set to zero mass at the origin (list value
-// -1), so that a read past the end of a segment stays finite.
+// near.  `ids`, if given, receives each entry's row in the adjoint's
+// source array (particle s -> s, cell c -> n_part + c).  The PAD slots after
+// the last entry are set to zero mass at the origin (row -1), so that a
+// read past the end of a segment stays finite.
 template <class T, class V4, int PAD = 0>
 __device__ __forceinline__ int stage_tile(const int32_t* __restrict__ ent, int len, const Src& src, double cx,
                                           double cy, double cz, double hx, double hy, double hz, double far2,
-                                          V4* tile, int32_t* ids) {
+                                          V4* tile, int32_t* ids, int32_t n_part = 0) {
     const int lane = threadIdx.x;
     if (PAD > 0 && lane < PAD) {
         V4 z;
@@ -259,7 +260,7 @@ __device__ __forceinline__ int stage_tile(const int32_t* __restrict__ ent, int l
         if (valid) {
             const int pos = far ? len - 1 - (nfar + __popcll(mf & lt)) : nnear + __popcll(mn & lt);
             tile[pos] = e;
-            if (ids) ids[pos] = v;
+            if (ids) ids[pos] = v >= 0 ? v : n_part + (-v - 1);
         }
         nnear += __popcll(mn);
         nfar += __popcll(mf);
@@ -407,8 +408,9 @@ __device__ __forceinline__ void jac_coefs(T r2, T r, T rinv, const Coef<T>& c, T
 
 struct AdjOut {
     double *gix, *giy, *giz;            // i-side, sorted order (plain stores)
-    double *gj;                         // j-side on particles: [n][4] = (x, y, z, m), atomics
-    double *gn;                         // j-side on cells: [n_nodes][4], atomics
+    double *gj;                         // j-side, [n + n_nodes][4] = (x, y, z, m), atomics:
+                                        // row s for particle s, row n + c for cell c
+    double *gn;                         // = gj + 4 n, the cell rows
     int64_t n, nn;
 };
 
@@ -515,7 +517,7 @@ __device__ __forceinline__ void adjoint_entries(int a, int b, const V4* tile, co
         const T val = ((ra & 2) ? hi : lo) * (ra == 3 ? T(1) : p.w);
         if (valid && ra < 4 && val != T(0)) {
             // the four components of one source are adjacent (one 32-byte line)
-            double* dst = v >= 0 ? out.gj + 4 * (int64_t)v + ra : out.gn + 4 * (int64_t)(-v - 1) + ra;
+            double* dst = out.gj + (4 * (int64_t)v + ra);
             unsafeAtomicAdd(dst, (double)val);
         }
     }
@@ -559,7 +561,8 @@ __device__ __forceinline__ void adjoint_group(const GroupArgs& ga, const Src& sr
     for (int64_t tb = e0; tb < e1; tb += kTile) {
         const int len = (int)((e1 - tb) < kTile ? (e1 - tb) : kTile);
         __syncthreads();
-        const int nnear = stage_tile<T, V4, kRows>(ga.ent + tb, len, src, cx, cy, cz, hx, hy, hz, c0.far2, tile, ids);
+        const int nnear = stage_tile<T, V4, kRows>(ga.ent + tb, len, src, cx, cy, cz, hx, hy, hz, c0.far2, tile, ids,
+                                                   (int32_t)out.n);
         __syncthreads();
 #pragma unroll
         for (int ib = 0; ib < NB; ++ib) tg.A[ib] = tg.Bx[ib] = tg.By[ib] = tg.Bz[ib] = T(0);
@@ -714,21 +717,20 @@ void launch_adjoint(const Tree& t, const Lists& l, const srf_params& p, const do
                     const double* wz, int64_t ws, double* gx, double* gy, double* gz, int64_t gs, double* gm,
                     int64_t gms, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
     const int64_t n = t.n, nn = t.n_nodes, ng = t.n_groups;
-    DevBuf<double> part(7 * n, st), node(8 * nn, st);
+    DevBuf<double> rows(4 * (n + nn), st), part(3 * n, st), node(4 * nn, st);
     AdjOut o;
-    o.gj = part.get();          // [n][4], 32-byte aligned at the block start
-    o.gix = o.gj + 4 * n;
+    o.gj = rows.get();          // [n + nn][4], 32-byte aligned at the block start
+    o.gn = o.gj + 4 * n;
+    o.gix = part.get();
     o.giy = o.gix + n;
     o.giz = o.giy + n;
-    o.gn = node.get();
     o.n = n;
     o.nn = nn;
-    double* sax = o.gn + 4 * nn;
+    double* sax = node.get();
     double* say = sax + nn;
     double* saz = say + nn;
     double* sb = saz + nn;
-    fill_f64(o.gj, 0.0, 4 * n, st);
-    fill_f64(o.gn, 0.0, 4 * nn, st);
+    fill_f64(o.gj, 0.0, 4 * (n + nn), st);
     if (ev0) SRF_HIP(hipEventRecord(ev0, st));
     if (p.precision == SRF_FP64) {
         hipLaunchKernelGGL(k_adjoint<double>, dim3((unsigned)ng), dim3(64), 0, st, group_args(t, l), src_args(t),
