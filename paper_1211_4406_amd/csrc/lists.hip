@@ -92,10 +92,11 @@ struct ItemWriter {
     int32_t* dst;      // the item array
     int64_t start;     // index of the group's first item
     int64_t pos;       // index of the next item
+    int64_t end;       // capacity limit: items at or past `end` are counted, not stored
     __device__ __forceinline__ void put(int32_t v) {
-        buf[pos & (kWc - 1)] = v;
+        if (pos < end) buf[pos & (kWc - 1)] = v;
         ++pos;
-        if ((pos & (kWc - 1)) == 0) {
+        if ((pos & (kWc - 1)) == 0 && pos <= end) {
             const int64_t c0 = pos - kWc;
             if (c0 >= start) {
                 int4* d = reinterpret_cast<int4*>(dst + c0);
@@ -107,6 +108,7 @@ struct ItemWriter {
         }
     }
     __device__ __forceinline__ void finish() {
+        if (pos > end) return;
         int64_t k = pos & ~(int64_t)(kWc - 1);
         if (k < start) k = start;
         for (; k < pos; ++k) dst[k] = buf[k & (kWc - 1)];
@@ -117,6 +119,13 @@ struct ItemWriter {
 // is visited while at least one of them opened its parent; mask[L] (G bits
 // per level, packed in one 64-bit word) holds the groups that opened the
 // visited cell's parent at level L - 1.
+//
+// The counting walk (WRITE = false) sizes each group's list and also stores
+// its items into a slot of kSlot items per group (items past the slot are
+// counted in totals[3], and the lists are then rebuilt with WRITE = true:
+// a second walk that stores the items of every group compactly at ioff).
+constexpr int64_t kSlot = 2048;
+
 template <int G, bool WRITE>
 __global__ __launch_bounds__(128) void k_lists(int64_t ng, const double* __restrict__ glo,
                                                const double* __restrict__ ghi, const int32_t* __restrict__ gcount,
@@ -127,7 +136,7 @@ __global__ __launch_bounds__(128) void k_lists(int64_t ng, const double* __restr
     static_assert(G * kLevels <= 64, "level masks must fit one word");
     const int64_t t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int64_t g0 = t * G;
-    __shared__ int32_t wbuf[WRITE ? 128 * G * kWcStride : 1];
+    __shared__ int32_t wbuf[128 * G * kWcStride];
     Frame f[G];
     int64_t np[G], nc[G], w[G];
     ItemWriter out[G];
@@ -138,11 +147,10 @@ __global__ __launch_bounds__(128) void k_lists(int64_t ng, const double* __restr
         const int64_t g = g0 + q < ng ? g0 + q : ng - 1;
         f[q] = group_frame(glo, ghi, g);
         if (g0 + q < ng) valid |= 1ull << q;
-        if (WRITE) {
-            out[q].buf = wbuf + (threadIdx.x * G + q) * kWcStride;
-            out[q].dst = items;
-            out[q].start = out[q].pos = ioff[g];
-        }
+        out[q].buf = wbuf + (threadIdx.x * G + q) * kWcStride;
+        out[q].dst = items;
+        out[q].start = out[q].pos = WRITE ? ioff[g] : g * kSlot;
+        out[q].end = WRITE ? INT64_MAX : g * kSlot + kSlot;
     }
     const uint64_t full = (1ull << G) - 1ull;
     uint64_t masks = valid;  // level 0
@@ -159,12 +167,11 @@ __global__ __launch_bounds__(128) void k_lists(int64_t ng, const double* __restr
                 if (cls == 3) {
                     open |= 1ull << q;
                 } else if (cls == 1) {
-                    if (WRITE) out[q].put(-(int32_t)i - 1);
-                    else ++nc[q];
+                    out[q].put(-(int32_t)i - 1);
+                    if (!WRITE) ++nc[q];
                 } else if (cls == 2) {
-                    if (WRITE) {
-                        out[q].put((int32_t)i);
-                    } else {
+                    out[q].put((int32_t)i);
+                    if (!WRITE) {
                         uint32_t m = k.count;
                         if (m == kPackCountMax) m = (uint32_t)rng[i].count;
                         np[q] += m;
@@ -181,13 +188,11 @@ __global__ __launch_bounds__(128) void k_lists(int64_t ng, const double* __restr
             i = k.skip;
         }
     }
-    if (WRITE) {
 #pragma unroll
-        for (int q = 0; q < G; ++q)
-            if ((valid >> q) & 1ull) out[q].finish();
-        return;
-    }
-    unsigned long long a = 0, b = 0, c = 0;
+    for (int q = 0; q < G; ++q)
+        if ((valid >> q) & 1ull) out[q].finish();
+    if (WRITE) return;
+    unsigned long long a = 0, b = 0, c = 0, d = 0;
 #pragma unroll
     for (int q = 0; q < G; ++q) {
         if (!((valid >> q) & 1ull)) continue;
@@ -196,17 +201,20 @@ __global__ __launch_bounds__(128) void k_lists(int64_t ng, const double* __restr
         a += (unsigned long long)np[q];
         b += (unsigned long long)nc[q];
         c += (unsigned long long)gcount[g0 + q] * (unsigned long long)(np[q] + nc[q]);
+        d += (w[q] + nc[q] > kSlot) ? 1ull : 0ull;
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
         a += __shfl_xor(a, o, 64);
         b += __shfl_xor(b, o, 64);
         c += __shfl_xor(c, o, 64);
+        d += __shfl_xor(d, o, 64);
     }
     if ((threadIdx.x & 63) == 0) {
         atomicAdd(&totals[0], a);
         atomicAdd(&totals[1], b);
         atomicAdd(&totals[2], c);
+        if (d) atomicAdd(&totals[3], d);
     }
 }
 
@@ -216,13 +224,17 @@ __global__ __launch_bounds__(128) void k_lists(int64_t ng, const double* __restr
 // item sizes places each item, and the lanes write their items in rounds
 // (round s writes the s-th entry of every item that has one), so a round
 // fills a contiguous stretch of the list.
-__global__ __launch_bounds__(64) void k_expand(int64_t ng, const int64_t* __restrict__ ioff,
-                                               const int32_t* __restrict__ items, const NodeRange* __restrict__ rng,
-                                               const int64_t* __restrict__ off, int32_t* __restrict__ ent) {
+// Items of group g: icnt[g] of them from g * slot when slot > 0, else
+// [ioff[g], ioff[g + 1]).
+__global__ __launch_bounds__(64) void k_expand(int64_t ng, int64_t slot, const int64_t* __restrict__ icnt,
+                                               const int64_t* __restrict__ ioff, const int32_t* __restrict__ items,
+                                               const NodeRange* __restrict__ rng, const int64_t* __restrict__ off,
+                                               int32_t* __restrict__ ent) {
     const int64_t g = xcd_block(blockIdx.x, gridDim.x);
     if (g >= ng) return;
     const int lane = threadIdx.x;
-    const int64_t i0 = ioff[g], i1 = ioff[g + 1];
+    const int64_t i0 = slot > 0 ? g * slot : ioff[g];
+    const int64_t i1 = slot > 0 ? i0 + icnt[g] : ioff[g + 1];
     int64_t base = off[g];
     for (int64_t c0 = i0; c0 < i1; c0 += 64) {
         const int64_t ii = c0 + lane;
@@ -265,7 +277,8 @@ void build_lists(const Tree& t, Lists& l, hipStream_t st) {
     const double th2 = l.theta * l.theta;
     l.n_groups = ng;
     l.off.alloc(ng + 1, st);
-    DevBuf<int64_t> ioff(ng + 1, st);
+    DevBuf<int64_t> icnt(ng + 1, st);
+    DevBuf<int32_t> slots(ng * kSlot > 0 ? ng * kSlot : 1, st);
     DevBuf<unsigned long long> totals(4, st);
     fill_u64(totals.get(), 0ull, 4, st);
     const int B = 128;
@@ -273,31 +286,41 @@ void build_lists(const Tree& t, Lists& l, hipStream_t st) {
     const int64_t nthreads = (ng + G - 1) / G;
     hipLaunchKernelGGL((k_lists<G, false>), dim3(grid_for(nthreads, B, 1 << 30)), dim3(B), 0, st, ng, t.glo.get(),
                        t.ghi.get(), t.gcount.get(), t.pack.get(), t.range.get(), t.n_nodes, rc2, th2, l.off.get(),
-                       ioff.get(), totals.get(), (const int64_t*)nullptr, (int32_t*)nullptr);
+                       icnt.get(), totals.get(), (const int64_t*)nullptr, slots.get());
     SRF_HIP(hipGetLastError());
     exclusive_scan_i64(l.off.get(), ng, true, st);
-    exclusive_scan_i64(ioff.get(), ng, true, st);
-    unsigned long long h[3];
-    int64_t n_items = 0;
-    SRF_HIP(hipMemcpyAsync(h, totals.get(), 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-    SRF_HIP(hipMemcpyAsync(&n_items, ioff.get() + ng, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    unsigned long long h[4];
+    SRF_HIP(hipMemcpyAsync(h, totals.get(), 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     SRF_HIP(hipStreamSynchronize(st));
     l.n_particle_entries = (int64_t)h[0];
     l.n_node_entries = (int64_t)h[1];
     l.n_entries = (int64_t)(h[0] + h[1]);
     l.interactions = (int64_t)h[2];
     l.ent.alloc(l.n_entries > 0 ? l.n_entries : 1, st);
+    if (ng == 0) return;
+    if (h[3] == 0) {
+        // every group's items fit its slot
+        hipLaunchKernelGGL(k_expand, dim3((unsigned)ng), dim3(64), 0, st, ng, kSlot, icnt.get(),
+                           (const int64_t*)nullptr, slots.get(), t.range.get(), l.off.get(), l.ent.get());
+        SRF_HIP(hipGetLastError());
+        return;
+    }
+    // some group has more items than a slot holds: walk again and store
+    // every group's items compactly
+    slots.reset();
+    exclusive_scan_i64(icnt.get(), ng, true, st);
+    int64_t n_items = 0;
+    SRF_HIP(hipMemcpyAsync(&n_items, icnt.get() + ng, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    SRF_HIP(hipStreamSynchronize(st));
     DevBuf<int32_t> items(n_items > 0 ? n_items : 1, st);
     hipLaunchKernelGGL((k_lists<G, true>), dim3(grid_for(nthreads, B, 1 << 30)), dim3(B), 0, st, ng, t.glo.get(),
                        t.ghi.get(), t.gcount.get(), t.pack.get(), t.range.get(), t.n_nodes, rc2, th2,
-                       (int64_t*)nullptr, (int64_t*)nullptr, (unsigned long long*)nullptr, (const int64_t*)ioff.get(),
+                       (int64_t*)nullptr, (int64_t*)nullptr, (unsigned long long*)nullptr, (const int64_t*)icnt.get(),
                        items.get());
     SRF_HIP(hipGetLastError());
-    if (ng > 0) {
-        hipLaunchKernelGGL(k_expand, dim3((unsigned)ng), dim3(64), 0, st, ng, ioff.get(), items.get(), t.range.get(),
-                           l.off.get(), l.ent.get());
-        SRF_HIP(hipGetLastError());
-    }
+    hipLaunchKernelGGL(k_expand, dim3((unsigned)ng), dim3(64), 0, st, ng, (int64_t)0, (const int64_t*)nullptr,
+                       icnt.get(), items.get(), t.range.get(), l.off.get(), l.ent.get());
+    SRF_HIP(hipGetLastError());
 }
 
 }  // namespace srf
