@@ -221,21 +221,22 @@ __global__ __launch_bounds__(128) void k_lists(int64_t ng, const double* __restr
 // Expansion: one wave per group turns its items into entries.  Items are
 // taken 64 at a time (one per lane); a leaf item stands for its particles
 // first..first+count-1, a cell item for itself.  An inclusive scan of the
-// item sizes places each item, and the lanes write their items in rounds
-// (round s writes the s-th entry of every item that has one), so a round
-// fills a contiguous stretch of the list.
+// item sizes places each item; then lane k writes entries k, k + 64, ... of
+// the chunk, finding its item by binary search over the scan in LDS, so
+// every store of the wave covers 64 consecutive entries.
 // Items of group g: icnt[g] of them from g * slot when slot > 0, else
 // [ioff[g], ioff[g + 1]).
 __global__ __launch_bounds__(64) void k_expand(int64_t ng, int64_t slot, const int64_t* __restrict__ icnt,
                                                const int64_t* __restrict__ ioff, const int32_t* __restrict__ items,
                                                const NodeRange* __restrict__ rng, const int64_t* __restrict__ off,
                                                int32_t* __restrict__ ent) {
+    __shared__ int32_t s_end[64], s_first[64];
     const int64_t g = xcd_block(blockIdx.x, gridDim.x);
     if (g >= ng) return;
     const int lane = threadIdx.x;
     const int64_t i0 = slot > 0 ? g * slot : ioff[g];
     const int64_t i1 = slot > 0 ? i0 + icnt[g] : ioff[g + 1];
-    int64_t base = off[g];
+    int32_t* dst = ent + off[g];
     for (int64_t c0 = i0; c0 < i1; c0 += 64) {
         const int64_t ii = c0 + lane;
         int32_t v = 0, first = 0, n = 0;
@@ -257,13 +258,23 @@ __global__ __launch_bounds__(64) void k_expand(int64_t ng, int64_t slot, const i
             if (lane >= o) incl += u;
         }
         const int total = __shfl(incl, 63, 64);
-        int maxn = n;
+        __syncthreads();
+        s_end[lane] = incl;
+        // a leaf's entry q is first + q; a cell's only entry is its code,
+        // stored as first - 0 with the leaf flag clear
+        s_first[lane] = v >= 0 ? first - (incl - n) : first;
+        __syncthreads();
+        const uint64_t leafmask = __ballot(v >= 0 && n > 0);
+        for (int k = lane; k < total; k += 64) {
+            // first item whose end exceeds k
+            int lo = 0;
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) maxn = max(maxn, __shfl_xor(maxn, o, 64));
-        int32_t* dst = ent + base + (incl - n);
-        for (int s2 = 0; s2 < maxn; ++s2)
-            if (s2 < n) dst[s2] = v >= 0 ? first + s2 : first;
-        base += total;
+            for (int step = 32; step >= 1; step >>= 1)
+                if (s_end[lo + step - 1] <= k) lo += step;
+            const int32_t f = s_first[lo];
+            dst[k] = ((leafmask >> lo) & 1ull) ? f + k : f;
+        }
+        dst += total;
     }
 }
 
