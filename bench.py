@@ -228,7 +228,10 @@ def main():
     fpi = FLOPS_ADJOINT if dominant == "adjoint" else FLOPS_FORCE
     achieved = fpi * I / (kd * 1e-3)
     prof = profiled_counters(args.workload, ps.params.theta)
-    kernel_names = {"force": "k_force<float, false>", "adjoint": "k_adjoint<float>"}
+    # kernel instances the library launches for these parameters: plain FP32
+    # partial sums; far pairs take r from s when (2 eps / r_cut)^2 <= 5e-4
+    rs = "true" if 4.0 * ps.params.eps ** 2 / ps.params.r_cut ** 2 <= 5e-4 else "false"
+    kernel_names = {"force": f"k_force<float, false, {rs}>", "adjoint": f"k_adjoint<float, {rs}>"}
     kname = kernel_names[dominant]
     traffic = None
     executed = {}

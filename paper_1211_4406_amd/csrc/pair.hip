@@ -38,6 +38,7 @@ struct Coef {
     T E0, E1, E2;              // k^2 g'(xi)/xi on [1,2] = -t^4 (E2 r^2 + E1 r + E0)
     T k, eps2, rh2;            // k = 2/r_cut, eps^2, (r_cut/2)^2
     T m3;                      // -3 (not an inline constant of the ISA)
+    T heps2;                   // -eps^2 / 2
     double far2;               // (r_cut/2)^2 in FP64, for the near/far split of a tile
 };
 
@@ -69,6 +70,7 @@ Coef<T> make_coef(double rc, double eps) {
     c.eps2 = (T)(eps * eps);
     c.rh2 = (T)(0.25 * rc * rc);
     c.m3 = (T)(-3.0);
+    c.heps2 = (T)(-0.5 * eps * eps);
     c.far2 = 0.25 * rc * rc;
     return c;
 }
@@ -102,7 +104,7 @@ __device__ __forceinline__ Coef<T> pinned(const Coef<T>& a) {
     c.R0 = pin_(a.R0); c.R1 = pin_(a.R1); c.R2 = pin_(a.R2); c.R3 = pin_(a.R3);
     c.C1 = pin_(a.C1); c.C3 = pin_(a.C3); c.C4 = pin_(a.C4); c.C5 = pin_(a.C5); c.C6 = pin_(a.C6);
     c.E0 = pin_(a.E0); c.E1 = pin_(a.E1); c.E2 = pin_(a.E2);
-    c.k = pin_(a.k); c.eps2 = pin_(a.eps2); c.rh2 = pin_(a.rh2); c.m3 = pin_(a.m3);
+    c.k = pin_(a.k); c.eps2 = pin_(a.eps2); c.rh2 = pin_(a.rh2); c.m3 = pin_(a.m3); c.heps2 = pin_(a.heps2);
     c.far2 = a.far2;
     return c;
 }
@@ -159,16 +161,27 @@ struct Acc {
     }
 };
 
+// Unsoftened distance r of a far pair from s^2 = r^2 + eps^2 and s^-1.  With
+// RS it is r = s - eps^2 / (2 s) = s^2 s^-1 - (eps^2 / 2) s^-1, whose
+// relative error is y^2/8 + O(y^3) with y = eps^2 / s^2 <= (2 eps / r_cut)^2
+// for far pairs (s >= r_cut / 2); the host selects RS only when that bound
+// keeps the error below half an FP32 ulp.  Otherwise r = sqrt(r^2).
+template <class T, bool RS>
+__device__ __forceinline__ T far_r(T r2, T s2, T rinv, const Coef<T>& c) {
+    return RS ? fma_(c.heps2, rinv, s2 * rinv) : sqrt_(r2);
+}
+
 // Force of one source (offset p.xyz, mass p.w) on one target (xi, yi, zi),
 // accumulated into acc.  NEAR selects the full cutoff function; otherwise
 // the source lies at xi >= 1 from the target, g = t^5 R, and the factor
 // m s^-3 t^5 R is formed as m (q^2)(q t)(t R) with q = t s^-1.
-template <class T, class V4, bool NEAR, bool COMP>
+template <class T, class V4, bool NEAR, bool COMP, bool RS>
 __device__ __forceinline__ void pair_force(const V4& p, T xi, T yi, T zi, const Coef<T>& c, Acc<T, COMP>& acc) {
     const T dx = p.x - xi, dy = p.y - yi, dz = p.z - zi;
     const T r2 = fma_(dz, dz, fma_(dy, dy, dx * dx));
-    const T rinv = rsqrt_(r2 + c.eps2);
-    const T r = sqrt_(r2);
+    const T s2 = r2 + c.eps2;
+    const T rinv = rsqrt_(s2);
+    const T r = NEAR ? sqrt_(r2) : far_r<T, RS>(r2, s2, rinv, c);
     T f;
     if (NEAR) {
         T t;
@@ -272,7 +285,7 @@ __device__ __forceinline__ int stage_tile(const int32_t* __restrict__ ent, int l
 // (entries a + st, a + st + S, ...).  The unrolled loop takes U entries
 // per stream (8 for the shorter far pairs, 4 for near pairs) while all
 // streams have U left, so its trip count is the same for every lane.
-template <class T, class V4, int S, bool NEAR, bool COMP>
+template <class T, class V4, int S, bool NEAR, bool COMP, bool RS>
 __device__ __forceinline__ void force_segment(const V4* tile, int a, int b, int st, T xi, T yi, T zi,
                                               const Coef<T>& c, Acc<T, COMP>& acc) {
     constexpr int U = NEAR ? 4 : 8;
@@ -283,9 +296,9 @@ __device__ __forceinline__ void force_segment(const V4* tile, int a, int b, int 
 #pragma unroll
         for (int u = 0; u < U; ++u) pp[u] = tp[u * S];
 #pragma unroll
-        for (int u = 0; u < U; ++u) pair_force<T, V4, NEAR, COMP>(pp[u], xi, yi, zi, c, acc);
+        for (int u = 0; u < U; ++u) pair_force<T, V4, NEAR, COMP, RS>(pp[u], xi, yi, zi, c, acc);
     }
-    for (int k = kk + st; k < b; k += S, tp += S) pair_force<T, V4, NEAR, COMP>(tp[0], xi, yi, zi, c, acc);
+    for (int k = kk + st; k < b; k += S, tp += S) pair_force<T, V4, NEAR, COMP, RS>(tp[0], xi, yi, zi, c, acc);
 }
 
 struct GroupArgs {
@@ -297,7 +310,7 @@ struct GroupArgs {
 };
 
 // ------------------------------------------------------------------ force
-template <class T, int S, bool COMP>
+template <class T, int S, bool COMP, bool RS>
 __device__ __forceinline__ void force_group(const GroupArgs& ga, const Src& src, const Coef<T>& c0, double G,
                                             double* __restrict__ ax, double* __restrict__ ay,
                                             double* __restrict__ az, int64_t os, int64_t g, int32_t first,
@@ -324,8 +337,8 @@ __device__ __forceinline__ void force_group(const GroupArgs& ga, const Src& src,
         __syncthreads();
         Acc<T, COMP> acc;
         if (active) {
-            force_segment<T, V4, S, true, COMP>(tile, 0, nnear, st, xi, yi, zi, c, acc);
-            force_segment<T, V4, S, false, COMP>(tile, nnear, len, st, xi, yi, zi, c, acc);
+            force_segment<T, V4, S, true, COMP, RS>(tile, 0, nnear, st, xi, yi, zi, c, acc);
+            force_segment<T, V4, S, false, COMP, RS>(tile, nnear, len, st, xi, yi, zi, c, acc);
         }
         sx += COMP ? (double)acc.x - (double)acc.cx : (double)acc.x;
         sy += COMP ? (double)acc.y - (double)acc.cy : (double)acc.y;
@@ -352,8 +365,8 @@ __device__ __forceinline__ void force_group(const GroupArgs& ga, const Src& src,
 }
 
 // Streams per group: the largest of 1, 2, 3, 4, 8 with S * N_i <= 64.
-template <class T, bool COMP>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_force(
+template <class T, bool COMP, bool RS>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) void k_force(
     GroupArgs ga, Src src, Coef<T> c, double G, double* __restrict__ ax, double* __restrict__ ay,
     double* __restrict__ az, int64_t os) {
     using V4 = typename Vec4<T>::type;
@@ -361,11 +374,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     __shared__ double red[64 * 3];
     const int64_t g = xcd_block(blockIdx.x, gridDim.x);
     const int32_t first = ga.gfirst[g], cnt = ga.gcount[g];
-    if (cnt > 32) force_group<T, 1, COMP>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
-    else if (cnt > 21) force_group<T, 2, COMP>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
-    else if (cnt > 16) force_group<T, 3, COMP>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
-    else if (cnt > 8) force_group<T, 4, COMP>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
-    else force_group<T, 8, COMP>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
+    if (cnt > 32) force_group<T, 1, COMP, RS>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
+    else if (cnt > 21) force_group<T, 2, COMP, RS>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
+    else if (cnt > 16) force_group<T, 3, COMP, RS>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
+    else if (cnt > 8) force_group<T, 4, COMP, RS>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
+    else force_group<T, 8, COMP, RS>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
 }
 
 // ---------------------------------------------------------------- adjoint
@@ -465,7 +478,7 @@ struct Targets {
 };
 
 // Entry blocks [a, b) of a staged tile (all near or all far).
-template <class T, class V4, int NB, bool NEAR>
+template <class T, class V4, int NB, bool NEAR, bool RS>
 __device__ __forceinline__ void adjoint_entries(int a, int b, const V4* tile, const int32_t* ids, int lane,
                                                 Targets<T, NB>& tg, const Coef<T>& c, const AdjOut& out) {
     const int ra = lane & (kRow - 1), rb = lane >> 4;
@@ -482,8 +495,9 @@ __device__ __forceinline__ void adjoint_entries(int a, int b, const V4* tile, co
         for (int ib = 0; ib < NB; ++ib) {
             const T dx = p.x - tg.x[ib], dy = p.y - tg.y[ib], dz = p.z - tg.z[ib];
             const T r2 = fma_(dz, dz, fma_(dy, dy, dx * dx));
-            const T rinv = (NEAR && v == tg.id[ib]) ? T(0) : rsqrt_(r2 + c.eps2);
-            const T r = sqrt_(r2);
+            const T s2 = r2 + c.eps2;
+            const T rinv = (NEAR && v == tg.id[ib]) ? T(0) : rsqrt_(s2);
+            const T r = NEAR ? sqrt_(r2) : far_r<T, RS>(r2, s2, rinv, c);
             T phi, psi;
             jac_coefs<T, NEAR>(r2, r, rinv, c, phi, psi);
             const T dw = fma_(dz, tg.wz[ib], fma_(dy, tg.wy[ib], dx * tg.wx[ib]));
@@ -523,7 +537,7 @@ __device__ __forceinline__ void adjoint_entries(int a, int b, const V4* tile, co
     }
 }
 
-template <class T, int NB>
+template <class T, int NB, bool RS>
 __device__ __forceinline__ void adjoint_group(const GroupArgs& ga, const Src& src, const Coef<T>& c0,
                                               const double* __restrict__ wx, const double* __restrict__ wy,
                                               const double* __restrict__ wz, int64_t ws, const AdjOut& out,
@@ -566,8 +580,8 @@ __device__ __forceinline__ void adjoint_group(const GroupArgs& ga, const Src& sr
         __syncthreads();
 #pragma unroll
         for (int ib = 0; ib < NB; ++ib) tg.A[ib] = tg.Bx[ib] = tg.By[ib] = tg.Bz[ib] = T(0);
-        adjoint_entries<T, V4, NB, true>(0, nnear, tile, ids, lane, tg, c, out);
-        adjoint_entries<T, V4, NB, false>(nnear, len, tile, ids, lane, tg, c, out);
+        adjoint_entries<T, V4, NB, true, RS>(0, nnear, tile, ids, lane, tg, c, out);
+        adjoint_entries<T, V4, NB, false, RS>(nnear, len, tile, ids, lane, tg, c, out);
         // FP32 tile partials into this lane's FP64 slots
 #pragma unroll
         for (int ib = 0; ib < NB; ++ib) {
@@ -594,7 +608,7 @@ __device__ __forceinline__ void adjoint_group(const GroupArgs& ga, const Src& sr
     }
 }
 
-template <class T>
+template <class T, bool RS>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) void k_adjoint(GroupArgs ga, Src src, Coef<T> c, const double* __restrict__ wx,
                                                 const double* __restrict__ wy, const double* __restrict__ wz, int64_t ws,
                                                 AdjOut out) {
@@ -606,13 +620,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     const int32_t first = ga.gfirst[g], cnt = ga.gcount[g];
     static_assert(kRow * kRows == 64, "one wave is kRows rows of kRow lanes");
     if (cnt > 48)
-        adjoint_group<T, 4>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, ids, ired);
+        adjoint_group<T, 4, RS>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, ids, ired);
     else if (cnt > 32)
-        adjoint_group<T, 3>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, ids, ired);
+        adjoint_group<T, 3, RS>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, ids, ired);
     else if (cnt > 16)
-        adjoint_group<T, 2>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, ids, ired);
+        adjoint_group<T, 2, RS>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, ids, ired);
     else
-        adjoint_group<T, 1>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, ids, ired);
+        adjoint_group<T, 1, RS>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, ids, ired);
 }
 
 // Node sources -> member particles.  For a cell c0 and its ancestors c
@@ -695,19 +709,38 @@ Src src_args(const Tree& t) {
 
 }  // namespace
 
+// Far pairs of the FP32 kernels take r = s - eps^2/(2 s) (see far_r) when
+// y = (2 eps / r_cut)^2 <= 5e-4, i.e. when its relative error y^2/8 stays
+// below 3.2e-8, half an FP32 ulp.
+static bool far_r_from_s(const srf_params& p) {
+    const double y = 4.0 * p.eps * p.eps / (p.r_cut * p.r_cut);
+    return y <= 5e-4;
+}
+
 void launch_force(const Tree& t, const Lists& l, const srf_params& p, double* ax, double* ay, double* az, int64_t os,
                   hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
     const int64_t ng = t.n_groups;
     if (ev0) SRF_HIP(hipEventRecord(ev0, st));
     if (p.precision == SRF_FP64) {
-        hipLaunchKernelGGL((k_force<double, false>), dim3((unsigned)ng), dim3(64), 0, st, group_args(t, l),
+        hipLaunchKernelGGL((k_force<double, false, false>), dim3((unsigned)ng), dim3(64), 0, st, group_args(t, l),
                            src_args(t), make_coef<double>(p.r_cut, p.eps), p.G, ax, ay, az, os);
-    } else if (p.compensated) {
-        hipLaunchKernelGGL((k_force<float, true>), dim3((unsigned)ng), dim3(64), 0, st, group_args(t, l),
-                           src_args(t), make_coef<float>(p.r_cut, p.eps), p.G, ax, ay, az, os);
     } else {
-        hipLaunchKernelGGL((k_force<float, false>), dim3((unsigned)ng), dim3(64), 0, st, group_args(t, l),
-                           src_args(t), make_coef<float>(p.r_cut, p.eps), p.G, ax, ay, az, os);
+        const bool rs = far_r_from_s(p);
+        const Coef<float> c = make_coef<float>(p.r_cut, p.eps);
+        const GroupArgs ga = group_args(t, l);
+        const Src sa = src_args(t);
+        if (p.compensated && rs)
+            hipLaunchKernelGGL((k_force<float, true, true>), dim3((unsigned)ng), dim3(64), 0, st, ga, sa, c, p.G, ax,
+                               ay, az, os);
+        else if (p.compensated)
+            hipLaunchKernelGGL((k_force<float, true, false>), dim3((unsigned)ng), dim3(64), 0, st, ga, sa, c, p.G, ax,
+                               ay, az, os);
+        else if (rs)
+            hipLaunchKernelGGL((k_force<float, false, true>), dim3((unsigned)ng), dim3(64), 0, st, ga, sa, c, p.G, ax,
+                               ay, az, os);
+        else
+            hipLaunchKernelGGL((k_force<float, false, false>), dim3((unsigned)ng), dim3(64), 0, st, ga, sa, c, p.G, ax,
+                               ay, az, os);
     }
     SRF_HIP(hipGetLastError());
     if (ev1) SRF_HIP(hipEventRecord(ev1, st));
@@ -733,11 +766,14 @@ void launch_adjoint(const Tree& t, const Lists& l, const srf_params& p, const do
     fill_f64(o.gj, 0.0, 4 * (n + nn), st);
     if (ev0) SRF_HIP(hipEventRecord(ev0, st));
     if (p.precision == SRF_FP64) {
-        hipLaunchKernelGGL(k_adjoint<double>, dim3((unsigned)ng), dim3(64), 0, st, group_args(t, l), src_args(t),
-                           make_coef<double>(p.r_cut, p.eps), wx, wy, wz, ws, o);
+        hipLaunchKernelGGL((k_adjoint<double, false>), dim3((unsigned)ng), dim3(64), 0, st, group_args(t, l),
+                           src_args(t), make_coef<double>(p.r_cut, p.eps), wx, wy, wz, ws, o);
+    } else if (far_r_from_s(p)) {
+        hipLaunchKernelGGL((k_adjoint<float, true>), dim3((unsigned)ng), dim3(64), 0, st, group_args(t, l),
+                           src_args(t), make_coef<float>(p.r_cut, p.eps), wx, wy, wz, ws, o);
     } else {
-        hipLaunchKernelGGL(k_adjoint<float>, dim3((unsigned)ng), dim3(64), 0, st, group_args(t, l), src_args(t),
-                           make_coef<float>(p.r_cut, p.eps), wx, wy, wz, ws, o);
+        hipLaunchKernelGGL((k_adjoint<float, false>), dim3((unsigned)ng), dim3(64), 0, st, group_args(t, l),
+                           src_args(t), make_coef<float>(p.r_cut, p.eps), wx, wy, wz, ws, o);
     }
     SRF_HIP(hipGetLastError());
     if (ev1) SRF_HIP(hipEventRecord(ev1, st));

@@ -199,6 +199,31 @@ def test_lists_with_more_items_than_a_slot():
     assert st["rms"] <= FP32_TOL
 
 
+@pytest.mark.parametrize("eps", [2e-4, 1e-2])
+def test_far_distance_paths(eps):
+    """Far pairs take r = s - eps^2/(2 s) when (2 eps / r_cut)^2 <= 5e-4 and
+    the exact square root otherwise (eps = 1e-2 with r_cut = 0.1 gives 0.04):
+    force and adjoint agree with the oracle on both paths."""
+    ps = synth.small_clustered(8000, 131, r_cut=0.1, eps=eps, theta=0.5, per_halo=800)
+    say(f"[gpu] far-distance path eps={eps} n={ps.n}")
+    ot = oracle.OracleTree(ps.x, ps.y, ps.z, ps.m, ps.params)
+    _, _, a32 = gpu_forward(ps)
+    st = rel_stats(a32, ot.force())
+    say(f"    force: {st}")
+    assert st["rms"] <= FP32_TOL
+    w = synth.loss_weights(ps.n, 132)
+    rx, rm = ot.adjoint(w)
+    p = srf.Params.of(ps.params)
+    x, m = dev_inputs(ps)
+    tree = srf.tree_build(x, m, p)
+    lists = srf.make_lists(tree, p)
+    gx, gm = srf.short_range_adjoint(tree, lists, p, torch.tensor(w, dtype=torch.float64, device="cuda"))
+    sx = rel_stats(gx.cpu().numpy(), rx)
+    l2m = np.linalg.norm(gm.cpu().numpy() - rm) / np.linalg.norm(rm)
+    say(f"    adjoint: dL/dx {sx}, dL/dm normwise {l2m:.3e}")
+    assert sx["rms"] <= FP32_TOL and l2m <= FP32_TOL
+
+
 def test_compensated_force_option():
     """compensated = 1 selects Kahan FP32 partial sums over each tile: the
     result stays within the FP32 tolerance, is no less accurate than plain
