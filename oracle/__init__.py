@@ -17,7 +17,8 @@ Steps (Ishiyama, Nitadori & Makino, SC12):
   a8 unpermute
   a9 adjoint of L = sum_i w_i . a_i with the structure held fixed.
 Plus the plain definition: brute-force minimum-image sums (O(N^2) and a
-cell list) and their gradient.
+cell list) and their gradient.  The long-range (PM) half of the force split
+and the Ewald sum that judges PP + PM live in ``oracle.pm`` (numpy, FP64).
 
 Parity pins (tests/test_oracle_*.py): g against the S2-S2 cloud integral
 that defines it; brute force against O(N^2), momentum, translation and the
