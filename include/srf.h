@@ -126,6 +126,21 @@ int srf_short_range_adjoint(const srf_tree* t, const srf_lists* l, const srf_par
                             double* gx, double* gy, double* gz, int64_t g_stride,
                             double* gm, int64_t gm_stride, void* stream);
 
+/* Long-range (PM) half of the force split (Sec. 2 density split; PM steps
+ * of Sec. 4), all in FP64 on a periodic n_mesh^3 mesh (points at i/n_mesh):
+ * TSC assignment of the tree's particles to 27 mesh points each, 3-D FFT,
+ * multiplication by -4 pi G S(k)^2 / (k^2 W(k)^2) (S the transform of the
+ * S2 cloud of radius r_cut/2, W the TSC window), inverse FFT, fourth-order
+ * central differences, TSC interpolation.  The accelerations are written
+ * (not added) to (ax, ay, az)[i*out_stride] in input order; PP + PM is the
+ * TreePM force.  Uses the sorted particles of `t`; r_cut and G need not
+ * match the tree's lists, but r_cut is normally the one of the PP part.
+ *   n_mesh: a power of two in [16, 1024] (memory: 40 n_mesh^3 bytes).
+ * Asynchronous on `stream` (FP64 atomics: reproducible only to rounding).
+ * Errors: SRF_EINVAL, SRF_ENOMEM, SRF_EHIP. */
+int srf_pm_force(const srf_tree* t, double G, double r_cut, int32_t n_mesh, double* ax, double* ay, double* az,
+                 int64_t out_stride, void* stream);
+
 /* Release a handle (NULL is ignored).  Memory returns to the library's
  * device-memory cache; work still queued on the handle's stream stays valid. */
 void srf_tree_free(srf_tree* t);
@@ -172,9 +187,11 @@ int srf_lists_info(const srf_lists* l, int64_t* n_groups, int64_t* n_particle_en
  * have n_groups + 1 entries. */
 int srf_lists_export(const srf_lists* l, int64_t* poff, int64_t* pidx, int64_t* noff, int64_t* nidx);
 
-/* Kernel timing (host): average duration in milliseconds of the last
- * `srf_short_range_force` / `srf_short_range_adjoint` pair-kernel launch,
- * measured with HIP events on the call's stream when timing is enabled. */
+/* Kernel timing (host): duration in milliseconds of the last timed
+ * `srf_short_range_force` ("force") or `srf_short_range_adjoint`
+ * ("adjoint") pair-kernel launch, or of the whole last `srf_pm_force`
+ * ("pm"), measured with HIP events on the call's stream when timing is
+ * enabled. */
 int srf_set_kernel_timing(int enable);
 int srf_last_kernel_ms(const char* which, double* ms);
 

@@ -109,7 +109,7 @@ def green(n, r_cut, G):
 
 def pm_potential(rho, r_cut, G):
     n = rho.shape[0]
-    return np.fft.irfftn(np.fft.rfftn(rho) * green(n, r_cut, G), s=rho.shape)
+    return np.fft.irfftn(np.fft.rfftn(rho) * green(n, r_cut, G), s=rho.shape, axes=(0, 1, 2))
 
 
 def fd4_accel(phi):

@@ -23,7 +23,8 @@ import torch
 
 __all__ = [
     "Params", "Tree", "Lists", "SrfError", "FP32_REL", "FP64", "lib", "lib_path", "tree_build", "make_lists",
-    "short_range_force", "short_range_adjoint", "ShortRange", "short_range", "set_kernel_timing", "last_kernel_ms",
+    "short_range_force", "short_range_adjoint", "ShortRange", "short_range", "pm_force", "set_kernel_timing",
+    "last_kernel_ms",
 ]
 
 FP32_REL = 0
@@ -105,6 +106,7 @@ def lib():
     L.srf_sorted_export.argtypes = [vp] + [vp] * 4
     L.srf_lists_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
     L.srf_lists_export.argtypes = [vp] * 5
+    L.srf_pm_force.argtypes = [vp, C.c_double, C.c_double, C.c_int32, vp, vp, vp, i64, vp]
     L.srf_set_kernel_timing.argtypes = [C.c_int]
     L.srf_last_kernel_ms.argtypes = [C.c_char_p, C.POINTER(C.c_double)]
     _lib = L
@@ -263,6 +265,20 @@ def short_range_adjoint(tree: Tree, lists: Lists, params: Params, w: torch.Tenso
     _check(lib().srf_short_range_adjoint(tree.handle, lists.handle, C.byref(cp), *wcols, C.c_int64(ws), *gcols,
                                          C.c_int64(gs), _dptr(gm), C.c_int64(1), _stream()))
     return gx, gm
+
+
+def pm_force(tree: Tree, G: float, r_cut: float, n_mesh: int, out: torch.Tensor | None = None,
+             device=None) -> torch.Tensor:
+    """Long-range (PM) accelerations [N,3] float64 of the tree's particles,
+    in input order, on an n_mesh^3 mesh with the S2 split of radius r_cut/2."""
+    if out is None:
+        out = torch.empty((tree.n, 3), dtype=torch.float64, device=device or torch.device("cuda"))
+    out_, cols, os_ = _cols(out)
+    if out_.data_ptr() != out.data_ptr():
+        raise ValueError("out must have unit column stride")
+    _check(lib().srf_pm_force(tree.handle, C.c_double(G), C.c_double(r_cut), C.c_int32(n_mesh), *cols,
+                              C.c_int64(os_), _stream()))
+    return out
 
 
 class ShortRange(torch.autograd.Function):

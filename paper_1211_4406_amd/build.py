@@ -26,6 +26,7 @@ SOURCES = {
     "tree.hip": ["-ffp-contract=off"],
     "lists.hip": ["-ffp-contract=off"],
     "pair.hip": [],
+    "pm.hip": [],
     "api.hip": [],
 }
 

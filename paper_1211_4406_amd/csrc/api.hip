@@ -60,8 +60,8 @@ void check_pair(const srf_tree* t, const srf_lists* l, const srf_params* p) {
 
 struct Timing {
     bool enabled = false;
-    bool have[2] = {false, false};
-    hipEvent_t ev[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    bool have[3] = {false, false, false};
+    hipEvent_t ev[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
 };
 Timing g_timing;
 
@@ -177,6 +177,22 @@ int srf_short_range_adjoint(const srf_tree* t, const srf_lists* l, const srf_par
         timing_events(1, &e0, &e1);
         srf::launch_adjoint(t->t, l->l, *p, wx, wy, wz, w_stride, gx, gy, gz, g_stride, gm, gm_stride,
                             (hipStream_t)stream, e0, e1);
+    });
+}
+
+int srf_pm_force(const srf_tree* t, double G, double r_cut, int32_t n_mesh, double* ax, double* ay, double* az,
+                 int64_t out_stride, void* stream) {
+    return guarded([&] {
+        if (!t) srf::fail(SRF_EINVAL, "tree is NULL");
+        if (!ax || !ay || !az) srf::fail(SRF_EINVAL, "NULL output pointer");
+        if (out_stride < 1) srf::fail(SRF_EINVAL, "out_stride must be >= 1");
+        if (!std::isfinite(G)) srf::fail(SRF_EINVAL, "G must be finite");
+        if (!(std::isfinite(r_cut) && r_cut > 0.0 && r_cut < 0.25)) srf::fail(SRF_EINVAL, "r_cut must lie in (0, 0.25)");
+        if (n_mesh < 16 || n_mesh > 1024 || (n_mesh & (n_mesh - 1)) != 0)
+            srf::fail(SRF_EINVAL, "n_mesh must be a power of two in [16, 1024]");
+        hipEvent_t e0, e1;
+        timing_events(2, &e0, &e1);
+        srf::launch_pm(t->t, G, r_cut, n_mesh, ax, ay, az, out_stride, (hipStream_t)stream, e0, e1);
     });
 }
 
@@ -310,8 +326,11 @@ int srf_set_kernel_timing(int enable) {
 int srf_last_kernel_ms(const char* which, double* ms) {
     return guarded([&] {
         if (!which || !ms) srf::fail(SRF_EINVAL, "NULL argument");
-        int k = std::strcmp(which, "force") == 0 ? 0 : (std::strcmp(which, "adjoint") == 0 ? 1 : -1);
-        if (k < 0) srf::fail(SRF_EINVAL, "which must be \"force\" or \"adjoint\"");
+        int k = std::strcmp(which, "force") == 0 ? 0
+                : std::strcmp(which, "adjoint") == 0 ? 1
+                : std::strcmp(which, "pm") == 0      ? 2
+                                                     : -1;
+        if (k < 0) srf::fail(SRF_EINVAL, "which must be \"force\", \"adjoint\" or \"pm\"");
         if (!g_timing.have[k]) srf::fail(SRF_EINVAL, "no timed launch recorded");
         SRF_HIP(hipEventSynchronize(g_timing.ev[k][1]));
         float f = 0.0f;

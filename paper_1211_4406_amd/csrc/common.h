@@ -148,6 +148,8 @@ void build_lists(const Tree& t, Lists& l, hipStream_t stream);
 void launch_force(const Tree& t, const Lists& l, const srf_params& p, double* ax, double* ay, double* az,
                   int64_t os, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);
 // a9
+void launch_pm(const Tree& t, double G, double r_cut, int n_mesh, double* ax, double* ay, double* az, int64_t os,
+               hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);
 void launch_adjoint(const Tree& t, const Lists& l, const srf_params& p, const double* wx, const double* wy,
                     const double* wz, int64_t ws, double* gx, double* gy, double* gz, int64_t gs, double* gm,
                     int64_t gms, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);

@@ -144,7 +144,7 @@ def zeldovich(grid: int, rms_cells: float, rng: np.random.Generator) -> np.ndarr
     for K in (KX, KY, KZ):
         comp = 1j * K * delta / k2
         comp[nyq] = 0.0
-        psi.append(np.fft.irfftn(comp, s=(grid, grid, grid)))
+        psi.append(np.fft.irfftn(comp, s=(grid, grid, grid), axes=(0, 1, 2)))
         del comp
     del KX, KY, KZ, k2, delta
     psi = np.stack([p.reshape(-1) for p in psi], axis=1)

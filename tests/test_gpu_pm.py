@@ -1,0 +1,107 @@
+"""GPU parity of the long-range (PM) step against the FP64 oracle, and the
+TreePM total (PP + PM) against the Ewald sum.
+
+Both sides compute in FP64 with the same assignment, Green's function,
+differences and interpolation; they differ by the FFT algorithm and the
+order of the atomic mesh sums, so the tolerance is 1e-10 (rms relative)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1211_4406_amd as srf
+import synth
+from oracle import pm
+
+pytestmark = pytest.mark.gpu
+PM_TOL = 1e-10
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_pm(ps, n_mesh, r_cut=None, G=1.0):
+    p = srf.Params.of(ps.params)
+    x = torch.tensor(ps.positions(), dtype=torch.float64, device="cuda")
+    m = torch.tensor(ps.m, dtype=torch.float64, device="cuda")
+    tree = srf.tree_build(x, m, p)
+    a = srf.pm_force(tree, G, ps.params.r_cut if r_cut is None else r_cut, n_mesh)
+    torch.cuda.synchronize()
+    return tree, a.cpu().numpy()
+
+
+@pytest.mark.parametrize("case", ["uniform-3001-n16", "clustered-20000-n32", "uniform-4096-n64"])
+def test_pm_matches_oracle(case):
+    if case == "uniform-3001-n16":
+        rng = np.random.default_rng(7)
+        P = rng.random((3001, 3))
+        ps = synth.ParticleSet(P[:, 0].copy(), P[:, 1].copy(), P[:, 2].copy(), rng.uniform(0.5, 1.5, 3001) / 3001,
+                               synth.Params(1.0, 3.0 / 16, 1e-3, 0.5, 64, 16), case)
+        n_mesh = 16
+    elif case == "clustered-20000-n32":
+        ps = synth.small_clustered(20000, 71, r_cut=3.0 / 32, eps=2e-4, theta=0.5, per_halo=1000)
+        n_mesh = 32
+    else:
+        ps = synth.make_config(1)
+        n_mesh = 64
+    say(f"[gpu] pm {case} n={ps.n} n_mesh={n_mesh}")
+    _, a = gpu_pm(ps, n_mesh)
+    ref = pm.pm_force(ps.x, ps.y, ps.z, ps.m, 1.0, ps.params.r_cut, n_mesh)
+    st = oracle.relative_errors(a, ref)[1]
+    say(f"    vs oracle: {st}")
+    assert st["rms"] <= PM_TOL
+    mom = np.linalg.norm((ps.m[:, None] * a).sum(0)) / np.sum(ps.m * np.linalg.norm(a, axis=1))
+    assert mom < 1e-12
+
+
+def test_pm_full_size_clustered():
+    ps = synth.make_config(2)   # 2^21 particles, r_cut = 3/64: mesh 64^3 (N_PM = N/8)
+    say(f"[gpu] pm full size n={ps.n}")
+    _, a = gpu_pm(ps, 64)
+    ref = pm.pm_force(ps.x, ps.y, ps.z, ps.m, 1.0, ps.params.r_cut, 64)
+    st = oracle.relative_errors(a, ref)[1]
+    say(f"    vs oracle: {st}")
+    assert st["rms"] <= PM_TOL
+
+
+def test_treepm_total_matches_ewald():
+    """PP at theta = 0 (all particles within r_cut) plus PM against Ewald:
+    the GPU total has the error of the method (as the oracle's own total)."""
+    rng = np.random.default_rng(4)
+    n, n_mesh = 256, 16
+    P = rng.random((n, 3))
+    m = np.full(n, 1.0 / n)
+    r_cut = 3.0 / n_mesh
+    ps = synth.ParticleSet(P[:, 0].copy(), P[:, 1].copy(), P[:, 2].copy(), m,
+                           synth.Params(1.0, r_cut, 1e-6, 0.0, 64, 16), "uniform-256")
+    p = srf.Params.of(ps.params, srf.FP64)
+    x = torch.tensor(ps.positions(), dtype=torch.float64, device="cuda")
+    mm = torch.tensor(m, dtype=torch.float64, device="cuda")
+    tree = srf.tree_build(x, mm, p)
+    lists = srf.make_lists(tree, p)
+    a = (srf.short_range_force(tree, lists, p) + srf.pm_force(tree, 1.0, r_cut, n_mesh)).cpu().numpy()
+    ew = pm.ewald_force(ps.x, ps.y, ps.z, m, 1.0)
+    ref = oracle.brute_force(ps.x, ps.y, ps.z, m, 1.0, r_cut, 1e-6, method="n2") + \
+        pm.pm_force(ps.x, ps.y, ps.z, m, 1.0, r_cut, n_mesh)
+    e_gpu = np.linalg.norm(a - ew, axis=1) / np.linalg.norm(ew, axis=1)
+    e_ref = np.linalg.norm(ref - ew, axis=1) / np.linalg.norm(ew, axis=1)
+    say(f"[gpu] TreePM vs Ewald: median {np.median(e_gpu):.3e} (oracle {np.median(e_ref):.3e}), "
+        f"rms {np.sqrt(np.mean(e_gpu ** 2)):.3e}")
+    assert np.median(e_gpu) < 5e-2
+    assert np.max(np.abs(e_gpu - e_ref)) < 1e-8
+
+
+def test_pm_rejects_bad_mesh():
+    ps = synth.make_config(1)
+    p = srf.Params.of(ps.params)
+    x = torch.tensor(ps.positions(), dtype=torch.float64, device="cuda")
+    m = torch.tensor(ps.m, dtype=torch.float64, device="cuda")
+    tree = srf.tree_build(x, m, p)
+    for bad in (8, 48, 2048):
+        with pytest.raises(srf.SrfError) as e:
+            srf.pm_force(tree, 1.0, 0.1, bad)
+        assert e.value.status == -1
