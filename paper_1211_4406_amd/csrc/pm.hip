@@ -39,24 +39,118 @@ __device__ __forceinline__ Tsc tsc(double x, int n) {
     return t;
 }
 
-// 1. density (mass per unit volume) into the real parts of the complex mesh
-__global__ void k_tsc_assign(int64_t np, const double* __restrict__ px, const double* __restrict__ py,
-                             const double* __restrict__ pz, const double* __restrict__ pm, int n,
-                             double* __restrict__ mesh) {
-    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (s >= np) return;
-    const Tsc a = tsc(px[s], n), b = tsc(py[s], n), c = tsc(pz[s], n);
-    const double q = pm[s] * (double)n * n * n;
-    const int64_t nn = n;
+// 1. density (mass per unit volume) into the real parts of the complex mesh.
+// A workgroup takes kChunk consecutive sorted particles, which lie close
+// together (Morton order).  It finds the box of mesh points their stencils
+// touch; if that box fits kBoxMax points, the 27 contributions of each
+// particle are summed into the box in LDS and the box is then added to the
+// mesh with one global atomic per touched point; otherwise each
+// contribution goes to the mesh directly.
+constexpr int kAssignThreads = 256;
+constexpr int kChunk = 2048;
+constexpr int kBoxMax = 4096;   // FP64 values in LDS (32 KB)
+
+__device__ __forceinline__ int wrap_i(int i, int n) { return ((i % n) + n) % n; }
+
+__global__ __launch_bounds__(kAssignThreads) void k_tsc_assign(int64_t np, const double* __restrict__ px,
+                                                               const double* __restrict__ py,
+                                                               const double* __restrict__ pz,
+                                                               const double* __restrict__ pm, int n,
+                                                               double* __restrict__ mesh) {
+    __shared__ double box[kBoxMax];
+    __shared__ int red[6][kAssignThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int64_t s0 = (int64_t)blockIdx.x * kChunk;
+    const int cnt = (int)((np - s0) < kChunk ? (np - s0) : kChunk);
+    const double q = (double)n * n * n;
+    // unwrapped nearest mesh points of this chunk: bounding box
+    int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+    for (int k = tid; k < cnt; k += kAssignThreads) {
+        const double u[3] = {px[s0 + k] * n, py[s0 + k] * n, pz[s0 + k] * n};
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const double wij = q * a.w[i] * b.w[j];
-            const int64_t row = ((int64_t)a.i[i] * nn + b.i[j]) * nn;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) unsafeAtomicAdd(mesh + 2 * (row + c.i[k]), wij * c.w[k]);
+        for (int a = 0; a < 3; ++a) {
+            const int c = (int)floor(u[a] + 0.5);
+            lo[a] = min(lo[a], c);
+            hi[a] = max(hi[a], c);
         }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        for (int o = 32; o >= 1; o >>= 1) {
+            lo[a] = min(lo[a], __shfl_xor(lo[a], o, 64));
+            hi[a] = max(hi[a], __shfl_xor(hi[a], o, 64));
+        }
+        if (lane == 0) {
+            red[a][wid] = lo[a];
+            red[3 + a][wid] = hi[a];
+        }
+    }
+    __syncthreads();
+    int b0[3], bd[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int l = red[a][0], h = red[3 + a][0];
+        for (int w = 1; w < kAssignThreads / 64; ++w) {
+            l = min(l, red[a][w]);
+            h = max(h, red[3 + a][w]);
+        }
+        b0[a] = l - 1;
+        bd[a] = h - l + 3;
+    }
+    const int64_t vol = (int64_t)bd[0] * bd[1] * bd[2];
+    const int64_t nn = n;
+    if (vol <= kBoxMax && bd[0] <= n && bd[1] <= n && bd[2] <= n) {
+        for (int k = tid; k < vol; k += kAssignThreads) box[k] = 0.0;
+        __syncthreads();
+        for (int k = tid; k < cnt; k += kAssignThreads) {
+            const int64_t s = s0 + k;
+            const double u[3] = {px[s] * n, py[s] * n, pz[s] * n};
+            int c[3];
+            double w[3][3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double ci = floor(u[a] + 0.5);
+                const double d = u[a] - ci;
+                c[a] = (int)ci - b0[a];   // stencil centre, box-relative (>= 1)
+                w[a][0] = 0.5 * (0.5 - d) * (0.5 - d);
+                w[a][1] = 0.75 - d * d;
+                w[a][2] = 0.5 * (0.5 + d) * (0.5 + d);
+            }
+            const double mq = pm[s] * q;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const double wij = mq * w[0][i] * w[1][j];
+                    const int row = ((c[0] - 1 + i) * bd[1] + (c[1] - 1 + j)) * bd[2] + c[2] - 1;
+#pragma unroll
+                    for (int kk = 0; kk < 3; ++kk) atomicAdd(&box[row + kk], wij * w[2][kk]);
+                }
+        }
+        __syncthreads();
+        for (int k = tid; k < vol; k += kAssignThreads) {
+            const double v = box[k];
+            if (v == 0.0) continue;
+            const int iz = k % bd[2], iy = (k / bd[2]) % bd[1], ix = k / (bd[2] * bd[1]);
+            const int64_t g = ((int64_t)wrap_i(b0[0] + ix, n) * nn + wrap_i(b0[1] + iy, n)) * nn + wrap_i(b0[2] + iz, n);
+            unsafeAtomicAdd(mesh + 2 * g, v);
+        }
+        return;
+    }
+    for (int k = tid; k < cnt; k += kAssignThreads) {
+        const int64_t s = s0 + k;
+        const Tsc a = tsc(px[s], n), b = tsc(py[s], n), c = tsc(pz[s], n);
+        const double mq = pm[s] * q;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const double wij = mq * a.w[i] * b.w[j];
+                const int64_t row = ((int64_t)a.i[i] * nn + b.i[j]) * nn;
+#pragma unroll
+                for (int kk = 0; kk < 3; ++kk) unsafeAtomicAdd(mesh + 2 * (row + c.i[kk]), wij * c.w[kk]);
+            }
+    }
 }
 
 // twiddles exp(-2 pi i j / n), j < n/2
@@ -251,8 +345,8 @@ void launch_pm(const Tree& t, double G, double r_cut, int n, double* ax, double*
     fill_f64(reinterpret_cast<double*>(mesh.get()), 0.0, 2 * cells, st);
     hipLaunchKernelGGL(k_twiddle, dim3((unsigned)((n / 2 + 255) / 256)), dim3(256), 0, st, n, tw.get());
     SRF_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_tsc_assign, dim3(grid_for(np, 256, 1 << 30)), dim3(256), 0, st, np, t.px.get(), t.py.get(),
-                       t.pz.get(), t.pm.get(), n, reinterpret_cast<double*>(mesh.get()));
+    hipLaunchKernelGGL(k_tsc_assign, dim3((unsigned)((np + kChunk - 1) / kChunk)), dim3(kAssignThreads), 0, st, np,
+                       t.px.get(), t.py.get(), t.pz.get(), t.pm.get(), n, reinterpret_cast<double*>(mesh.get()));
     SRF_HIP(hipGetLastError());
     fft3(mesh.get(), n, tw.get(), false, st);
     hipLaunchKernelGGL(k_green, dim3(grid_for(cells, 256, 1 << 30)), dim3(256), 0, st, mesh.get(), n, r_cut, G);
