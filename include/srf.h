@@ -141,6 +141,16 @@ int srf_short_range_adjoint(const srf_tree* t, const srf_lists* l, const srf_par
 int srf_pm_force(const srf_tree* t, double G, double r_cut, int32_t n_mesh, double* ax, double* ay, double* az,
                  int64_t out_stride, void* stream);
 
+/* Kick and drift of the multiple-stepsize integrator (Sec. 3: a step is one
+ * PM cycle and two PP cycles; the Python layer composes them):
+ *   srf_kick:  v_i += dt a_i      (v, a: [i*stride] columns, device, FP64)
+ *   srf_drift: x_i += dt v_i, then wrapped into [0, 1)
+ * In place, asynchronous on `stream`.  Errors: SRF_EINVAL, SRF_EHIP. */
+int srf_kick(int64_t n, double* vx, double* vy, double* vz, int64_t v_stride, const double* ax, const double* ay,
+             const double* az, int64_t a_stride, double dt, void* stream);
+int srf_drift(int64_t n, double* x, double* y, double* z, int64_t x_stride, const double* vx, const double* vy,
+              const double* vz, int64_t v_stride, double dt, void* stream);
+
 /* Release a handle (NULL is ignored).  Memory returns to the library's
  * device-memory cache; work still queued on the handle's stream stays valid. */
 void srf_tree_free(srf_tree* t);

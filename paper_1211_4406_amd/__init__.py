@@ -23,8 +23,8 @@ import torch
 
 __all__ = [
     "Params", "Tree", "Lists", "SrfError", "FP32_REL", "FP64", "lib", "lib_path", "tree_build", "make_lists",
-    "short_range_force", "short_range_adjoint", "ShortRange", "short_range", "pm_force", "set_kernel_timing",
-    "last_kernel_ms",
+    "short_range_force", "short_range_adjoint", "ShortRange", "short_range", "pm_force", "kick", "drift",
+    "TreePMIntegrator", "set_kernel_timing", "last_kernel_ms",
 ]
 
 FP32_REL = 0
@@ -107,6 +107,8 @@ def lib():
     L.srf_lists_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
     L.srf_lists_export.argtypes = [vp] * 5
     L.srf_pm_force.argtypes = [vp, C.c_double, C.c_double, C.c_int32, vp, vp, vp, i64, vp]
+    L.srf_kick.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp, i64, C.c_double, vp]
+    L.srf_drift.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp, i64, C.c_double, vp]
     L.srf_set_kernel_timing.argtypes = [C.c_int]
     L.srf_last_kernel_ms.argtypes = [C.c_char_p, C.POINTER(C.c_double)]
     _lib = L
@@ -279,6 +281,69 @@ def pm_force(tree: Tree, G: float, r_cut: float, n_mesh: int, out: torch.Tensor 
     _check(lib().srf_pm_force(tree.handle, C.c_double(G), C.c_double(r_cut), C.c_int32(n_mesh), *cols,
                               C.c_int64(os_), _stream()))
     return out
+
+
+def kick(v: torch.Tensor, a: torch.Tensor, dt: float) -> None:
+    """v += dt a, in place ([N,3] float64 device tensors)."""
+    v_, vcols, vs = _cols(v)
+    if v_.data_ptr() != v.data_ptr():
+        raise ValueError("v must have unit column stride")
+    _, acols, as_ = _cols(a)
+    _check(lib().srf_kick(C.c_int64(v.shape[0]), *vcols, C.c_int64(vs), *acols, C.c_int64(as_), C.c_double(dt),
+                          _stream()))
+
+
+def drift(x: torch.Tensor, v: torch.Tensor, dt: float) -> None:
+    """x += dt v, wrapped into [0,1), in place ([N,3] float64 device tensors)."""
+    x_, xcols, xs = _cols(x)
+    if x_.data_ptr() != x.data_ptr():
+        raise ValueError("x must have unit column stride")
+    _, vcols, vs = _cols(v)
+    _check(lib().srf_drift(C.c_int64(x.shape[0]), *xcols, C.c_int64(xs), *vcols, C.c_int64(vs), C.c_double(dt),
+                           _stream()))
+
+
+class TreePMIntegrator:
+    """Multiple-stepsize (impulse) integrator of the TreePM force (Sec. 3:
+    one step is one PM cycle and two PP cycles).  A step of length dt is
+
+        kick(PM, dt/2); 2 x [kick(PP, dt/4); drift(dt/2); PP at new x; kick(PP, dt/4)]; PM at new x; kick(PM, dt/2)
+
+    which is symmetric (time-reversible) and evaluates PM once and PP twice
+    per step; the PM of the new positions reuses the tree of the last PP
+    evaluation, and the accelerations of the step's end start the next.
+    x, v are [N,3] float64 device tensors updated in place; m is [N]."""
+
+    def __init__(self, params: Params, n_mesh: int, pm_r_cut: float | None = None):
+        self.params = params
+        self.n_mesh = int(n_mesh)
+        self.pm_r_cut = params.r_cut if pm_r_cut is None else pm_r_cut
+        self.a_pp = None
+        self.a_pm = None
+
+    def _pp(self, x, m):
+        tree = tree_build(x, m, self.params)
+        lists = make_lists(tree, self.params)
+        return tree, short_range_force(tree, lists, self.params, device=x.device)
+
+    def step(self, x: torch.Tensor, v: torch.Tensor, m: torch.Tensor, dt: float) -> None:
+        if self.a_pp is None or self.a_pm is None:
+            tree, self.a_pp = self._pp(x, m)
+            self.a_pm = pm_force(tree, self.params.G, self.pm_r_cut, self.n_mesh, device=x.device)
+        kick(v, self.a_pm, 0.5 * dt)
+        tree = None
+        for _ in range(2):
+            kick(v, self.a_pp, 0.25 * dt)
+            drift(x, v, 0.5 * dt)
+            tree, self.a_pp = self._pp(x, m)
+            kick(v, self.a_pp, 0.25 * dt)
+        self.a_pm = pm_force(tree, self.params.G, self.pm_r_cut, self.n_mesh, device=x.device)
+        kick(v, self.a_pm, 0.5 * dt)
+
+    def reset(self) -> None:
+        """Forget the cached accelerations (call after changing x or m outside step)."""
+        self.a_pp = None
+        self.a_pm = None
 
 
 class ShortRange(torch.autograd.Function):

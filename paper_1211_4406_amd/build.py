@@ -27,6 +27,7 @@ SOURCES = {
     "lists.hip": ["-ffp-contract=off"],
     "pair.hip": [],
     "pm.hip": [],
+    "integ.hip": [],
     "api.hip": [],
 }
 

@@ -196,6 +196,28 @@ int srf_pm_force(const srf_tree* t, double G, double r_cut, int32_t n_mesh, doub
     });
 }
 
+int srf_kick(int64_t n, double* vx, double* vy, double* vz, int64_t v_stride, const double* ax, const double* ay,
+             const double* az, int64_t a_stride, double dt, void* stream) {
+    return guarded([&] {
+        if (n < 1) srf::fail(SRF_EINVAL, "n must be >= 1");
+        if (!vx || !vy || !vz || !ax || !ay || !az) srf::fail(SRF_EINVAL, "NULL pointer");
+        if (v_stride < 1 || a_stride < 1) srf::fail(SRF_EINVAL, "strides must be >= 1");
+        if (!std::isfinite(dt)) srf::fail(SRF_EINVAL, "dt must be finite");
+        srf::launch_kick(n, vx, vy, vz, v_stride, ax, ay, az, a_stride, dt, (hipStream_t)stream);
+    });
+}
+
+int srf_drift(int64_t n, double* x, double* y, double* z, int64_t x_stride, const double* vx, const double* vy,
+              const double* vz, int64_t v_stride, double dt, void* stream) {
+    return guarded([&] {
+        if (n < 1) srf::fail(SRF_EINVAL, "n must be >= 1");
+        if (!x || !y || !z || !vx || !vy || !vz) srf::fail(SRF_EINVAL, "NULL pointer");
+        if (x_stride < 1 || v_stride < 1) srf::fail(SRF_EINVAL, "strides must be >= 1");
+        if (!std::isfinite(dt)) srf::fail(SRF_EINVAL, "dt must be finite");
+        srf::launch_drift(n, x, y, z, x_stride, vx, vy, vz, v_stride, dt, (hipStream_t)stream);
+    });
+}
+
 void srf_tree_free(srf_tree* t) { delete t; }
 void srf_lists_free(srf_lists* l) { delete l; }
 void srf_release_cache(void) { srf::dev_release_all(); }
