@@ -39,15 +39,19 @@ METRIC = "short-range pair interactions/s + % FP32 VALU peak; fwd and fwd+adjoin
 # rocprofv3 counter runs, summarised in this file; they are used only while
 # the kernel sources still hash to the value recorded with them.
 COUNTER_PROFILE = os.path.join(ROOT, "profiles", "pair_kernels_zeldovich256_counters.md")
-KERNEL_SOURCES = ("paper_1211_4406_amd/csrc/pair.hip", "paper_1211_4406_amd/csrc/common.h",
-                  "paper_1211_4406_amd/build.py")
+KERNEL_SOURCES = ("paper_1211_4406_amd/csrc/pair.hip", "paper_1211_4406_amd/csrc/common.h")
 
 
 def kernel_source_hash() -> str:
+    """Hash of what determines the pair kernels' code: their source, the
+    shared header, and the compiler flags of their translation unit."""
+    from paper_1211_4406_amd import build as _build
+
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
+    h.update(" ".join(_build.COMMON + _build.SOURCES["pair.hip"]).encode())
     return h.hexdigest()[:16]
 
 
