@@ -111,6 +111,23 @@ def gcut_printed(xi):
     return g
 
 
+def qcut(xi):
+    """Potential factor q of the split (short-range potential -G m q(xi) / r)."""
+    xi = _f64(xi)
+    q = np.empty_like(xi)
+    lib().or_qcut_vec(_i64(xi.size), _ptr(xi), _ptr(q))
+    return q
+
+
+def brute_force_potential(x, y, z, m, G, r_cut, eps):
+    """Short-range potential by O(N^2) minimum-image summation (j != i)."""
+    x, y, z, m = map(_f64, (x, y, z, m))
+    phi = np.empty(x.size)
+    lib().or_bf_potential_n2(_i64(x.size), _ptr(x), _ptr(y), _ptr(z), _ptr(m), _d(G), _d(r_cut), _d(eps),
+                             _ptr(phi))
+    return phi
+
+
 def pair_force(d, r_cut, eps):
     """F(d) = d (|d|^2+eps^2)^(-3/2) g(2|d|/r_cut) [|d| < r_cut] for one offset."""
     out = np.empty(3)
@@ -326,6 +343,20 @@ class OracleTree:
         a = np.empty((self.n, 3))
         a[self.perm] = self.force_sorted()
         return a
+
+    def potential(self):
+        """Same-list short-range potential in input order (the target itself left out)."""
+        p = self.params
+        X0, X1, X2 = (np.ascontiguousarray(self.X[:, k]) for k in range(3))
+        phi = np.empty(self.n)
+        L = self.lists
+        lib().or_tree_potential(_i64(self.n_groups), _ptr(self.gfirst), _ptr(self.gcount), _ptr(L.poff),
+                                _ptr(L.pidx), _ptr(L.noff), _ptr(L.nidx), _ptr(self.ux), _ptr(self.uy),
+                                _ptr(self.uz), _ptr(self.m), _ptr(self.M), _ptr(X0), _ptr(X1), _ptr(X2), _d(p.G),
+                                _d(p.r_cut), _d(p.eps), _ptr(phi))
+        out = np.empty(self.n)
+        out[self.perm] = phi
+        return out
 
     def adjoint(self, w):
         """a9: (dL/dx [N,3], dL/dm [N]) in input order for L = sum_i w_i . a_i."""

@@ -167,3 +167,4 @@ def ewald_force(x, y, z, m, G, alpha=6.0, n_real=2, k_max=12):
     # sum_j m_j sin(k (x_j - x_i)) = S cos(k x_i) - C sin(k x_i)
     acc += ((S[None, :] * c - C[None, :] * s) * coef[None, :]) @ K
     return G * acc
+

@@ -83,6 +83,28 @@ double or_gcut_deriv(double xi) {
     return -xi * pow(t, 4.0) * (2.0 * xi * xi + 4.0 * xi - 1.0) / 5.0;
 }
 
+/* Potential factor q of the split: a source of mass m at distance r has the
+ * short-range potential -G m q(xi) / r, xi = 2 r / r_cut, the antiderivative
+ * of the Sec. 2 pair force (g = q - xi q', q(2) = 0):
+ *   q(xi) = xi * integral_xi^2 g(t) / t^2 dt
+ *         = 1 - 52/35 xi + 4/5 xi^3 - 2/5 xi^5 + 1/10 xi^6 + 2/35 xi^7 - 3/140 xi^8   (xi <= 1)
+ *         = (2 - xi)^6 (xi^2 + 4 xi + 2) / 140                                       (1 <= xi <= 2)
+ * and 0 beyond 2.  (1 - q)/r -> (52/35)(2/r_cut) as r -> 0: the potential of
+ * a particle's own S2 cloud at its centre is -G m (104/35) / r_cut. */
+double or_qcut(double xi) {
+    if (xi > 2.0) return 0.0;
+    if (xi <= 1.0) {
+        double x2 = xi * xi, x3 = x2 * xi, x5 = x3 * x2, x6 = x5 * xi, x7 = x6 * xi, x8 = x7 * xi;
+        return 1.0 - (52.0 / 35.0) * xi + 0.8 * x3 - 0.4 * x5 + 0.1 * x6 + (2.0 / 35.0) * x7 - (3.0 / 140.0) * x8;
+    }
+    double t = 2.0 - xi;
+    return pow(t, 6.0) * (xi * xi + 4.0 * xi + 2.0) / 140.0;
+}
+
+void or_qcut_vec(int64_t n, const double* xi, double* q) {
+    for (int64_t k = 0; k < n; ++k) q[k] = or_qcut(xi[k]);
+}
+
 void or_gcut_vec(int64_t n, const double* xi, double* g, double* dg) {
     for (int64_t k = 0; k < n; ++k) {
         g[k] = or_gcut(xi[k]);
@@ -157,6 +179,28 @@ void or_bf_n2(int64_t n, const double* x, const double* y, const double* z, cons
             a[0] += m[j] * d[0] * p; a[1] += m[j] * d[1] * p; a[2] += m[j] * d[2] * p;
         }
         ax[i] = G * a[0]; ay[i] = G * a[1]; az[i] = G * a[2];
+    }
+}
+
+/* Short-range potential of a unit source at squared distance r2: q(2r/r_cut)
+ * over the softened distance (r^2 + eps^2)^(1/2), 0 at and beyond r_cut. */
+static double pot_of(double r2, double rc, double eps) {
+    if (!(r2 < rc * rc)) return 0.0;
+    return or_qcut(2.0 * sqrt(r2) / rc) / sqrt(r2 + eps * eps);
+}
+
+/* O(N^2) short-range potential phi_i = -G sum_{j != i} m_j pot(d_ij). */
+void or_bf_potential_n2(int64_t n, const double* x, const double* y, const double* z, const double* m,
+                        double G, double rc, double eps, double* phi) {
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        double a = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double d[3] = {mimage(x[j] - x[i]), mimage(y[j] - y[i]), mimage(z[j] - z[i])};
+            a += m[j] * pot_of(d[0] * d[0] + d[1] * d[1] + d[2] * d[2], rc, eps);
+        }
+        phi[i] = -G * a;
     }
 }
 
@@ -707,6 +751,33 @@ void or_tree_force(int64_t ng, const int64_t* gfirst, const int64_t* gcount,
                 a[0] += NM[c] * d[0] * p; a[1] += NM[c] * d[1] * p; a[2] += NM[c] * d[2] * p;
             }
             ax[i] = G * a[0]; ay[i] = G * a[1]; az[i] = G * a[2];
+        }
+    }
+}
+
+/* Same-list short-range potential (sorted order): particle and cell sources
+ * of each group's list, the target itself left out. */
+void or_tree_potential(int64_t ng, const int64_t* gfirst, const int64_t* gcount,
+                       const int64_t* poff, const int64_t* pidx, const int64_t* noff, const int64_t* nidx,
+                       const double* ux, const double* uy, const double* uz, const double* m,
+                       const double* NM, const double* NX, const double* NY, const double* NZ,
+                       double G, double rc, double eps, double* phi) {
+    #pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t g = 0; g < ng; ++g) {
+        for (int64_t i = gfirst[g]; i < gfirst[g] + gcount[g]; ++i) {
+            double a = 0.0;
+            for (int64_t e = poff[g]; e < poff[g + 1]; ++e) {
+                int64_t j = pidx[e];
+                if (j == i) continue;
+                double d[3] = {mimage(ux[j] - ux[i]), mimage(uy[j] - uy[i]), mimage(uz[j] - uz[i])};
+                a += m[j] * pot_of(d[0] * d[0] + d[1] * d[1] + d[2] * d[2], rc, eps);
+            }
+            for (int64_t e = noff[g]; e < noff[g + 1]; ++e) {
+                int64_t c = nidx[e];
+                double d[3] = {mimage(NX[c] - ux[i]), mimage(NY[c] - uy[i]), mimage(NZ[c] - uz[i])};
+                a += NM[c] * pot_of(d[0] * d[0] + d[1] * d[1] + d[2] * d[2], rc, eps);
+            }
+            phi[i] = -G * a;
         }
     }
 }
