@@ -126,6 +126,21 @@ int srf_short_range_adjoint(const srf_tree* t, const srf_lists* l, const srf_par
                             double* gx, double* gy, double* gz, int64_t g_stride,
                             double* gm, int64_t gm_stride, void* stream);
 
+/* Short-range potential of the split, in input order:
+ *   phi_i = -G sum_{j != i} m_j q(2 r_ij / r_cut) / (r_ij^2 + eps^2)^(1/2)   -> phi[i*out_stride]
+ * over the same lists as srf_short_range_force (cells as their monopole),
+ * with q the potential factor whose pair force is the cutoff of Sec. 2
+ * (g = q - xi q'): q(xi) = 1 - 52/35 xi + 4/5 xi^3 - 2/5 xi^5 + 1/10 xi^6 +
+ * 2/35 xi^7 - 3/140 xi^8 on [0, 1], (2 - xi)^6 (xi^2 + 4 xi + 2) / 140 on
+ * [1, 2], 0 beyond.  The particle's own entry is left out (its own S2 cloud,
+ * -G m_i (104/35) / r_cut, is not added).  Precision and parameter rules as
+ * for srf_short_range_force; the output is written, not added.
+ * Fully asynchronous on `stream`.
+ * Errors: SRF_EINVAL (also when n + number of cells exceeds 2^31 - 1),
+ * SRF_EMISMATCH, SRF_EHIP. */
+int srf_short_range_potential(const srf_tree* t, const srf_lists* l, const srf_params* p, double* phi,
+                              int64_t out_stride, void* stream);
+
 /* Long-range (PM) half of the force split (Sec. 2 density split; PM steps
  * of Sec. 4), all in FP64 on a periodic n_mesh^3 mesh (points at i/n_mesh):
  * TSC assignment of the tree's particles to 27 mesh points each, 3-D FFT,

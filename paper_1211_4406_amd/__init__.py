@@ -3,13 +3,14 @@
 A thin binding of ``libsrf.so`` (declared in ``include/srf.h``): argument
 marshalling only -- every step of the path runs in the library's HIP
 kernels.  Tensors are torch CUDA (HIP) tensors; work is ordered on torch's
-current stream.  The library must be built (``python -m
-paper_1211_4406_amd.build``); importing this module without it raises.
+current stream.  The library must be built (``python
+paper_1211_4406_amd/build.py``); importing this module without it raises.
 
     tree  = tree_build(x, m, params)          # a1-a5
     lists = make_lists(tree, params)          # a6
     a     = short_range_force(tree, lists, params)            # a7-a8
     gx, gm = short_range_adjoint(tree, lists, params, w)      # a9
+    phi   = short_range_potential(tree, lists, params)        # potential of the split
     a     = ShortRange.apply(x, m, params)    # autograd: backward rebuilds the lists
 """
 from __future__ import annotations
@@ -23,7 +24,7 @@ import torch
 
 __all__ = [
     "Params", "Tree", "Lists", "SrfError", "FP32_REL", "FP64", "lib", "lib_path", "tree_build", "make_lists",
-    "short_range_force", "short_range_adjoint", "ShortRange", "short_range", "pm_force", "kick", "drift",
+    "short_range_force", "short_range_adjoint", "short_range_potential", "ShortRange", "short_range", "pm_force", "kick", "drift",
     "TreePMIntegrator", "set_kernel_timing", "last_kernel_ms",
 ]
 
@@ -82,7 +83,7 @@ def lib():
     if _lib is not None:
         return _lib
     if not os.path.exists(_LIB_PATH):
-        raise RuntimeError(f"{_LIB_PATH} is missing: build it with `python -m paper_1211_4406_amd.build` "
+        raise RuntimeError(f"{_LIB_PATH} is missing: build it with `python paper_1211_4406_amd/build.py` "
                            "(there is no fallback implementation)")
     L = C.CDLL(_LIB_PATH)
     vp, i64, i32, pp = C.c_void_p, C.c_int64, C.c_int32, C.POINTER(_CParams)
@@ -106,6 +107,7 @@ def lib():
     L.srf_sorted_export.argtypes = [vp] + [vp] * 4
     L.srf_lists_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
     L.srf_lists_export.argtypes = [vp] * 5
+    L.srf_short_range_potential.argtypes = [vp, vp, pp, vp, i64, vp]
     L.srf_pm_force.argtypes = [vp, C.c_double, C.c_double, C.c_int32, vp, vp, vp, i64, vp]
     L.srf_kick.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp, i64, C.c_double, vp]
     L.srf_drift.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp, i64, C.c_double, vp]
@@ -267,6 +269,20 @@ def short_range_adjoint(tree: Tree, lists: Lists, params: Params, w: torch.Tenso
     _check(lib().srf_short_range_adjoint(tree.handle, lists.handle, C.byref(cp), *wcols, C.c_int64(ws), *gcols,
                                          C.c_int64(gs), _dptr(gm), C.c_int64(1), _stream()))
     return gx, gm
+
+
+def short_range_potential(tree: Tree, lists: Lists, params: Params, out: torch.Tensor | None = None,
+                          device=None) -> torch.Tensor:
+    """[N] float64 short-range potentials in input order over the same lists
+    as the force (own entry left out)."""
+    if out is None:
+        out = torch.empty((tree.n,), dtype=torch.float64, device=device or torch.device("cuda"))
+    if out.dtype != torch.float64 or out.dim() != 1 or out.shape[0] != tree.n or not out.is_cuda:
+        raise ValueError("out must be a float64 CUDA vector of length n")
+    cp = params.c()
+    _check(lib().srf_short_range_potential(tree.handle, lists.handle, C.byref(cp), _dptr(out),
+                                           C.c_int64(out.stride(0)), _stream()))
+    return out
 
 
 def pm_force(tree: Tree, G: float, r_cut: float, n_mesh: int, out: torch.Tensor | None = None,

@@ -1,6 +1,8 @@
 """Build libsrf.so (HIP, gfx950) in place.
 
-    python -m paper_1211_4406_amd.build
+    python paper_1211_4406_amd/build.py
+
+(run as a script: importing the package loads the library it builds).
 
 Every translation unit is compiled for gfx950 only, with packed FP32
 instructions disabled.  The cell/group and list units are compiled without

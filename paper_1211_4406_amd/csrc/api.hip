@@ -180,6 +180,18 @@ int srf_short_range_adjoint(const srf_tree* t, const srf_lists* l, const srf_par
     });
 }
 
+int srf_short_range_potential(const srf_tree* t, const srf_lists* l, const srf_params* p, double* phi,
+                              int64_t out_stride, void* stream) {
+    return guarded([&] {
+        check_pair(t, l, p);
+        if (!phi) srf::fail(SRF_EINVAL, "NULL output pointer");
+        if (out_stride < 1) srf::fail(SRF_EINVAL, "out_stride must be >= 1");
+        if (t->t.n + t->t.n_nodes > INT32_MAX)
+            srf::fail(SRF_EINVAL, "the potential indexes particles and cells with 32-bit rows: n + n_cells too large");
+        srf::launch_potential(t->t, l->l, *p, phi, out_stride, (hipStream_t)stream);
+    });
+}
+
 int srf_pm_force(const srf_tree* t, double G, double r_cut, int32_t n_mesh, double* ax, double* ay, double* az,
                  int64_t out_stride, void* stream) {
     return guarded([&] {

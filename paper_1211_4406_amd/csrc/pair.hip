@@ -381,6 +381,140 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     else force_group<T, 8, COMP, RS>(ga, src, c, G, ax, ay, az, os, g, first, cnt, tile, red);
 }
 
+// -------------------------------------------------------------- potential
+// Short-range potential of the split, -G sum_j m_j q(xi) / s (the target
+// left out), with q the potential factor of the pair force (g = q - xi q'):
+//   q(xi) = 1 - 52/35 xi + 4/5 xi^3 - 2/5 xi^5 + 1/10 xi^6 + 2/35 xi^7 - 3/140 xi^8   xi <= 1
+//   q(xi) = (2 - xi)^6 (xi^2 + 4 xi + 2) / 140                                       1 <= xi <= 2
+// evaluated in r with the powers of k folded into the coefficients, as g.
+template <class T>
+struct PotCoef {
+    T D1, D3, D5, D6, D7, D8;   // q on [0,1] - 1, in r
+    T Q0, Q1, Q2;               // (xi^2 + 4 xi + 2) / 140 in r
+    T k, eps2, rh2, heps2;
+    double far2;
+};
+
+template <class T>
+PotCoef<T> make_pot_coef(double rc, double eps) {
+    const double k = 2.0 / rc;
+    PotCoef<T> c;
+    c.D1 = (T)(-52.0 / 35.0 * k);
+    c.D3 = (T)(0.8 * k * k * k);
+    c.D5 = (T)(-0.4 * pow(k, 5));
+    c.D6 = (T)(0.1 * pow(k, 6));
+    c.D7 = (T)(2.0 / 35.0 * pow(k, 7));
+    c.D8 = (T)(-3.0 / 140.0 * pow(k, 8));
+    c.Q0 = (T)(2.0 / 140.0);
+    c.Q1 = (T)(4.0 / 140.0 * k);
+    c.Q2 = (T)(1.0 / 140.0 * k * k);
+    c.k = (T)k;
+    c.eps2 = (T)(eps * eps);
+    c.rh2 = (T)(0.25 * rc * rc);
+    c.heps2 = (T)(-0.5 * eps * eps);
+    c.far2 = 0.25 * rc * rc;
+    return c;
+}
+
+template <class T>
+__device__ __forceinline__ PotCoef<T> pinned(const PotCoef<T>& a) {
+    PotCoef<T> c;
+    c.D1 = pin_(a.D1); c.D3 = pin_(a.D3); c.D5 = pin_(a.D5); c.D6 = pin_(a.D6); c.D7 = pin_(a.D7);
+    c.D8 = pin_(a.D8); c.Q0 = pin_(a.Q0); c.Q1 = pin_(a.Q1); c.Q2 = pin_(a.Q2);
+    c.k = pin_(a.k); c.eps2 = pin_(a.eps2); c.rh2 = pin_(a.rh2); c.heps2 = pin_(a.heps2);
+    c.far2 = a.far2;
+    return c;
+}
+
+// m q(xi) / s for one source (offset p.xyz, mass p.w); `self` leaves the
+// target's own entry out.
+template <class T, class V4, bool NEAR, bool RS>
+__device__ __forceinline__ T pair_pot(const V4& p, T xi, T yi, T zi, const PotCoef<T>& c, bool self) {
+    const T dx = p.x - xi, dy = p.y - yi, dz = p.z - zi;
+    const T r2 = fma_(dz, dz, fma_(dy, dy, dx * dx));
+    const T s2 = r2 + c.eps2;
+    const T rinv = (NEAR && self) ? T(0) : rsqrt_(s2);
+    T r;
+    if (NEAR) r = sqrt_(r2);
+    else r = RS ? fma_(c.heps2, rinv, s2 * rinv) : sqrt_(r2);
+    const T t = sat_(fma_(r, -c.k, T(2)));
+    const T t2 = t * t;
+    const T q2 = (t2 * t2) * t2 * fma_(fma_(r, c.Q2, c.Q1), r, c.Q0);
+    T q = q2;
+    if (NEAR) {
+        T u = fma_(r, c.D8, c.D7);
+        u = fma_(r, u, c.D6);
+        u = fma_(r, u, c.D5);
+        u = fma_(r2, u, c.D3);
+        u = fma_(r2, u, c.D1);
+        const T q1 = fma_(r, u, T(1));
+        q = r2 < c.rh2 ? q1 : q2;
+    }
+    return p.w * q * rinv;
+}
+
+template <class T, int S, bool RS>
+__device__ __forceinline__ void potential_group(const GroupArgs& ga, const Src& src, const PotCoef<T>& c0, double G,
+                                                double* __restrict__ phi, int64_t os, int32_t n_part, int64_t g,
+                                                int32_t first, int32_t cnt, typename Vec4<T>::type* tile,
+                                                int32_t* ids, double* red) {
+    using V4 = typename Vec4<T>::type;
+    const PotCoef<T> c = pinned(c0);
+    const int lane = threadIdx.x;
+    const int il = lane % cnt, st = lane / cnt;
+    const bool active = st < S;
+    const double cx = (ga.glo[g * 3 + 0] + ga.ghi[g * 3 + 0]) * 0.5;
+    const double cy = (ga.glo[g * 3 + 1] + ga.ghi[g * 3 + 1]) * 0.5;
+    const double cz = (ga.glo[g * 3 + 2] + ga.ghi[g * 3 + 2]) * 0.5;
+    const double hx = (ga.ghi[g * 3 + 0] - ga.glo[g * 3 + 0]) * 0.5;
+    const double hy = (ga.ghi[g * 3 + 1] - ga.glo[g * 3 + 1]) * 0.5;
+    const double hz = (ga.ghi[g * 3 + 2] - ga.glo[g * 3 + 2]) * 0.5;
+    const int32_t me = first + il;
+    const T xi = (T)(src.px[me] - cx), yi = (T)(src.py[me] - cy), zi = (T)(src.pz[me] - cz);
+    double sum = 0.0;
+    const int64_t e0 = ga.off[g], e1 = ga.off[g + 1];
+    for (int64_t tb = e0; tb < e1; tb += kTile) {
+        const int len = (int)((e1 - tb) < kTile ? (e1 - tb) : kTile);
+        __syncthreads();
+        const int nnear = stage_tile<T, V4>(ga.ent + tb, len, src, cx, cy, cz, hx, hy, hz, c0.far2, tile, ids,
+                                            n_part);
+        __syncthreads();
+        T acc = 0;
+        if (active) {
+            for (int k = st; k < nnear; k += S) acc += pair_pot<T, V4, true, RS>(tile[k], xi, yi, zi, c, ids[k] == me);
+            for (int k = nnear + st; k < len; k += S)
+                acc += pair_pot<T, V4, false, RS>(tile[k], xi, yi, zi, c, false);
+        }
+        sum += (double)acc;
+    }
+    red[lane] = active ? sum : 0.0;
+    __syncthreads();
+    if (lane < cnt) {
+        double tot = 0.0;
+#pragma unroll
+        for (int q = 0; q < S; ++q) tot += red[lane + q * cnt];
+        phi[(int64_t)ga.perm[me] * os] = -G * tot;
+    }
+}
+
+// Streams per group as in the force kernel.  `n_part` is the particle count
+// (the staged rows of cells start there, so that no cell matches a target).
+template <class T, bool RS>
+__global__ __launch_bounds__(64) void k_potential(GroupArgs ga, Src src, PotCoef<T> c, double G,
+                                                  double* __restrict__ phi, int64_t os, int32_t n_part) {
+    using V4 = typename Vec4<T>::type;
+    __shared__ V4 tile[kTile];
+    __shared__ int32_t ids[kTile];
+    __shared__ double red[64];
+    const int64_t g = xcd_block(blockIdx.x, gridDim.x);
+    const int32_t first = ga.gfirst[g], cnt = ga.gcount[g];
+    if (cnt > 32) potential_group<T, 1, RS>(ga, src, c, G, phi, os, n_part, g, first, cnt, tile, ids, red);
+    else if (cnt > 21) potential_group<T, 2, RS>(ga, src, c, G, phi, os, n_part, g, first, cnt, tile, ids, red);
+    else if (cnt > 16) potential_group<T, 3, RS>(ga, src, c, G, phi, os, n_part, g, first, cnt, tile, ids, red);
+    else if (cnt > 8) potential_group<T, 4, RS>(ga, src, c, G, phi, os, n_part, g, first, cnt, tile, ids, red);
+    else potential_group<T, 8, RS>(ga, src, c, G, phi, os, n_part, g, first, cnt, tile, ids, red);
+}
+
 // ---------------------------------------------------------------- adjoint
 // For a pair (target i with weight w, source of mass mu at offset d):
 //   V = J(d) w = phi w + psi (d . w) d,  psi = phi'(r) / r,
@@ -744,6 +878,21 @@ void launch_force(const Tree& t, const Lists& l, const srf_params& p, double* ax
     }
     SRF_HIP(hipGetLastError());
     if (ev1) SRF_HIP(hipEventRecord(ev1, st));
+}
+
+void launch_potential(const Tree& t, const Lists& l, const srf_params& p, double* phi, int64_t os, hipStream_t st) {
+    const int64_t ng = t.n_groups;
+    if (p.precision == SRF_FP64) {
+        hipLaunchKernelGGL((k_potential<double, false>), dim3((unsigned)ng), dim3(64), 0, st, group_args(t, l),
+                           src_args(t), make_pot_coef<double>(p.r_cut, p.eps), p.G, phi, os, (int32_t)t.n);
+    } else if (far_r_from_s(p)) {
+        hipLaunchKernelGGL((k_potential<float, true>), dim3((unsigned)ng), dim3(64), 0, st, group_args(t, l),
+                           src_args(t), make_pot_coef<float>(p.r_cut, p.eps), p.G, phi, os, (int32_t)t.n);
+    } else {
+        hipLaunchKernelGGL((k_potential<float, false>), dim3((unsigned)ng), dim3(64), 0, st, group_args(t, l),
+                           src_args(t), make_pot_coef<float>(p.r_cut, p.eps), p.G, phi, os, (int32_t)t.n);
+    }
+    SRF_HIP(hipGetLastError());
 }
 
 void launch_adjoint(const Tree& t, const Lists& l, const srf_params& p, const double* wx, const double* wy,
