@@ -567,11 +567,14 @@ struct AdjOut {
 // 4 (entry b of the block on row b).  For one entry block a lane evaluates
 // its entry against its target of each of the NB target blocks:
 //   - the i-side term -mu V goes to the lane's FP32 accumulator of that
-//     target (summed over rows once per tile, in FP64),
+//     target (summed over the rows once per tile, in FP64, into the FP64
+//     total the target's own lane keeps),
 //   - V = J w_i and phi (d . w_i) are summed in registers over the NB
-//     blocks, then over the 16 lanes of the row with DPP moves; four lanes
-//     of the row scale by the source mass and add the totals to the
-//     source's gradient with one FP64 atomic per component.
+//     blocks, then over the 16 lanes of the row with DPP moves; the row's
+//     first lane stores the four totals in the tile's j-side slot of the
+//     entry, and once per tile the slots are scaled by the source masses and
+//     added to the sources' gradients with FP64 atomics (four lanes per
+//     source, one 32-byte row each).
 // Targets past N_i carry zero weight, so they add nothing to either side.
 constexpr int kRow = 16;   // lanes per row: targets per block
 constexpr int kRows = 4;   // rows: entries per block
@@ -588,18 +591,12 @@ __device__ __forceinline__ float dpp_f(float v, int ctrl) {
         default: return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x140, 0xf, 0xf, false));
     }
 }
-__device__ __forceinline__ float row16_sum(float v) {
-    v += dpp_f(v, 0);   // quad_perm [1,0,3,2]
-    v += dpp_f(v, 1);   // quad_perm [2,3,0,1]
-    v += dpp_f(v, 2);   // row_half_mirror
-    v += dpp_f(v, 3);   // row_mirror
-    return v;
-}
-__device__ __forceinline__ double row16_sum(double v) {
-#pragma unroll
-    for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
+// Step k of the row sum: quad_perm [1,0,3,2], quad_perm [2,3,0,1],
+// row_half_mirror, row_mirror.  After steps 0..k-1 the lanes of each group
+// of 2^k hold equal values, so step k adds the partner at xor 2^k; the FP64
+// form uses that shuffle directly.
+__device__ __forceinline__ float row16_step(float v, int k) { return v + dpp_f(v, k); }
+__device__ __forceinline__ double row16_step(double v, int k) { return v + __shfl_xor(v, 1 << k, 64); }
 
 // Targets of one lane: block ib holds target 16 ib + a.
 template <class T, int NB>
@@ -611,19 +608,19 @@ struct Targets {
     int32_t id[NB];     // sorted particle index, for the self test
 };
 
-// Entry blocks [a, b) of a staged tile (all near or all far).
+// Entry blocks [a, b) of a staged tile (all near or all far).  Slots past
+// b hold entries of the next segment or the zero padding: their mass is
+// taken as zero and their j-side slot is written again by the segment that
+// owns it (or lies past the tile's entries).
 template <class T, class V4, int NB, bool NEAR, bool RS>
-__device__ __forceinline__ void adjoint_entries(int a, int b, const V4* tile, const int32_t* ids, int lane,
-                                                Targets<T, NB>& tg, const Coef<T>& c, const AdjOut& out) {
+__device__ __forceinline__ void adjoint_entries(int a, int b, const V4* tile, const int32_t* ids, V4* jbuf,
+                                                int lane, Targets<T, NB>& tg, const Coef<T>& c) {
     const int ra = lane & (kRow - 1), rb = lane >> 4;
     for (int eb = a; eb < b; eb += kRows) {
-        // slots up to b + kRows - 1 hold entries of the next segment or the
-        // zero padding; past b the mass is taken as zero
         const int e = eb + rb;
-        const bool valid = e < b;
         V4 p = tile[e];
-        const int32_t v = ids[e];
-        p.w = valid ? p.w : T(0);
+        p.w = e < b ? p.w : T(0);
+        const int32_t v = NEAR ? ids[e] : 0;
         T jx, jy, jz, jm;
 #pragma unroll
         for (int ib = 0; ib < NB; ++ib) {
@@ -654,20 +651,39 @@ __device__ __forceinline__ void adjoint_entries(int a, int b, const V4* tile, co
                 jm = fma_(phi, dw, jm);
             }
         }
-        jx = row16_sum(jx);
-        jy = row16_sum(jy);
-        jz = row16_sum(jz);
-        jm = row16_sum(jm);
-        // component ra of (mu V_x, mu V_y, mu V_z, sum phi (d . w)); a zero
-        // (every pair of the entry beyond r_cut) is not added
-        const T lo = (ra & 1) ? jy : jx;
-        const T hi = (ra & 1) ? jm : jz;
-        const T val = ((ra & 2) ? hi : lo) * (ra == 3 ? T(1) : p.w);
-        if (valid && ra < 4 && val != T(0)) {
-            // the four components of one source are adjacent (one 32-byte line)
-            double* dst = out.gj + (4 * (int64_t)v + ra);
-            unsafeAtomicAdd(dst, (double)val);
+        // row sums, the four chains interleaved step by step; the empty asm
+        // keeps the last DPP add fused (otherwise it is split into a move
+        // and an add inside the store's branch)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            jx = row16_step(jx, k);
+            jy = row16_step(jy, k);
+            jz = row16_step(jz, k);
+            jm = row16_step(jm, k);
         }
+        asm volatile("" : "+v"(jx), "+v"(jy), "+v"(jz), "+v"(jm));
+        if (ra == 0) {
+            V4 o;
+            o.x = jx;
+            o.y = jy;
+            o.z = jz;
+            o.w = jm;
+            jbuf[e] = o;
+        }
+    }
+}
+
+// j-side slots of a finished tile -> FP64 atomics: (mu V_x, mu V_y, mu V_z,
+// sum phi (d . w)) of entry e go to row ids[e] of the j-side array.  A zero
+// (every pair of the entry beyond r_cut) is not added.
+template <class T, class V4>
+__device__ __forceinline__ void flush_jside(int len, const V4* tile, const int32_t* ids, const V4* jbuf,
+                                            double* __restrict__ gj) {
+    const T* jv = reinterpret_cast<const T*>(jbuf);
+    for (int q = threadIdx.x; q < 4 * len; q += 64) {
+        const int e = q >> 2, comp = q & 3;
+        const T val = comp == 3 ? jv[q] : jv[q] * tile[e].w;
+        if (val != T(0)) unsafeAtomicAdd(gj + (4 * (int64_t)ids[e] + comp), (double)val);
     }
 }
 
@@ -676,11 +692,12 @@ __device__ __forceinline__ void adjoint_group(const GroupArgs& ga, const Src& sr
                                               const double* __restrict__ wx, const double* __restrict__ wy,
                                               const double* __restrict__ wz, int64_t ws, const AdjOut& out,
                                               int64_t g, int32_t first, int32_t cnt,
-                                              typename Vec4<T>::type* tile, int32_t* ids, double* ired) {
+                                              typename Vec4<T>::type* tile, int32_t* ids,
+                                              typename Vec4<T>::type* jbuf) {
     using V4 = typename Vec4<T>::type;
     const Coef<T> c = pinned(c0);
     const int lane = threadIdx.x;
-    const int ra = lane & (kRow - 1);
+    const int ra = lane & (kRow - 1), rb = lane >> 4;
     const double cx = (ga.glo[g * 3 + 0] + ga.ghi[g * 3 + 0]) * 0.5;
     const double cy = (ga.glo[g * 3 + 1] + ga.ghi[g * 3 + 1]) * 0.5;
     const double cz = (ga.glo[g * 3 + 2] + ga.ghi[g * 3 + 2]) * 0.5;
@@ -701,10 +718,9 @@ __device__ __forceinline__ void adjoint_group(const GroupArgs& ga, const Src& sr
         tg.wy[ib] = on ? (T)wy[wi] : T(0);
         tg.wz[ib] = on ? (T)wz[wi] : T(0);
         tg.id[ib] = on ? first + i : INT32_MIN;   // INT32_MIN is no list value
-        ired[(ib * 64 + lane) * 3 + 0] = 0.0;
-        ired[(ib * 64 + lane) * 3 + 1] = 0.0;
-        ired[(ib * 64 + lane) * 3 + 2] = 0.0;
     }
+    // FP64 i-side total of target `lane` (block rb, slot ra), kept by that lane
+    double gx = 0.0, gy = 0.0, gz = 0.0;
     const int64_t e0 = ga.off[g], e1 = ga.off[g + 1];
     for (int64_t tb = e0; tb < e1; tb += kTile) {
         const int len = (int)((e1 - tb) < kTile ? (e1 - tb) : kTile);
@@ -714,31 +730,33 @@ __device__ __forceinline__ void adjoint_group(const GroupArgs& ga, const Src& sr
         __syncthreads();
 #pragma unroll
         for (int ib = 0; ib < NB; ++ib) tg.A[ib] = tg.Bx[ib] = tg.By[ib] = tg.Bz[ib] = T(0);
-        adjoint_entries<T, V4, NB, true, RS>(0, nnear, tile, ids, lane, tg, c, out);
-        adjoint_entries<T, V4, NB, false, RS>(nnear, len, tile, ids, lane, tg, c, out);
-        // FP32 tile partials into this lane's FP64 slots
+        adjoint_entries<T, V4, NB, true, RS>(0, nnear, tile, ids, jbuf, lane, tg, c);
+        adjoint_entries<T, V4, NB, false, RS>(nnear, len, tile, ids, jbuf, lane, tg, c);
+        // FP32 tile partials of the four rows summed in FP64 (xor 16, xor 32)
 #pragma unroll
         for (int ib = 0; ib < NB; ++ib) {
-            ired[(ib * 64 + lane) * 3 + 0] -= (double)fma_(tg.A[ib], tg.wx[ib], tg.Bx[ib]);
-            ired[(ib * 64 + lane) * 3 + 1] -= (double)fma_(tg.A[ib], tg.wy[ib], tg.By[ib]);
-            ired[(ib * 64 + lane) * 3 + 2] -= (double)fma_(tg.A[ib], tg.wz[ib], tg.Bz[ib]);
+            double px = (double)fma_(tg.A[ib], tg.wx[ib], tg.Bx[ib]);
+            double py = (double)fma_(tg.A[ib], tg.wy[ib], tg.By[ib]);
+            double pz = (double)fma_(tg.A[ib], tg.wz[ib], tg.Bz[ib]);
+            px += __shfl_xor(px, 16, 64);
+            py += __shfl_xor(py, 16, 64);
+            pz += __shfl_xor(pz, 16, 64);
+            px += __shfl_xor(px, 32, 64);
+            py += __shfl_xor(py, 32, 64);
+            pz += __shfl_xor(pz, 32, 64);
+            if (rb == ib) {
+                gx -= px;
+                gy -= py;
+                gz -= pz;
+            }
         }
+        __syncthreads();
+        flush_jside<T, V4>(len, tile, ids, jbuf, out.gj);
     }
-    __syncthreads();
-    // target i = 16 ib + a: sum its four rows
     if (lane < cnt) {
-        const int ib = lane >> 4, a = lane & (kRow - 1);
-        double tx = 0, ty = 0, tz = 0;
-#pragma unroll
-        for (int r = 0; r < kRows; ++r) {
-            const int l = ib * 64 + r * kRow + a;
-            tx += ired[l * 3 + 0];
-            ty += ired[l * 3 + 1];
-            tz += ired[l * 3 + 2];
-        }
-        out.gix[first + lane] = tx;
-        out.giy[first + lane] = ty;
-        out.giz[first + lane] = tz;
+        out.gix[first + lane] = gx;
+        out.giy[first + lane] = gy;
+        out.giz[first + lane] = gz;
     }
 }
 
@@ -749,18 +767,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     using V4 = typename Vec4<T>::type;
     __shared__ V4 tile[kTile + kRows];
     __shared__ int32_t ids[kTile + kRows];
-    __shared__ double ired[4 * 64 * 3];   // per target block and lane: FP64 i-side sums
+    __shared__ V4 jbuf[kTile + kRows];   // j-side totals of the tile's entries
     const int64_t g = xcd_block(blockIdx.x, gridDim.x);
     const int32_t first = ga.gfirst[g], cnt = ga.gcount[g];
     static_assert(kRow * kRows == 64, "one wave is kRows rows of kRow lanes");
     if (cnt > 48)
-        adjoint_group<T, 4, RS>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, ids, ired);
+        adjoint_group<T, 4, RS>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, ids, jbuf);
     else if (cnt > 32)
-        adjoint_group<T, 3, RS>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, ids, ired);
+        adjoint_group<T, 3, RS>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, ids, jbuf);
     else if (cnt > 16)
-        adjoint_group<T, 2, RS>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, ids, ired);
+        adjoint_group<T, 2, RS>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, ids, jbuf);
     else
-        adjoint_group<T, 1, RS>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, ids, ired);
+        adjoint_group<T, 1, RS>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, ids, jbuf);
 }
 
 // Node sources -> member particles.  For a cell c0 and its ancestors c
