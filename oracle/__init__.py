@@ -16,6 +16,8 @@ Steps (Ishiyama, Nitadori & Makino, SC12):
   a7 same-list force         (Sec. 2 force sum with eq. (cutoff))
   a8 unpermute
   a9 adjoint of L = sum_i w_i . a_i with the structure held fixed.
+Accuracy variants over the same lists: the short-range potential and the
+quadrupole term of the cells (second moments about the centre of mass).
 Plus the plain definition: brute-force minimum-image sums (O(N^2) and a
 cell list) and their gradient.  The long-range (PM) half of the force split
 and the Ewald sum that judges PP + PM live in ``oracle.pm`` (numpy, FP64).
@@ -109,6 +111,34 @@ def gcut_printed(xi):
     g = np.empty_like(xi)
     lib().or_gcut_printed_vec(_i64(xi.size), _ptr(xi), _ptr(g))
     return g
+
+
+def gcut_deriv2(xi):
+    """d^2 g / d xi^2 (quadrupole term of a cell)."""
+    xi = _f64(np.atleast_1d(xi))
+    out = np.empty_like(xi)
+    lib().or_gcut_deriv2_vec(_i64(xi.size), _ptr(xi), _ptr(out))
+    return out
+
+
+def quad_term(d, S, r_cut, eps):
+    """1/2 S_ab d_a d_b F(d) of one unit-weighted second-moment tensor
+    S = (xx, yy, zz, xy, xz, yz) at offset d (source minus target)."""
+    S = _f64(S)
+    out = np.empty(3)
+    lib().or_quad_term(_d(d[0]), _d(d[1]), _d(d[2]), _ptr(S), _d(r_cut), _d(eps), _ptr(out))
+    return out
+
+
+def second_moments(tree: "Tree", ux, uy, uz, m, X):
+    """Second moments S [nn, 6] = (xx, yy, zz, xy, xz, yz) of every cell
+    about its centre of mass X [nn, 3] (sorted-order inputs)."""
+    nn = tree.size
+    S = np.empty((nn, 6))
+    X0, X1, X2 = (np.ascontiguousarray(X[:, k]) for k in range(3))
+    lib().or_second_moments(_i64(nn), _ptr(tree.first), _ptr(tree.count), _ptr(_f64(ux)), _ptr(_f64(uy)),
+                            _ptr(_f64(uz)), _ptr(_f64(m)), _ptr(X0), _ptr(X1), _ptr(X2), _ptr(S))
+    return S
 
 
 def qcut(xi):
@@ -357,6 +387,34 @@ class OracleTree:
         out = np.empty(self.n)
         out[self.perm] = phi
         return out
+
+    def second_moments(self):
+        if getattr(self, "_S", None) is None:
+            self._S = second_moments(self.tree, self.ux, self.uy, self.uz, self.m, self.X)
+        return self._S
+
+    def quad_correction_sorted(self, sel=None):
+        """Quadrupole term of every cell entry of each group's list (sorted order)."""
+        p = self.params
+        S = self.second_moments()
+        X0, X1, X2 = (np.ascontiguousarray(self.X[:, k]) for k in range(3))
+        ax, ay, az = np.zeros(self.n), np.zeros(self.n), np.zeros(self.n)
+        if sel is None:
+            sel_arr, nsel = None, -1
+        else:
+            sel_arr = np.ascontiguousarray(sel, dtype=np.int64)
+            nsel = sel_arr.size
+        L = self.lists
+        lib().or_tree_quad(_i64(self.n_groups), _ptr(self.gfirst), _ptr(self.gcount), _ptr(L.noff), _ptr(L.nidx),
+                           _ptr(self.ux), _ptr(self.uy), _ptr(self.uz), _ptr(X0), _ptr(X1), _ptr(X2), _ptr(S),
+                           _d(p.G), _d(p.r_cut), _d(p.eps), _ptr(sel_arr), _i64(nsel), _ptr(ax), _ptr(ay), _ptr(az))
+        return np.stack([ax, ay, az], axis=1)
+
+    def force_quadrupole(self):
+        """Same-list force with the cells' quadrupole terms, input order."""
+        a = np.empty((self.n, 3))
+        a[self.perm] = self.force_sorted() + self.quad_correction_sorted()
+        return a
 
     def adjoint(self, w):
         """a9: (dL/dx [N,3], dL/dm [N]) in input order for L = sum_i w_i . a_i."""

@@ -83,6 +83,24 @@ double or_gcut_deriv(double xi) {
     return -xi * pow(t, 4.0) * (2.0 * xi * xi + 4.0 * xi - 1.0) / 5.0;
 }
 
+/* d^2g/dxi^2: on [0,1] term by term from the monomials of g'; on [1,2] the
+ * derivative of the factored g' = -xi t^4 P / 5 (t = 2 - xi,
+ * P = 2 xi^2 + 4 xi - 1): -t^3 (t P - 4 xi P + xi t P') / 5, P' = 4 xi + 4. */
+double or_gcut_deriv2(double xi) {
+    if (xi > 2.0) return 0.0;
+    if (xi <= 1.0) {
+        double x2 = xi * xi, x3 = x2 * xi, x4 = x3 * xi, x5 = x4 * xi, x6 = x5 * xi;
+        return -(48.0 / 5.0) * xi + 32.0 * x3 - 15.0 * x4 - (72.0 / 5.0) * x5 + (42.0 / 5.0) * x6;
+    }
+    double t = 2.0 - xi;
+    double P = 2.0 * xi * xi + 4.0 * xi - 1.0, dP = 4.0 * xi + 4.0;
+    return -t * t * t * (t * P - 4.0 * xi * P + xi * t * dP) / 5.0;
+}
+
+void or_gcut_deriv2_vec(int64_t n, const double* xi, double* out) {
+    for (int64_t k = 0; k < n; ++k) out[k] = or_gcut_deriv2(xi[k]);
+}
+
 /* Potential factor q of the split: a source of mass m at distance r has the
  * short-range potential -G m q(xi) / r, xi = 2 r / r_cut, the antiderivative
  * of the Sec. 2 pair force (g = q - xi q', q(2) = 0):
@@ -778,6 +796,89 @@ void or_tree_potential(int64_t ng, const int64_t* gfirst, const int64_t* gcount,
                 a += NM[c] * pot_of(d[0] * d[0] + d[1] * d[1] + d[2] * d[2], rc, eps);
             }
             phi[i] = -G * a;
+        }
+    }
+}
+
+/* ================================================================== */
+/* Quadrupole term of a cell (accuracy variant)                        */
+/* ================================================================== */
+
+/* The multipole expansion of a cell (Sec. 1) taken one order past the
+ * monopole.  With phi(r) = g(k r) / s^3 (k = 2 / r_cut, s^2 = r^2 + eps^2),
+ * psi = phi'(r) / r and chi = psi'(r) / r, the pair force F(D) = D phi(|D|)
+ * has the second derivatives
+ *   d_a d_b F_c = psi (delta_bc D_a + delta_ab D_c + delta_ac D_b) + chi D_a D_b D_c,
+ * so a cell of mass M, centre of mass X and second moments
+ * S_ab = sum_k m_k (x_k - X)_a (x_k - X)_b pulls a target at offset D = X - x by
+ *   M F(D) + 1/2 S_ab d_a d_b F(D)
+ *   = M F(D) + psi S D + (psi tr(S) / 2 + chi (D . S D) / 2) D      (first-order term: 0 at the COM).
+ * psi and chi follow from g, g' and g'' by the chain rule:
+ *   psi = k g' / (r s^3) - 3 g / s^5,
+ *   chi = k^2 g'' / (r^2 s^3) - k g' / (r^3 s^3) - 6 k g' / (r s^5) + 15 g / s^7. */
+static void quad_coefs(double r2, double rc, double eps, double* psi, double* chi) {
+    *psi = *chi = 0.0;
+    if (!(r2 < rc * rc) || !(r2 > 0.0)) return;
+    double r = sqrt(r2), k = 2.0 / rc, xi = k * r;
+    double s2 = r2 + eps * eps, s = sqrt(s2), s3 = s2 * s, s5 = s3 * s2, s7 = s5 * s2;
+    double g = or_gcut(xi), g1 = or_gcut_deriv(xi), g2 = or_gcut_deriv2(xi);
+    *psi = k * g1 / (r * s3) - 3.0 * g / s5;
+    *chi = k * k * g2 / (r2 * s3) - k * g1 / (r2 * r * s3) - 6.0 * k * g1 / (r * s5) + 15.0 * g / s7;
+}
+
+/* 1/2 S_ab d_a d_b F(D) for S = (xx, yy, zz, xy, xz, yz); 0 at and beyond r_cut. */
+void or_quad_term(double dx, double dy, double dz, const double* S, double rc, double eps, double* out) {
+    double psi, chi;
+    quad_coefs(dx * dx + dy * dy + dz * dz, rc, eps, &psi, &chi);
+    double sd[3] = {S[0] * dx + S[3] * dy + S[4] * dz,
+                    S[3] * dx + S[1] * dy + S[5] * dz,
+                    S[4] * dx + S[5] * dy + S[2] * dz};
+    double dsd = dx * sd[0] + dy * sd[1] + dz * sd[2];
+    double c = 0.5 * psi * (S[0] + S[1] + S[2]) + 0.5 * chi * dsd;
+    out[0] = psi * sd[0] + c * dx;
+    out[1] = psi * sd[1] + c * dy;
+    out[2] = psi * sd[2] + c * dz;
+}
+
+/* Second moments about the centre of mass, directly from the definition:
+ * S_c = sum_{k in c} m_k (x_k - X_c)(x_k - X_c)^T as (xx, yy, zz, xy, xz, yz)
+ * (a cell never straddles the periodic boundary, so no image is taken). */
+void or_second_moments(int64_t nn, const int64_t* first, const int64_t* count,
+                       const double* ux, const double* uy, const double* uz, const double* m,
+                       const double* X, const double* Y, const double* Z, double* S) {
+    #pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t c = 0; c < nn; ++c) {
+        double a[6] = {0, 0, 0, 0, 0, 0};
+        for (int64_t k = first[c]; k < first[c] + count[c]; ++k) {
+            double dx = ux[k] - X[c], dy = uy[k] - Y[c], dz = uz[k] - Z[c];
+            a[0] += m[k] * dx * dx; a[1] += m[k] * dy * dy; a[2] += m[k] * dz * dz;
+            a[3] += m[k] * dx * dy; a[4] += m[k] * dx * dz; a[5] += m[k] * dy * dz;
+        }
+        for (int q = 0; q < 6; ++q) S[c * 6 + q] = a[q];
+    }
+}
+
+/* Quadrupole correction of the same-list force (sorted order): for every
+ * group g, member i and cell c of its list, G * 1/2 S_c : dd F(X_c - x_i)
+ * (minimum image).  Written, not added; `sel`/`nsel` as in or_tree_force. */
+void or_tree_quad(int64_t ng, const int64_t* gfirst, const int64_t* gcount, const int64_t* noff,
+                  const int64_t* nidx, const double* ux, const double* uy, const double* uz,
+                  const double* NX, const double* NY, const double* NZ, const double* S,
+                  double G, double rc, double eps, const int64_t* sel, int64_t nsel,
+                  double* ax, double* ay, double* az) {
+    int64_t todo = nsel < 0 ? ng : nsel;
+    #pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < todo; ++q) {
+        int64_t g = nsel < 0 ? q : sel[q];
+        for (int64_t i = gfirst[g]; i < gfirst[g] + gcount[g]; ++i) {
+            double a[3] = {0, 0, 0}, t[3];
+            for (int64_t e = noff[g]; e < noff[g + 1]; ++e) {
+                int64_t c = nidx[e];
+                or_quad_term(mimage(NX[c] - ux[i]), mimage(NY[c] - uy[i]), mimage(NZ[c] - uz[i]), S + 6 * c, rc,
+                             eps, t);
+                a[0] += t[0]; a[1] += t[1]; a[2] += t[2];
+            }
+            ax[i] = G * a[0]; ay[i] = G * a[1]; az[i] = G * a[2];
         }
     }
 }
