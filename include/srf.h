@@ -126,6 +126,23 @@ int srf_short_range_adjoint(const srf_tree* t, const srf_lists* l, const srf_par
                             double* gx, double* gy, double* gz, int64_t g_stride,
                             double* gm, int64_t gm_stride, void* stream);
 
+/* Quadrupole term of the cells (the cell expansion of Sec. 1 taken one
+ * order past the monopole), ADDED to (ax, ay, az)[i*out_stride] in input
+ * order: for every cell c in the list of particle i's group,
+ *   G * 1/2 S_ab d_a d_b F(X_c - x_i)
+ *     = G [psi S D + (psi tr(S)/2 + chi (D . S D)/2) D],   D = X_c - x_i (minimum image),
+ * with S_c = sum_{k in c} m_k (x_k - X_c)(x_k - X_c)^T the cell's second
+ * moments about its centre of mass, F(D) = D phi(|D|) the cutoff pair force
+ * of srf_short_range_force, psi = phi'(r)/r and chi = psi'(r)/r.  Called
+ * after srf_short_range_force on the same output, it gives the force with
+ * quadrupole cells.  The second moments are computed by this call (FP64,
+ * for the cells that occur in the lists).  Precision and parameter rules as
+ * for srf_short_range_force.  Asynchronous on `stream`.  There is no
+ * adjoint of this term.  Errors: SRF_EINVAL, SRF_EMISMATCH, SRF_ENOMEM,
+ * SRF_EHIP. */
+int srf_short_range_quadrupole(const srf_tree* t, const srf_lists* l, const srf_params* p, double* ax, double* ay,
+                               double* az, int64_t out_stride, void* stream);
+
 /* Short-range potential of the split, in input order:
  *   phi_i = -G sum_{j != i} m_j q(2 r_ij / r_cut) / (r_ij^2 + eps^2)^(1/2)   -> phi[i*out_stride]
  * over the same lists as srf_short_range_force (cells as their monopole),

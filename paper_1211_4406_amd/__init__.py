@@ -24,7 +24,7 @@ import torch
 
 __all__ = [
     "Params", "Tree", "Lists", "SrfError", "FP32_REL", "FP64", "lib", "lib_path", "tree_build", "make_lists",
-    "short_range_force", "short_range_adjoint", "short_range_potential", "ShortRange", "short_range", "pm_force", "kick", "drift",
+    "short_range_force", "short_range_adjoint", "short_range_potential", "short_range_quadrupole", "ShortRange", "short_range", "pm_force", "kick", "drift",
     "TreePMIntegrator", "set_kernel_timing", "last_kernel_ms",
 ]
 
@@ -108,6 +108,7 @@ def lib():
     L.srf_lists_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
     L.srf_lists_export.argtypes = [vp] * 5
     L.srf_short_range_potential.argtypes = [vp, vp, pp, vp, i64, vp]
+    L.srf_short_range_quadrupole.argtypes = [vp, vp, pp, vp, vp, vp, i64, vp]
     L.srf_pm_force.argtypes = [vp, C.c_double, C.c_double, C.c_int32, vp, vp, vp, i64, vp]
     L.srf_kick.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp, i64, C.c_double, vp]
     L.srf_drift.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp, i64, C.c_double, vp]
@@ -247,8 +248,9 @@ def make_lists(tree: Tree, params: Params) -> Lists:
 
 
 def short_range_force(tree: Tree, lists: Lists, params: Params, out: torch.Tensor | None = None,
-                      device=None) -> torch.Tensor:
-    """a7-a8: [N,3] float64 accelerations in input order."""
+                      device=None, quadrupole: bool = False) -> torch.Tensor:
+    """a7-a8: [N,3] float64 accelerations in input order; with
+    ``quadrupole`` the cells' quadrupole terms are added (no adjoint)."""
     if out is None:
         out = torch.empty((tree.n, 3), dtype=torch.float64, device=device or torch.device("cuda"))
     out_, cols, os_ = _cols(out)
@@ -256,6 +258,20 @@ def short_range_force(tree: Tree, lists: Lists, params: Params, out: torch.Tenso
         raise ValueError("out must have unit column stride")
     cp = params.c()
     _check(lib().srf_short_range_force(tree.handle, lists.handle, C.byref(cp), *cols, C.c_int64(os_), _stream()))
+    if quadrupole:
+        short_range_quadrupole(tree, lists, params, out)
+    return out
+
+
+def short_range_quadrupole(tree: Tree, lists: Lists, params: Params, out: torch.Tensor) -> torch.Tensor:
+    """Adds the cells' quadrupole terms to the [N,3] float64 accelerations
+    ``out`` (input order) in place."""
+    out_, cols, os_ = _cols(out)
+    if out_.data_ptr() != out.data_ptr():
+        raise ValueError("out must have unit column stride")
+    cp = params.c()
+    _check(lib().srf_short_range_quadrupole(tree.handle, lists.handle, C.byref(cp), *cols, C.c_int64(os_),
+                                            _stream()))
     return out
 
 

@@ -28,6 +28,7 @@ SOURCES = {
     "tree.hip": ["-ffp-contract=off"],
     "lists.hip": ["-ffp-contract=off"],
     "pair.hip": [],
+    "quad.hip": [],
     "pm.hip": [],
     "integ.hip": [],
     "api.hip": [],

@@ -180,6 +180,16 @@ int srf_short_range_adjoint(const srf_tree* t, const srf_lists* l, const srf_par
     });
 }
 
+int srf_short_range_quadrupole(const srf_tree* t, const srf_lists* l, const srf_params* p, double* ax, double* ay,
+                               double* az, int64_t out_stride, void* stream) {
+    return guarded([&] {
+        check_pair(t, l, p);
+        if (!ax || !ay || !az) srf::fail(SRF_EINVAL, "NULL output pointer");
+        if (out_stride < 1) srf::fail(SRF_EINVAL, "out_stride must be >= 1");
+        srf::launch_quadrupole(t->t, l->l, *p, ax, ay, az, out_stride, (hipStream_t)stream);
+    });
+}
+
 int srf_short_range_potential(const srf_tree* t, const srf_lists* l, const srf_params* p, double* phi,
                               int64_t out_stride, void* stream) {
     return guarded([&] {

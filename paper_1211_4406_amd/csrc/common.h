@@ -155,6 +155,8 @@ void launch_kick(int64_t n, double* vx, double* vy, double* vz, int64_t vs, cons
 void launch_drift(int64_t n, double* x, double* y, double* z, int64_t xs, const double* vx, const double* vy,
                   const double* vz, int64_t vs, double dt, hipStream_t stream);
 void launch_potential(const Tree& t, const Lists& l, const srf_params& p, double* phi, int64_t os, hipStream_t st);
+void launch_quadrupole(const Tree& t, const Lists& l, const srf_params& p, double* ax, double* ay, double* az,
+                       int64_t os, hipStream_t st);
 void launch_adjoint(const Tree& t, const Lists& l, const srf_params& p, const double* wx, const double* wy,
                     const double* wz, int64_t ws, double* gx, double* gy, double* gz, int64_t gs, double* gm,
                     int64_t gms, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);

@@ -61,6 +61,7 @@ def test_null_and_size_errors():
     assert L.srf_make_lists(None, C.byref(p), None, C.byref(h)) == -1
     assert L.srf_short_range_force(None, None, C.byref(p), None, None, None, 1, None) == -1
     assert L.srf_short_range_potential(None, None, C.byref(p), None, 1, None) == -1
+    assert L.srf_short_range_quadrupole(None, None, C.byref(p), None, None, None, 1, None) == -1
     assert L.srf_pm_force(None, 1.0, 0.05, 64, None, None, None, 1, None) == -1
     assert "tree" in L.srf_last_error().decode()
     L.srf_tree_free(None)
