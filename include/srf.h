@@ -17,7 +17,10 @@
  * held fixed.
  *
  * Calls are made in this order: srf_tree_build -> srf_make_lists ->
- * srf_short_range_force and/or srf_short_range_adjoint.
+ * srf_short_range_force and/or srf_short_range_adjoint (and, over the same
+ * tree and lists, srf_short_range_potential, or srf_short_range_quadrupole
+ * after srf_short_range_force on the same output).  srf_pm_force needs only
+ * the tree; srf_kick and srf_drift need no handle.
  *
  * Memory and streams.  Unless a comment says "host", every pointer is a
  * device pointer (HIP device memory of the current device) owned by the
