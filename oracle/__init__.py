@@ -296,14 +296,21 @@ class Lists:
     nidx: np.ndarray   # int64 node ids (preorder), ascending within a group
 
 
-def make_lists(tree: Tree, lo, hi, r_cut: float, theta: float) -> Lists:
-    """a6: per-group lists in canonical order (two passes: count, fill)."""
+def make_lists(tree: Tree, lo, hi, r_cut: float, theta: float, com=None) -> Lists:
+    """a6: per-group lists in canonical order (two passes: count, fill).
+    With ``com`` ([nn, 3] centres of mass) the opening criterion measures
+    the distance to each cell's centre of mass instead of its geometric
+    centre (the pruning stays box to box)."""
     ng = lo.shape[0]
     lo = _f64(lo)
     hi = _f64(hi)
     np_, nn_ = np.empty(ng, np.int64), np.empty(ng, np.int64)
+    if com is None:
+        cx = cy = cz = None
+    else:
+        cx, cy, cz = (np.ascontiguousarray(com[:, k], dtype=np.float64) for k in range(3))
     args = (_ptr(tree.level), _ptr(tree.prefix), _ptr(tree.first), _ptr(tree.count), _ptr(tree.child),
-            _ptr(tree.leaf), _d(r_cut), _d(theta))
+            _ptr(tree.leaf), _d(r_cut), _d(theta), _ptr(cx), _ptr(cy), _ptr(cz))
     lib().or_lists_count(_i64(ng), _ptr(lo), _ptr(hi), *args, _ptr(np_), _ptr(nn_))
     poff = np.zeros(ng + 1, np.int64)
     noff = np.zeros(ng + 1, np.int64)
@@ -331,7 +338,8 @@ class OracleTree:
         self.M, self.X = moments(self.tree, self.ux, self.uy, self.uz, self.m)
         self.gfirst, self.gcount = groups(self.tree, params.n_group, self.n)
         self.lo, self.hi = group_bbox(self.gfirst, self.gcount, self.ux, self.uy, self.uz)
-        self.lists = make_lists(self.tree, self.lo, self.hi, params.r_cut, params.theta)
+        self.lists = make_lists(self.tree, self.lo, self.hi, params.r_cut, params.theta,
+                                com=self.X if getattr(params, "mac", 0) == 1 else None)
 
     @property
     def n_groups(self) -> int:

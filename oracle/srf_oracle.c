@@ -657,7 +657,8 @@ static int prune_cell(const double cen[3], double side, const double cg[3], cons
 }
 
 /* Opening criterion: accept the cell as one monopole iff side^2 <
- * theta^2 d^2, d = distance from the group box to the cell centre. */
+ * theta^2 d^2, d = distance from the group box to `cen`: the cell's
+ * geometric centre, or (centre-of-mass variant) its centre of mass. */
 static int accept_cell(const double cen[3], double side, const double cg[3], const double hg[3], double theta) {
     double d2 = gap2(cen, cg, hg, 0.0);
     return side * side < (theta * theta) * d2;
@@ -667,6 +668,7 @@ typedef struct {
     const int32_t* level; const uint64_t* prefix; const int64_t* first; const int64_t* count;
     const int64_t* child; const uint8_t* leaf;
     double rc, theta;
+    const double *X, *Y, *Z;          /* centres of mass for the MAC, or NULL (geometric centre) */
     double cg[3], hg[3];
     int64_t np, nn;
     int64_t* pidx; int64_t* nidx;     /* NULL in the counting pass */
@@ -676,7 +678,9 @@ static void list_rec(list_ctx* c, int64_t node) {
     double cen[3], side;
     cell_geom(c->level[node], c->prefix[node], cen, &side);
     if (prune_cell(cen, side, c->cg, c->hg, c->rc)) return;
-    if (accept_cell(cen, side, c->cg, c->hg, c->theta)) {
+    double mac_cen[3] = {cen[0], cen[1], cen[2]};
+    if (c->X) { mac_cen[0] = c->X[node]; mac_cen[1] = c->Y[node]; mac_cen[2] = c->Z[node]; }
+    if (accept_cell(mac_cen, side, c->cg, c->hg, c->theta)) {
         if (c->nidx) c->nidx[c->nn] = node;
         c->nn++;
         return;
@@ -705,13 +709,13 @@ static void group_frame(const double* lo, const double* hi, int64_t g, double cg
 void or_lists_count(int64_t ng, const double* lo, const double* hi,
                     const int32_t* level, const uint64_t* prefix, const int64_t* first, const int64_t* count,
                     const int64_t* child, const uint8_t* leaf, double rc, double theta,
-                    int64_t* np, int64_t* nn) {
+                    const double* X, const double* Y, const double* Z, int64_t* np, int64_t* nn) {
     #pragma omp parallel for schedule(dynamic, 8)
     for (int64_t g = 0; g < ng; ++g) {
         list_ctx c;
         memset(&c, 0, sizeof c);
         c.level = level; c.prefix = prefix; c.first = first; c.count = count; c.child = child; c.leaf = leaf;
-        c.rc = rc; c.theta = theta;
+        c.rc = rc; c.theta = theta; c.X = X; c.Y = Y; c.Z = Z;
         group_frame(lo, hi, g, c.cg, c.hg);
         list_rec(&c, 0);
         np[g] = c.np; nn[g] = c.nn;
@@ -723,13 +727,14 @@ void or_lists_count(int64_t ng, const double* lo, const double* hi,
 void or_lists_fill(int64_t ng, const double* lo, const double* hi,
                    const int32_t* level, const uint64_t* prefix, const int64_t* first, const int64_t* count,
                    const int64_t* child, const uint8_t* leaf, double rc, double theta,
+                   const double* X, const double* Y, const double* Z,
                    const int64_t* poff, const int64_t* noff, int64_t* pidx, int64_t* nidx) {
     #pragma omp parallel for schedule(dynamic, 8)
     for (int64_t g = 0; g < ng; ++g) {
         list_ctx c;
         memset(&c, 0, sizeof c);
         c.level = level; c.prefix = prefix; c.first = first; c.count = count; c.child = child; c.leaf = leaf;
-        c.rc = rc; c.theta = theta;
+        c.rc = rc; c.theta = theta; c.X = X; c.Y = Y; c.Z = Z;
         group_frame(lo, hi, g, c.cg, c.hg);
         c.pidx = pidx + poff[g]; c.nidx = nidx + noff[g];
         list_rec(&c, 0);

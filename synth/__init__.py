@@ -34,6 +34,7 @@ class Params:
     theta: float = 0.5
     n_group: int = 64
     n_leaf: int = 16
+    mac: int = 0        # 0: opening distance to the cell's geometric centre, 1: to its centre of mass
 
 
 @dataclass

@@ -22,8 +22,8 @@ def _sets():
     }
 
 
-def _coverage_check(ps, theta, n_check_groups=None):
-    p = synth.Params(ps.params.G, ps.params.r_cut, ps.params.eps, theta, 64, 16)
+def _coverage_check(ps, theta, n_check_groups=None, mac=0):
+    p = synth.Params(ps.params.G, ps.params.r_cut, ps.params.eps, theta, 64, 16, mac)
     ot = oracle.OracleTree(ps.x, ps.y, ps.z, ps.m, p)
     u = np.stack([ot.ux, ot.uy, ot.uz], axis=1)
     L = ot.lists
@@ -49,13 +49,13 @@ def _coverage_check(ps, theta, n_check_groups=None):
         assert np.all(np.isin(np.arange(ot.gfirst[g], ot.gfirst[g] + ot.gcount[g]), pl))
         # accepted cells satisfy the opening criterion geometrically: the
         # cell side is below theta times the distance from any point of the
-        # group box to the cell centre
+        # group box to the cell centre (its centre of mass with mac = 1)
         cg = 0.5 * (ot.lo[g] + ot.hi[g])
         hg = 0.5 * (ot.hi[g] - ot.lo[g])
         for c in nl:
             side = 2.0 ** -int(t.level[c])
             f = int(t.first[c])
-            cen = (np.floor(u[f] / side) + 0.5) * side
+            cen = (np.floor(u[f] / side) + 0.5) * side if mac == 0 else ot.X[c]
             dd = np.abs(cen - cg)
             dd = np.minimum(dd, 1 - dd)
             gap = np.maximum(dd - hg, 0)
@@ -102,3 +102,30 @@ def test_group_count_and_interactions_consistent():
     nj = np.diff(ot.lists.poff) + np.diff(ot.lists.noff)
     assert ot.interactions() == int(np.sum(ot.gcount * nj))
     assert ot.interactions() >= oracle.pair_count(ps.x, ps.y, ps.z, ps.params.r_cut)
+
+
+@pytest.mark.parametrize("name", ["uniform", "clustered", "tight"])
+@pytest.mark.parametrize("theta", [0.5, 1.0])
+def test_list_coverage_centre_of_mass_mac(name, theta):
+    """Centre-of-mass opening criterion: same coverage rules, every accepted
+    cell within theta of its centre of mass."""
+    ps = _sets()[name]
+    _coverage_check(ps, theta, n_check_groups=40, mac=1)
+
+
+def test_centre_of_mass_mac_theta0_and_accuracy():
+    ps = synth.small_clustered(6000, 62, r_cut=0.1, eps=2e-4, theta=0.7, per_halo=1000)
+    p0 = synth.Params(1.0, 0.1, 2e-4, 0.0, 64, 16, 0)
+    p1 = synth.Params(1.0, 0.1, 2e-4, 0.0, 64, 16, 1)
+    a, b = oracle.OracleTree(ps.x, ps.y, ps.z, ps.m, p0), oracle.OracleTree(ps.x, ps.y, ps.z, ps.m, p1)
+    for k in ("poff", "pidx", "noff", "nidx"):
+        assert np.array_equal(getattr(a.lists, k), getattr(b.lists, k))
+    # measuring to the expansion centre: the normwise error against the
+    # direct sum is no worse than with the geometric centre on this set
+    ref = oracle.brute_force(ps.x, ps.y, ps.z, ps.m, 1.0, 0.1, 2e-4)
+    for theta in (0.5, 0.8, 1.0):
+        e = []
+        for mac in (0, 1):
+            ot = oracle.OracleTree(ps.x, ps.y, ps.z, ps.m, synth.Params(1.0, 0.1, 2e-4, theta, 64, 16, mac))
+            e.append(oracle.relative_errors(ot.force(), ref)[1]["l2"])
+        assert e[1] <= 1.05 * e[0], (theta, e)
