@@ -52,6 +52,17 @@ enum srf_status {
     SRF_EMISMATCH = -5   /* tree, lists and params do not belong together          */
 };
 
+/* Opening criterion of srf_make_lists: a cell of side s is accepted as one
+ * monopole iff s^2 < theta^2 d^2, d the distance from the group's box to
+ * the cell's geometric centre (SRF_MAC_CENTRE, the default) or to its centre
+ * of mass (SRF_MAC_COM; the pruning by r_cut stays box to box).  With
+ * SRF_MAC_COM the decisions depend on the FP64 centres of mass, whose last
+ * bits depend on the summation order. */
+enum srf_mac {
+    SRF_MAC_CENTRE = 0,
+    SRF_MAC_COM = 1
+};
+
 enum srf_precision {
     SRF_FP32_REL = 0,    /* FP32 pair arithmetic on group-relative coordinates, FP64
                             positions, moments and per-particle accumulation         */
@@ -61,7 +72,7 @@ enum srf_precision {
 /* Parameters.  Valid ranges (else SRF_EINVAL):
  *   G finite; 0 < r_cut < 0.25; eps > 0 and finite; 0 <= theta <= 1;
  *   1 <= n_group <= 64; 1 <= n_leaf <= n_group; precision in srf_precision;
- *   compensated in {0, 1}. */
+ *   compensated in {0, 1}; mac in srf_mac. */
 typedef struct {
     double G;            /* gravitational constant                                  */
     double r_cut;        /* cutoff radius, box units (box side = 1)                 */
@@ -73,6 +84,8 @@ typedef struct {
     int32_t compensated; /* 1: compensated (Kahan) FP32 partial sums over each list
                             tile of the SRF_FP32_REL force kernel; 0: plain FP32.
                             No effect on the FP64 kernel or on the adjoint.       */
+    int32_t mac;         /* enum srf_mac: the point the opening criterion measures
+                            to (srf_make_lists; must match the lists after)       */
 } srf_params;
 
 typedef struct srf_tree srf_tree;

@@ -23,13 +23,15 @@ import numpy as np
 import torch
 
 __all__ = [
-    "Params", "Tree", "Lists", "SrfError", "FP32_REL", "FP64", "lib", "lib_path", "tree_build", "make_lists",
+    "Params", "Tree", "Lists", "SrfError", "FP32_REL", "FP64", "MAC_CENTRE", "MAC_COM", "lib", "lib_path", "tree_build", "make_lists",
     "short_range_force", "short_range_adjoint", "short_range_potential", "short_range_quadrupole", "ShortRange", "short_range", "pm_force", "kick", "drift",
     "TreePMIntegrator", "set_kernel_timing", "last_kernel_ms",
 ]
 
 FP32_REL = 0
 FP64 = 1
+MAC_CENTRE = 0   # opening distance to the cell's geometric centre
+MAC_COM = 1      # ... to its centre of mass
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libsrf.so")
@@ -43,7 +45,8 @@ class SrfError(RuntimeError):
 
 class _CParams(C.Structure):
     _fields_ = [("G", C.c_double), ("r_cut", C.c_double), ("eps", C.c_double), ("theta", C.c_double),
-                ("n_group", C.c_int32), ("n_leaf", C.c_int32), ("precision", C.c_int32), ("compensated", C.c_int32)]
+                ("n_group", C.c_int32), ("n_leaf", C.c_int32), ("precision", C.c_int32), ("compensated", C.c_int32),
+                ("mac", C.c_int32)]
 
 
 @dataclass(frozen=True)
@@ -57,17 +60,18 @@ class Params:
     n_leaf: int = 16
     precision: int = FP32_REL
     compensated: int = 0
+    mac: int = MAC_CENTRE
 
     def c(self) -> _CParams:
         return _CParams(float(self.G), float(self.r_cut), float(self.eps), float(self.theta), int(self.n_group),
-                        int(self.n_leaf), int(self.precision), int(self.compensated))
+                        int(self.n_leaf), int(self.precision), int(self.compensated), int(self.mac))
 
     @staticmethod
     def of(p, precision: int | None = None, compensated: int | None = None) -> "Params":
         """Convert any object with G, r_cut, eps, theta, n_group, n_leaf."""
         prec = getattr(p, "precision", FP32_REL) if precision is None else precision
         comp = getattr(p, "compensated", 0) if compensated is None else compensated
-        return Params(p.G, p.r_cut, p.eps, p.theta, p.n_group, p.n_leaf, prec, comp)
+        return Params(p.G, p.r_cut, p.eps, p.theta, p.n_group, p.n_leaf, prec, comp, getattr(p, "mac", MAC_CENTRE))
 
 
 _lib = None

@@ -48,13 +48,15 @@ void validate(const srf_params* p) {
     if (p->n_leaf < 1 || p->n_leaf > p->n_group) srf::fail(SRF_EINVAL, "n_leaf must lie in [1, n_group]");
     if (p->precision != SRF_FP32_REL && p->precision != SRF_FP64) srf::fail(SRF_EINVAL, "unknown precision");
     if (p->compensated != 0 && p->compensated != 1) srf::fail(SRF_EINVAL, "compensated must be 0 or 1");
+    if (p->mac != SRF_MAC_CENTRE && p->mac != SRF_MAC_COM) srf::fail(SRF_EINVAL, "unknown mac");
 }
 
 void check_pair(const srf_tree* t, const srf_lists* l, const srf_params* p) {
     if (!t || !l) srf::fail(SRF_EINVAL, "tree or lists is NULL");
     validate(p);
     if (l->l.tree != &t->t) srf::fail(SRF_EMISMATCH, "lists were built from another tree");
-    if (p->r_cut != l->l.r_cut || p->theta != l->l.theta || p->n_group != t->t.n_group || p->n_leaf != t->t.n_leaf)
+    if (p->r_cut != l->l.r_cut || p->theta != l->l.theta || p->mac != l->l.mac || p->n_group != t->t.n_group ||
+        p->n_leaf != t->t.n_leaf)
         srf::fail(SRF_EMISMATCH, "params differ from those the tree and lists were built with");
 }
 
@@ -139,6 +141,7 @@ int srf_make_lists(const srf_tree* t, const srf_params* p, void* stream, srf_lis
         l.tree = &t->t;
         l.r_cut = p->r_cut;
         l.theta = p->theta;
+        l.mac = p->mac;
         l.n_group = p->n_group;
         l.n_leaf = p->n_leaf;
         l.stream = st;

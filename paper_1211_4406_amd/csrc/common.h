@@ -111,6 +111,7 @@ struct Lists {
     int64_t n_node_entries = 0;
     int64_t interactions = 0;
     double r_cut = 0, theta = 0;
+    int32_t mac = 0;
     int32_t n_group = 0, n_leaf = 0;
     hipStream_t stream = nullptr;
     DevBuf<int64_t> off;       // [ng+1] entry offsets per group

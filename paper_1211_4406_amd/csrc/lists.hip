@@ -15,6 +15,8 @@
 //   d2 = (e_x e_x + e_y e_y) + e_z e_z
 //   prune  iff d2(half = side/2) >= r_cut * r_cut
 //   accept iff side * side < (theta * theta) * d2(half = 0)
+// with cen_c the cell's geometric centre, or for the acceptance test of the
+// centre-of-mass criterion its centre of mass.
 #include "common.h"
 
 namespace srf {
@@ -65,16 +67,18 @@ __device__ __forceinline__ Cell decode(const uint4 r) {
     return k;
 }
 
-// 0: pruned, 1: accepted as a monopole, 2: leaf (expand), 3: open.
-__device__ __forceinline__ int classify(const Cell& k, const Frame& f, double rc2, double th2) {
+// 0: pruned, 1: accepted as a monopole, 2: leaf (expand), 3: open.  `mc`
+// is the point the acceptance test measures to (the geometric centre, or
+// the centre of mass with the centre-of-mass criterion).
+__device__ __forceinline__ int classify(const Cell& k, const double* mc, const Frame& f, double rc2, double th2) {
     double ex = axis_gap(k.c[0], f.cg[0], k.hs + f.hg[0]);
     double ey = axis_gap(k.c[1], f.cg[1], k.hs + f.hg[1]);
     double ez = axis_gap(k.c[2], f.cg[2], k.hs + f.hg[2]);
     double D2 = (ex * ex + ey * ey) + ez * ez;
     if (D2 >= rc2) return 0;
-    ex = axis_gap(k.c[0], f.cg[0], f.hg[0]);
-    ey = axis_gap(k.c[1], f.cg[1], f.hg[1]);
-    ez = axis_gap(k.c[2], f.cg[2], f.hg[2]);
+    ex = axis_gap(mc[0], f.cg[0], f.hg[0]);
+    ey = axis_gap(mc[1], f.cg[1], f.hg[1]);
+    ez = axis_gap(mc[2], f.cg[2], f.hg[2]);
     double d2 = (ex * ex + ey * ey) + ez * ez;
     if (k.side * k.side < th2 * d2) return 1;
     return k.leaf ? 2 : 3;
@@ -126,10 +130,12 @@ struct ItemWriter {
 // a second walk that stores the items of every group compactly at ioff).
 constexpr int64_t kSlot = 2048;
 
-template <int G, bool WRITE>
+template <int G, bool WRITE, bool COM>
 __global__ __launch_bounds__(128) void k_lists(int64_t ng, const double* __restrict__ glo,
                                                const double* __restrict__ ghi, const int32_t* __restrict__ gcount,
                                                const uint4* __restrict__ pack, const NodeRange* __restrict__ rng,
+                                               const double* __restrict__ nX, const double* __restrict__ nY,
+                                               const double* __restrict__ nZ,
                                                int64_t nn, double rc2, double th2, int64_t* __restrict__ cnt,
                                                int64_t* __restrict__ icnt, unsigned long long* __restrict__ totals,
                                                const int64_t* __restrict__ ioff, int32_t* __restrict__ items) {
@@ -160,10 +166,16 @@ __global__ __launch_bounds__(128) void k_lists(int64_t ng, const double* __restr
         const uint64_t act = (masks >> (k.level * G)) & full;
         uint64_t open = 0;
         if (act) {
+            double mcen[3] = {k.c[0], k.c[1], k.c[2]};
+            if (COM) {
+                mcen[0] = nX[i];
+                mcen[1] = nY[i];
+                mcen[2] = nZ[i];
+            }
 #pragma unroll
             for (int q = 0; q < G; ++q) {
                 if (!((act >> q) & 1ull)) continue;
-                const int cls = classify(k, f[q], rc2, th2);
+                const int cls = classify(k, mcen, f[q], rc2, th2);
                 if (cls == 3) {
                     open |= 1ull << q;
                 } else if (cls == 1) {
@@ -295,9 +307,16 @@ void build_lists(const Tree& t, Lists& l, hipStream_t st) {
     const int B = 128;
     constexpr int G = kGroupsPerThread;
     const int64_t nthreads = (ng + G - 1) / G;
-    hipLaunchKernelGGL((k_lists<G, false>), dim3(grid_for(nthreads, B, 1 << 30)), dim3(B), 0, st, ng, t.glo.get(),
-                       t.ghi.get(), t.gcount.get(), t.pack.get(), t.range.get(), t.n_nodes, rc2, th2, l.off.get(),
-                       icnt.get(), totals.get(), (const int64_t*)nullptr, slots.get());
+    if (l.mac == SRF_MAC_COM)
+        hipLaunchKernelGGL((k_lists<G, false, true>), dim3(grid_for(nthreads, B, 1 << 30)), dim3(B), 0, st, ng,
+                           t.glo.get(), t.ghi.get(), t.gcount.get(), t.pack.get(), t.range.get(), t.nX.get(),
+                           t.nY.get(), t.nZ.get(), t.n_nodes, rc2, th2, l.off.get(), icnt.get(), totals.get(),
+                           (const int64_t*)nullptr, slots.get());
+    else
+        hipLaunchKernelGGL((k_lists<G, false, false>), dim3(grid_for(nthreads, B, 1 << 30)), dim3(B), 0, st, ng,
+                           t.glo.get(), t.ghi.get(), t.gcount.get(), t.pack.get(), t.range.get(), t.nX.get(),
+                           t.nY.get(), t.nZ.get(), t.n_nodes, rc2, th2, l.off.get(), icnt.get(), totals.get(),
+                           (const int64_t*)nullptr, slots.get());
     SRF_HIP(hipGetLastError());
     exclusive_scan_i64(l.off.get(), ng, true, st);
     unsigned long long h[4];
@@ -324,10 +343,16 @@ void build_lists(const Tree& t, Lists& l, hipStream_t st) {
     SRF_HIP(hipMemcpyAsync(&n_items, icnt.get() + ng, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     SRF_HIP(hipStreamSynchronize(st));
     DevBuf<int32_t> items(n_items > 0 ? n_items : 1, st);
-    hipLaunchKernelGGL((k_lists<G, true>), dim3(grid_for(nthreads, B, 1 << 30)), dim3(B), 0, st, ng, t.glo.get(),
-                       t.ghi.get(), t.gcount.get(), t.pack.get(), t.range.get(), t.n_nodes, rc2, th2,
-                       (int64_t*)nullptr, (int64_t*)nullptr, (unsigned long long*)nullptr, (const int64_t*)icnt.get(),
-                       items.get());
+    if (l.mac == SRF_MAC_COM)
+        hipLaunchKernelGGL((k_lists<G, true, true>), dim3(grid_for(nthreads, B, 1 << 30)), dim3(B), 0, st, ng,
+                           t.glo.get(), t.ghi.get(), t.gcount.get(), t.pack.get(), t.range.get(), t.nX.get(),
+                           t.nY.get(), t.nZ.get(), t.n_nodes, rc2, th2, (int64_t*)nullptr, (int64_t*)nullptr,
+                           (unsigned long long*)nullptr, (const int64_t*)icnt.get(), items.get());
+    else
+        hipLaunchKernelGGL((k_lists<G, true, false>), dim3(grid_for(nthreads, B, 1 << 30)), dim3(B), 0, st, ng,
+                           t.glo.get(), t.ghi.get(), t.gcount.get(), t.pack.get(), t.range.get(), t.nX.get(),
+                           t.nY.get(), t.nZ.get(), t.n_nodes, rc2, th2, (int64_t*)nullptr, (int64_t*)nullptr,
+                           (unsigned long long*)nullptr, (const int64_t*)icnt.get(), items.get());
     SRF_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_expand, dim3((unsigned)ng), dim3(64), 0, st, ng, (int64_t)0, (const int64_t*)nullptr,
                        icnt.get(), items.get(), t.range.get(), l.off.get(), l.ent.get());

@@ -45,7 +45,7 @@ def _build_status(**kw):
 @pytest.mark.parametrize("kw", [dict(r_cut=0.25), dict(r_cut=0.0), dict(r_cut=float("nan")), dict(eps=0.0),
                                 dict(eps=-1.0), dict(theta=-0.1), dict(theta=1.5), dict(n_group=65),
                                 dict(n_group=0), dict(n_leaf=0), dict(n_group=8, n_leaf=9), dict(precision=3),
-                                dict(G=float("inf")), dict(compensated=2)])
+                                dict(G=float("inf")), dict(compensated=2), dict(mac=2)])
 def test_invalid_params_rejected_on_host(kw):
     st, msg, h = _build_status(**kw)
     assert st == -1 and msg and h is None

@@ -6,6 +6,7 @@ Tolerances: FP32 group-relative force vs the same-list FP64 oracle, rms
 relative error <= 1e-5; all-FP64 kernel <= 1e-12; adjoint likewise.
 """
 import ctypes as C
+import dataclasses
 import os
 import sys
 
@@ -247,6 +248,72 @@ def test_compensated_force_option():
     with pytest.raises(srf.SrfError) as e:
         srf.short_range_force(tree, lists, srf.Params.of(ps.params, srf.FP32_REL, 2))
     assert e.value.status == -1
+
+
+@pytest.mark.parametrize("name", ["cfg1-uniform-4096", "clustered-20000", "clustered-tight-12000"])
+@pytest.mark.parametrize("theta", [0.5, 1.0])
+def test_centre_of_mass_mac(name, theta):
+    """Centre-of-mass opening criterion.  Its decisions use the FP64 centres
+    of mass, which the GPU and the oracle sum in different orders (they agree
+    to about 1e-16 per particle of the cell), so a decision may flip where
+    side^2 and theta^2 d^2 agree to that level.  Lists must be identical
+    except in groups where every differing entry lies under a cell whose
+    criterion is that close to the threshold (by the oracle's centres of
+    mass); forces must match the oracle on the groups with identical lists."""
+    ps = case_sets()[name]
+    params = synth.Params(1.0, ps.params.r_cut, ps.params.eps, theta, 64, 16, srf.MAC_COM)
+    say(f"[gpu] centre-of-mass MAC {name} theta={theta} n={ps.n}")
+    ot = oracle.OracleTree(ps.x, ps.y, ps.z, ps.m, params)
+    tree, lists, a32 = gpu_forward(ps, params, srf.FP32_REL)
+    L, R = lists.export(), ot.lists
+    t = ot.tree
+    same = np.ones(ot.n_groups, bool)
+    for g in range(ot.n_groups):
+        pg, pr = L["pidx"][L["poff"][g]:L["poff"][g + 1]], R.pidx[R.poff[g]:R.poff[g + 1]]
+        ng_, nr = L["nidx"][L["noff"][g]:L["noff"][g + 1]], R.nidx[R.noff[g]:R.noff[g + 1]]
+        if np.array_equal(pg, pr) and np.array_equal(ng_, nr):
+            continue
+        same[g] = False
+        cg = 0.5 * (ot.lo[g] + ot.hi[g])
+        hg = 0.5 * (ot.hi[g] - ot.lo[g])
+        nd = np.setxor1d(ng_, nr)
+        border = []
+        for c in nd:
+            side = 2.0 ** -int(t.level[c])
+            dd = np.abs(ot.X[c] - cg)
+            dd = np.minimum(dd, 1 - dd)
+            gap = np.maximum(dd - hg, 0)
+            if abs(side * side - theta * theta * np.sum(gap * gap)) <= 1e-9 * side * side:
+                border.append(int(c))
+        assert border, f"group {g}: differing cells, none at the threshold"
+        def under(c):
+            while c >= 0:
+                if c in border:
+                    return True
+                c = int(t.parent[c])
+            return False
+        assert all(under(int(c)) for c in nd)
+        for s_ in np.setxor1d(pg, pr):
+            assert any(t.first[c] <= s_ < t.first[c] + t.count[c] for c in border)
+    say(f"    groups with identical lists: {same.sum()} of {ot.n_groups}")
+    assert (~same).sum() <= max(1, ot.n_groups // 1000)
+    ref = ot.force()
+    keep = np.zeros(ps.n, bool)
+    for g in np.flatnonzero(same):
+        keep[ot.perm[ot.gfirst[g]:ot.gfirst[g] + ot.gcount[g]]] = True
+    st = rel_stats(a32[keep], ref[keep])
+    say(f"    fp32 vs oracle: {st}")
+    assert st["rms"] <= FP32_TOL
+    # the geometric-centre lists differ from these at theta > 0
+    p0 = srf.Params.of(params)
+    lists0 = srf.make_lists(tree, dataclasses.replace(p0, mac=srf.MAC_CENTRE))
+    if theta > 0 and R.nidx.size:
+        assert lists0.info()["n_node_entries"] != lists.info()["n_node_entries"] or \
+            not np.array_equal(lists0.export()["nidx"], L["nidx"])
+    # lists built with one criterion are refused with the other
+    with pytest.raises(srf.SrfError) as e:
+        srf.short_range_force(tree, lists0, p0)
+    assert e.value.status == -5
 
 
 def test_domain_errors_reported():
