@@ -72,27 +72,45 @@ __device__ __forceinline__ int32_t lower_digit(const uint64_t* __restrict__ keys
     return lo;
 }
 
-// Children of the cells of one level: octant boundaries and counts.
-__global__ void k_child_count(int64_t begin, int64_t m, int level, int32_t n_leaf, const int32_t* __restrict__ first,
-                              const int32_t* __restrict__ count, const uint64_t* __restrict__ keys,
-                              int32_t* __restrict__ bnd, int32_t* __restrict__ cnt) {
-    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (k >= m) return;
-    int64_t c = begin + k;
-    int32_t f = first[c], nc = count[c];
-    bool split = (level == 0) || (level < kMaxLevel && nc > n_leaf);
-    int32_t* b = bnd + k * 9;
-    if (!split) {
-        cnt[k] = 0;
-        return;
+// Children of the cells of one level: octant boundaries and counts.  Eight
+// threads per cell (32 cells per block of 256): thread o finds boundary o
+// (the first index whose level-(L+1) digit is >= o; o = 0 is the cell's
+// first index), so each thread's chain of dependent loads is one binary
+// search; thread 0 then counts the non-empty octants.
+__global__ __launch_bounds__(256) void k_child_count(int64_t begin, int64_t m, int level, int32_t n_leaf,
+                                                     const int32_t* __restrict__ first,
+                                                     const int32_t* __restrict__ count,
+                                                     const uint64_t* __restrict__ keys, int32_t* __restrict__ bnd,
+                                                     int32_t* __restrict__ cnt) {
+    __shared__ int32_t sb[256 + 32];
+    const int64_t k = blockIdx.x * 32ll + (threadIdx.x >> 3);
+    const int o = threadIdx.x & 7;
+    const int slot = (threadIdx.x >> 3) * 9;
+    bool split = false;
+    if (k < m) {
+        const int64_t c = begin + k;
+        const int32_t f = first[c], nc = count[c];
+        split = (level == 0) || (level < kMaxLevel && nc > n_leaf);
+        if (split) {
+            const int shift = 3 * (kMaxLevel - (level + 1));
+            const int32_t bo = o == 0 ? f : lower_digit(keys, f, f + nc, shift, (uint32_t)o);
+            sb[slot + o] = bo;
+            bnd[k * 9 + o] = bo;
+            if (o == 0) {
+                sb[slot + 8] = f + nc;
+                bnd[k * 9 + 8] = f + nc;
+            }
+        }
     }
-    const int shift = 3 * (kMaxLevel - (level + 1));
-    b[0] = f;
-    b[8] = f + nc;
-    int nz = 0;
-    for (uint32_t o = 1; o < 8; ++o) b[o] = lower_digit(keys, f, f + nc, shift, o);
-    for (int o = 0; o < 8; ++o) nz += (b[o + 1] > b[o]) ? 1 : 0;
-    cnt[k] = nz;
+    __syncthreads();
+    if (k < m && o == 0) {
+        int nz = 0;
+        if (split) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) nz += (sb[slot + q + 1] > sb[slot + q]) ? 1 : 0;
+        }
+        cnt[k] = nz;
+    }
 }
 
 __global__ void k_child_write(int64_t begin, int64_t m, int64_t out_begin, int level, const int32_t* __restrict__ bnd,
@@ -354,8 +372,8 @@ void build_cells_and_groups(Tree& t, int32_t* d_flag, hipStream_t st) {
     for (int L = 0; L < kMaxLevel; ++L) {
         const int64_t m = cur_end - cur_begin;
         DevBuf<int32_t> bnd(m * 9, st), cnt(m + 1, st);
-        hipLaunchKernelGGL(k_child_count, dim3(grid_for(m, B, 1 << 30)), dim3(B), 0, st, cur_begin, m, L, t.n_leaf,
-                           b.first.get(), b.count.get(), t.keys.get(), bnd.get(), cnt.get());
+        hipLaunchKernelGGL(k_child_count, dim3(grid_for(m, 32, 1 << 30)), dim3(256), 0, st, cur_begin, m, L,
+                           t.n_leaf, b.first.get(), b.count.get(), t.keys.get(), bnd.get(), cnt.get());
         SRF_HIP(hipGetLastError());
         exclusive_scan_i32(cnt.get(), m, true, st);
         const int64_t c = read_i32(cnt.get() + m, st);
