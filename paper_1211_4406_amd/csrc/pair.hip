@@ -178,8 +178,10 @@ __device__ __forceinline__ T far_r(T r2, T s2, T rinv, const Coef<T>& c) {
 template <class T, class V4, bool NEAR, bool COMP, bool RS>
 __device__ __forceinline__ void pair_force(const V4& p, T xi, T yi, T zi, const Coef<T>& c, Acc<T, COMP>& acc) {
     const T dx = p.x - xi, dy = p.y - yi, dz = p.z - zi;
-    const T r2 = fma_(dz, dz, fma_(dy, dy, dx * dx));
-    const T s2 = r2 + c.eps2;
+    // the far path with r from s needs no unsoftened r^2: s^2 directly
+    const bool direct = !NEAR && RS;
+    const T r2 = direct ? T(0) : fma_(dz, dz, fma_(dy, dy, dx * dx));
+    const T s2 = direct ? fma_(dz, dz, fma_(dy, dy, fma_(dx, dx, c.eps2))) : r2 + c.eps2;
     const T rinv = rsqrt_(s2);
     const T r = NEAR ? sqrt_(r2) : far_r<T, RS>(r2, s2, rinv, c);
     T f;
