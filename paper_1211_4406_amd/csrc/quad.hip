@@ -18,9 +18,9 @@
 // coefficients, and 0 at and beyond r_cut through the clamp of t.
 //
 // Three kernels: mark the cells that occur in some list, their second
-// moments (one wave per marked cell, FP64), and the correction pass (one
-// wave per group, targets in lanes, the list's cells compacted into LDS in
-// chunks of 256 entries), which adds G times the term to the accelerations.
+// moments (FP64, 64 cells per wave), and the correction pass (one wave per
+// group, targets in lanes, the list's cells compacted into LDS in chunks of
+// 256 entries), which adds G times the term to the accelerations.
 #include "common.h"
 
 namespace srf {
@@ -35,6 +35,7 @@ struct QCoef {
     T E0, E1, E2;                  // -k^2 H on [1,2] / t^4
     T F0, F1, F2;                  // k^4 H'/xi on [1,2] / t^3: F0 / r + F1 + F2 r
     T k, eps2, rh2;
+    T three, six, fifteen;         // held in registers (not inline constants)
 };
 
 template <class T>
@@ -70,6 +71,9 @@ QCoef<T> make_qcoef(double rc, double eps) {
     c.k = (T)k;
     c.eps2 = (T)(eps * eps);
     c.rh2 = (T)(0.25 * rc * rc);
+    c.three = (T)3;
+    c.six = (T)6;
+    c.fifteen = (T)15;
     return c;
 }
 
@@ -77,6 +81,31 @@ __device__ __forceinline__ float q_rsqrt(float x) { return __builtin_amdgcn_rsqf
 __device__ __forceinline__ double q_rsqrt(double x) { return 1.0 / sqrt(x); }
 __device__ __forceinline__ float q_sat(float x) { return fminf(fmaxf(x, 0.0f), 1.0f); }
 __device__ __forceinline__ double q_sat(double x) { return fmin(fmax(x, 0.0), 1.0); }
+
+// Keep a loop-invariant value in a vector register (the empty asm makes it
+// opaque), so that the pair arithmetic reads VGPR operands only.
+__device__ __forceinline__ float q_pin(float x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+__device__ __forceinline__ double q_pin(double x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+template <class T>
+__device__ __forceinline__ QCoef<T> q_pinned(const QCoef<T>& a) {
+    QCoef<T> c;
+    c.A3 = q_pin(a.A3); c.A5 = q_pin(a.A5); c.A6 = q_pin(a.A6); c.A7 = q_pin(a.A7); c.A8 = q_pin(a.A8);
+    c.B1 = q_pin(a.B1); c.B3 = q_pin(a.B3); c.B4 = q_pin(a.B4); c.B5 = q_pin(a.B5); c.B6 = q_pin(a.B6);
+    c.J0 = q_pin(a.J0); c.J1 = q_pin(a.J1); c.J2 = q_pin(a.J2); c.J3 = q_pin(a.J3); c.J4 = q_pin(a.J4);
+    c.C0 = q_pin(a.C0); c.C1 = q_pin(a.C1); c.C2 = q_pin(a.C2); c.C3 = q_pin(a.C3);
+    c.E0 = q_pin(a.E0); c.E1 = q_pin(a.E1); c.E2 = q_pin(a.E2);
+    c.F0 = q_pin(a.F0); c.F1 = q_pin(a.F1); c.F2 = q_pin(a.F2);
+    c.k = q_pin(a.k); c.eps2 = q_pin(a.eps2); c.rh2 = q_pin(a.rh2);
+    c.three = q_pin(a.three); c.six = q_pin(a.six); c.fifteen = q_pin(a.fifteen);
+    return c;
+}
 
 template <class T>
 struct QV4 {};
@@ -101,38 +130,66 @@ __global__ void k_mark_cells(int64_t n_entries, const int32_t* __restrict__ ent,
     }
 }
 
-// S_c = sum_k m_k (x_k - X_c)(x_k - X_c)^T as (xx, yy, zz, xy, xz, yz), one
-// wave per marked cell; the lanes' partial sums are combined in a fixed
-// order, so the result is deterministic.  A cell never straddles the
+// S_c = sum_k m_k (x_k - X_c)(x_k - X_c)^T as (xx, yy, zz, xy, xz, yz) for
+// the marked cells.  One wave takes 64 consecutive cells: a cell of at most
+// kSmallCell particles is summed by its own lane; each larger one is summed
+// by the whole wave (lanes stride over its particles, partial sums combined
+// in a fixed order).  Deterministic either way.  A cell never straddles the
 // periodic boundary, so no image is taken.
+constexpr int32_t kSmallCell = 64;
+
+__device__ __forceinline__ void add_second(double (&a)[6], double m, double dx, double dy, double dz) {
+    a[0] += m * dx * dx;
+    a[1] += m * dy * dy;
+    a[2] += m * dz * dz;
+    a[3] += m * dx * dy;
+    a[4] += m * dx * dz;
+    a[5] += m * dy * dz;
+}
+
 __global__ __launch_bounds__(64) void k_second_moments(int64_t nn, const NodeRange* __restrict__ range,
                                                        const int32_t* __restrict__ used,
                                                        const double* __restrict__ px, const double* __restrict__ py,
                                                        const double* __restrict__ pz, const double* __restrict__ pm,
                                                        const double* __restrict__ nX, const double* __restrict__ nY,
                                                        const double* __restrict__ nZ, double* __restrict__ S) {
-    const int64_t c = blockIdx.x;
-    if (c >= nn || !used[c]) return;
-    const NodeRange rg = range[c];
-    const double X = nX[c], Y = nY[c], Z = nZ[c];
-    double a[6] = {0, 0, 0, 0, 0, 0};
-    for (int32_t k = rg.first + threadIdx.x; k < rg.first + rg.count; k += 64) {
-        const double dx = px[k] - X, dy = py[k] - Y, dz = pz[k] - Z, m = pm[k];
-        a[0] += m * dx * dx;
-        a[1] += m * dy * dy;
-        a[2] += m * dz * dz;
-        a[3] += m * dx * dy;
-        a[4] += m * dx * dz;
-        a[5] += m * dy * dz;
+    const int lane = threadIdx.x;
+    const int64_t c = blockIdx.x * 64ll + lane;
+    const bool on = c < nn && used[c];
+    NodeRange rg;
+    rg.first = rg.count = 0;
+    double X = 0, Y = 0, Z = 0;
+    if (on) {
+        rg = range[c];
+        X = nX[c];
+        Y = nY[c];
+        Z = nZ[c];
     }
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) a[q] += __shfl_xor(a[q], o, 64);
-    }
-    if (threadIdx.x == 0) {
+    // small cells: one lane each
+    if (on && rg.count <= kSmallCell) {
+        double a[6] = {0, 0, 0, 0, 0, 0};
+        for (int32_t k = rg.first; k < rg.first + rg.count; ++k) add_second(a, pm[k], px[k] - X, py[k] - Y, pz[k] - Z);
 #pragma unroll
         for (int q = 0; q < 6; ++q) S[c * 6 + q] = a[q];
+    }
+    // large cells: the whole wave, one after another
+    uint64_t big = __ballot(on && rg.count > kSmallCell);
+    while (big) {
+        const int l = __ffsll((unsigned long long)big) - 1;
+        big &= big - 1;
+        const int32_t f = __shfl(rg.first, l, 64), n = __shfl(rg.count, l, 64);
+        const double bx = __shfl(X, l, 64), by = __shfl(Y, l, 64), bz = __shfl(Z, l, 64);
+        double a[6] = {0, 0, 0, 0, 0, 0};
+        for (int32_t k = f + lane; k < f + n; k += 64) add_second(a, pm[k], px[k] - bx, py[k] - by, pz[k] - bz);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) a[q] += __shfl_xor(a[q], o, 64);
+        }
+        if (lane == l) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) S[c * 6 + q] = a[q];
+        }
     }
 }
 
@@ -160,8 +217,8 @@ __device__ __forceinline__ void quad_pair(const V4& p, const V4& s1, const V2& s
     const bool inner = r2 < c.rh2;
     const T g = inner ? g1 : g2, h = inner ? h1 : h2, j = inner ? j1 : j2;
     const T s3 = u * rinv;
-    const T psi = s3 * (h - T(3) * u * g);
-    const T chi = s3 * (j - u * (T(6) * h - T(15) * u * g));
+    const T psi = s3 * (h - c.three * u * g);
+    const T chi = s3 * (j - u * (c.six * h - c.fifteen * u * g));
     const T sx = s1.x * dx + s1.w * dy + s2.x * dz;
     const T sy = s1.w * dx + s1.y * dy + s2.y * dz;
     const T sz = s2.x * dx + s2.y * dy + s1.z * dz;
@@ -199,6 +256,7 @@ __global__ __launch_bounds__(64) void k_quadrupole(const int32_t* __restrict__ g
     const int32_t me = first + (lane < cnt ? lane : 0);
     const T xi = (T)(px[me] - cx), yi = (T)(py[me] - cy), zi = (T)(pz[me] - cz);
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const QCoef<T> cq = q_pinned(c);
     double sx = 0, sy = 0, sz = 0;
     const int64_t e0 = off[g], e1 = off[g + 1];
     for (int64_t tb = e0; tb < e1; tb += kQChunk) {
@@ -238,7 +296,7 @@ __global__ __launch_bounds__(64) void k_quadrupole(const int32_t* __restrict__ g
         }
         __syncthreads();
         T ox = 0, oy = 0, oz = 0;
-        for (int k = 0; k < nc; ++k) quad_pair<T, V4, V2>(cp[k], cs1[k], cs2[k], xi, yi, zi, c, ox, oy, oz);
+        for (int k = 0; k < nc; ++k) quad_pair<T, V4, V2>(cp[k], cs1[k], cs2[k], xi, yi, zi, cq, ox, oy, oz);
         sx += (double)ox;
         sy += (double)oy;
         sz += (double)oz;
@@ -263,7 +321,7 @@ void launch_quadrupole(const Tree& t, const Lists& l, const srf_params& p, doubl
         hipLaunchKernelGGL(k_mark_cells, dim3(grid_for(l.n_entries, 256, 1 << 16)), dim3(256), 0, st, l.n_entries,
                            l.ent.get(), used.get());
     SRF_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_second_moments, dim3((unsigned)nn), dim3(64), 0, st, nn, t.range.get(), used.get(),
+    hipLaunchKernelGGL(k_second_moments, dim3((unsigned)((nn + 63) / 64)), dim3(64), 0, st, nn, t.range.get(), used.get(),
                        t.px.get(), t.py.get(), t.pz.get(), t.pm.get(), t.nX.get(), t.nY.get(), t.nZ.get(), S.get());
     SRF_HIP(hipGetLastError());
     const unsigned ng = (unsigned)t.n_groups;
