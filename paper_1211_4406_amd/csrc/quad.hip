@@ -20,7 +20,8 @@
 // Three kernels: mark the cells that occur in some list, their second
 // moments (FP64, 64 cells per wave), and the correction pass (one wave per
 // group, targets in lanes, the list's cells compacted into LDS in chunks of
-// 256 entries), which adds G times the term to the accelerations.
+// 256 entries, split near/far as in the force kernel), which adds G times
+// the term to the accelerations.
 #include "common.h"
 
 namespace srf {
@@ -195,7 +196,9 @@ __global__ __launch_bounds__(64) void k_second_moments(int64_t nn, const NodeRan
 
 // Term of one cell (offset p.xyz from the group centre, p.w = tr(S) / 2,
 // s1 = (xx, yy, zz, xy), s2 = (xz, yz)) on the target at (xi, yi, zi).
-template <class T, class V4, class V2>
+// Without NEAR the cell lies at xi >= 1 from every target of the group and
+// only the [1, 2] forms are evaluated.
+template <class T, class V4, class V2, bool NEAR>
 __device__ __forceinline__ void quad_pair(const V4& p, const V4& s1, const V2& s2, T xi, T yi, T zi,
                                           const QCoef<T>& c, T& ox, T& oy, T& oz) {
     const T dx = p.x - xi, dy = p.y - yi, dz = p.z - zi;
@@ -204,18 +207,22 @@ __device__ __forceinline__ void quad_pair(const V4& p, const V4& s1, const V2& s
     const T u = rinv * rinv;
     const T ir = r2 > T(0) ? q_rsqrt(r2) : T(0);   // 1 / r (an accepted cell is never at r = 0)
     const T r = r2 * ir;
-    // [0, 1] forms
-    const T g1 = T(1) + r2 * r * (c.A3 + r2 * (c.A5 + r * (c.A6 + r * (c.A7 + r * c.A8))));
-    const T h1 = r * (c.B1 + r2 * (c.B3 + r * (c.B4 + r * (c.B5 + r * c.B6))));
-    const T j1 = c.J0 * ir + r * (c.J1 + r * (c.J2 + r * (c.J3 + r * c.J4)));
     // [1, 2] forms
     const T t = q_sat(T(2) - c.k * r);
     const T t2 = t * t, t3 = t2 * t, t4 = t2 * t2;
-    const T g2 = t4 * t * (c.C0 + r * (c.C1 + r * (c.C2 + r * c.C3)));
-    const T h2 = -t4 * (c.E0 + r * (c.E1 + r * c.E2));
-    const T j2 = t3 * (c.F0 * ir + c.F1 + c.F2 * r);
-    const bool inner = r2 < c.rh2;
-    const T g = inner ? g1 : g2, h = inner ? h1 : h2, j = inner ? j1 : j2;
+    T g = t4 * t * (c.C0 + r * (c.C1 + r * (c.C2 + r * c.C3)));
+    T h = -t4 * (c.E0 + r * (c.E1 + r * c.E2));
+    T j = t3 * (c.F0 * ir + c.F1 + c.F2 * r);
+    if (NEAR) {
+        // [0, 1] forms
+        const T g1 = T(1) + r2 * r * (c.A3 + r2 * (c.A5 + r * (c.A6 + r * (c.A7 + r * c.A8))));
+        const T h1 = r * (c.B1 + r2 * (c.B3 + r * (c.B4 + r * (c.B5 + r * c.B6))));
+        const T j1 = c.J0 * ir + r * (c.J1 + r * (c.J2 + r * (c.J3 + r * c.J4)));
+        const bool inner = r2 < c.rh2;
+        g = inner ? g1 : g;
+        h = inner ? h1 : h;
+        j = inner ? j1 : j;
+    }
     const T s3 = u * rinv;
     const T psi = s3 * (h - c.three * u * g);
     const T chi = s3 * (j - u * (c.six * h - c.fifteen * u * g));
@@ -240,7 +247,7 @@ __global__ __launch_bounds__(64) void k_quadrupole(const int32_t* __restrict__ g
                                                    const double* __restrict__ py, const double* __restrict__ pz,
                                                    const double* __restrict__ nX, const double* __restrict__ nY,
                                                    const double* __restrict__ nZ, const double* __restrict__ S,
-                                                   QCoef<T> c, double G, double* __restrict__ ax,
+                                                   QCoef<T> c, double far2, double G, double* __restrict__ ax,
                                                    double* __restrict__ ay, double* __restrict__ az, int64_t os) {
     using V4 = typename QV4<T>::type;
     using V2 = typename QV2<T>::type;
@@ -253,6 +260,9 @@ __global__ __launch_bounds__(64) void k_quadrupole(const int32_t* __restrict__ g
     const double cx = (glo[g * 3 + 0] + ghi[g * 3 + 0]) * 0.5;
     const double cy = (glo[g * 3 + 1] + ghi[g * 3 + 1]) * 0.5;
     const double cz = (glo[g * 3 + 2] + ghi[g * 3 + 2]) * 0.5;
+    const double hx = (ghi[g * 3 + 0] - glo[g * 3 + 0]) * 0.5;
+    const double hy = (ghi[g * 3 + 1] - glo[g * 3 + 1]) * 0.5;
+    const double hz = (ghi[g * 3 + 2] - glo[g * 3 + 2]) * 0.5;
     const int32_t me = first + (lane < cnt ? lane : 0);
     const T xi = (T)(px[me] - cx), yi = (T)(py[me] - cy), zi = (T)(pz[me] - cz);
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -262,20 +272,32 @@ __global__ __launch_bounds__(64) void k_quadrupole(const int32_t* __restrict__ g
     for (int64_t tb = e0; tb < e1; tb += kQChunk) {
         const int len = (int)((e1 - tb) < kQChunk ? (e1 - tb) : kQChunk);
         __syncthreads();
-        int nc = 0;
+        // cells compacted: near ones from the front, far ones (distance from
+        // the centre of mass to the group box >= r_cut / 2) from the back
+        int nnear = 0, nfar = 0;
         for (int k0 = 0; k0 < len; k0 += 64) {
             const int k = k0 + lane;
             const int32_t v = k < len ? ent[tb + k] : 0;
             const bool cell = v < 0;
-            const uint64_t mc = __ballot(cell);
+            double rx = 0, ry = 0, rz = 0;
+            bool far = false;
+            int64_t q = 0;
             if (cell) {
-                const int64_t q = -(int64_t)v - 1;
-                double rx = nX[q] - cx, ry = nY[q] - cy, rz = nZ[q] - cz;
+                q = -(int64_t)v - 1;
+                rx = nX[q] - cx;
+                ry = nY[q] - cy;
+                rz = nZ[q] - cz;
                 rx -= rint(rx);
                 ry -= rint(ry);
                 rz -= rint(rz);
+                const double ex = fmax(fabs(rx) - hx, 0.0), ey = fmax(fabs(ry) - hy, 0.0),
+                             ez = fmax(fabs(rz) - hz, 0.0);
+                far = ex * ex + ey * ey + ez * ez >= far2;
+            }
+            const uint64_t mn = __ballot(cell && !far), mf = __ballot(cell && far);
+            if (cell) {
                 const double* s = S + q * 6;
-                const int pos = nc + __popcll(mc & lt);
+                const int pos = far ? kQChunk - 1 - (nfar + __popcll(mf & lt)) : nnear + __popcll(mn & lt);
                 V4 a, b;
                 V2 d;
                 a.x = (T)rx;
@@ -292,11 +314,15 @@ __global__ __launch_bounds__(64) void k_quadrupole(const int32_t* __restrict__ g
                 cs1[pos] = b;
                 cs2[pos] = d;
             }
-            nc += __popcll(mc);
+            nnear += __popcll(mn);
+            nfar += __popcll(mf);
         }
         __syncthreads();
         T ox = 0, oy = 0, oz = 0;
-        for (int k = 0; k < nc; ++k) quad_pair<T, V4, V2>(cp[k], cs1[k], cs2[k], xi, yi, zi, cq, ox, oy, oz);
+        for (int k = 0; k < nnear; ++k)
+            quad_pair<T, V4, V2, true>(cp[k], cs1[k], cs2[k], xi, yi, zi, cq, ox, oy, oz);
+        for (int k = kQChunk - nfar; k < kQChunk; ++k)
+            quad_pair<T, V4, V2, false>(cp[k], cs1[k], cs2[k], xi, yi, zi, cq, ox, oy, oz);
         sx += (double)ox;
         sy += (double)oy;
         sz += (double)oz;
@@ -329,12 +355,12 @@ void launch_quadrupole(const Tree& t, const Lists& l, const srf_params& p, doubl
         hipLaunchKernelGGL(k_quadrupole<double>, dim3(ng), dim3(64), 0, st, t.gfirst.get(), t.gcount.get(),
                            t.glo.get(), t.ghi.get(), l.off.get(), l.ent.get(), t.perm.get(), t.px.get(), t.py.get(),
                            t.pz.get(), t.nX.get(), t.nY.get(), t.nZ.get(), S.get(),
-                           make_qcoef<double>(p.r_cut, p.eps), p.G, ax, ay, az, os);
+                           make_qcoef<double>(p.r_cut, p.eps), 0.25 * p.r_cut * p.r_cut, p.G, ax, ay, az, os);
     } else {
         hipLaunchKernelGGL(k_quadrupole<float>, dim3(ng), dim3(64), 0, st, t.gfirst.get(), t.gcount.get(),
                            t.glo.get(), t.ghi.get(), l.off.get(), l.ent.get(), t.perm.get(), t.px.get(), t.py.get(),
                            t.pz.get(), t.nX.get(), t.nY.get(), t.nZ.get(), S.get(),
-                           make_qcoef<float>(p.r_cut, p.eps), p.G, ax, ay, az, os);
+                           make_qcoef<float>(p.r_cut, p.eps), 0.25 * p.r_cut * p.r_cut, p.G, ax, ay, az, os);
     }
     SRF_HIP(hipGetLastError());
 }
