@@ -20,7 +20,7 @@ Accuracy variants over the same lists: the short-range potential and the
 quadrupole term of the cells (second moments about the centre of mass).
 Plus the plain definition: brute-force minimum-image sums (O(N^2) and a
 cell list) and their gradient.  The long-range (PM) half of the force split
-and the Ewald sum that judges PP + PM live in ``oracle.pm`` (numpy, FP64).
+and the Ewald sum that checks PP + PM live in ``oracle.pm`` (numpy, FP64).
 
 Parity pins (tests/test_oracle_*.py): g against the S2-S2 cloud integral
 that defines it; brute force against O(N^2), momentum, translation and the

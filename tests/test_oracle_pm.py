@@ -1,4 +1,4 @@
-"""Pins of the long-range (PM) oracle and of the Ewald sum that judges it.
+"""Pins of the long-range (PM) oracle and of the Ewald sum that checks it.
 
 Ewald: independent of the splitting parameter, zero force on a simple cubic
 lattice, pairwise antisymmetry, and the Newtonian limit for a close pair.
