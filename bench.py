@@ -83,7 +83,8 @@ def parse():
     ap.add_argument("--cpu-sample-groups", type=int, default=1500)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-pm", action="store_true", help="skip the separate long-range (PM) timing")
-    ap.add_argument("--no-quad", action="store_true", help="skip the separate quadrupole-term timing")
+    ap.add_argument("--no-quad", action="store_true",
+                    help="skip the separate timings of the quadrupole term and the potential")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (for HBM counter calibration)")
     return ap.parse_args()
@@ -231,7 +232,7 @@ def main():
 
     # quadrupole term of the cells (accuracy variant), added to a force
     # already computed on the same lists: timed on its own
-    quad_info = None
+    quad_info = potential_info = None
     if not args.no_quad:
         tree = srf.tree_build(x, m, p)
         lists = srf.make_lists(tree, p)
@@ -249,7 +250,19 @@ def main():
         linfo = lists.info()
         quad_info = dict(ms=float(np.median(times)), cell_entries=int(linfo["n_node_entries"]),
                          steps="mark listed cells, FP64 second moments, FP32 correction pass over the lists")
-        del tree, lists, aq
+        # the short-range potential over the same lists
+        phi = srf.short_range_potential(tree, lists, p)
+        times = []
+        for _ in range(3):
+            e0, e1 = ev(), ev()
+            e0.record()
+            srf.short_range_potential(tree, lists, p, out=phi)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        potential_info = dict(ms=float(np.median(times)),
+                              interactions_per_s=linfo["interactions"] / (float(np.median(times)) * 1e-3))
+        del tree, lists, aq, phi
 
     # long-range (PM) half of the split on the mesh the paper's sizing gives
     # (N_PM = N/8 mesh cells, r_cut = 3 mesh spacings): timed separately, it
@@ -339,6 +352,7 @@ def main():
         "fp64_force": fp64,
         "pm": pm_info,
         "quadrupole": quad_info,
+        "potential": potential_info,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "gen_s": t_gen,
