@@ -58,6 +58,11 @@ def test_null_and_size_errors():
     assert L.srf_tree_build(0, None, None, None, 1, None, 1, C.byref(p), None, C.byref(h)) == -1
     assert L.srf_tree_build(5, None, None, None, 1, None, 1, C.byref(p), None, C.byref(h)) == -1
     assert L.srf_tree_build(5, None, None, None, 1, None, 1, None, None, C.byref(h)) == -1
+    # sizes past the 32-bit particle index are refused before any pointer is used
+    for n in (2 ** 31 - 2, 2 ** 31, 2 ** 40):
+        assert L.srf_tree_build(n, None, None, None, 1, None, 1, C.byref(p), None, C.byref(h)) == -1
+        assert "n must lie" in L.srf_last_error().decode()
+    assert L.srf_kick(-1, None, None, None, 1, None, None, None, 1, 0.1, None) == -1
     assert L.srf_make_lists(None, C.byref(p), None, C.byref(h)) == -1
     assert L.srf_short_range_force(None, None, C.byref(p), None, None, None, 1, None) == -1
     assert L.srf_short_range_potential(None, None, C.byref(p), None, 1, None) == -1
