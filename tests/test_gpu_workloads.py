@@ -6,7 +6,9 @@ same-list FP64 oracle (on sampled groups), and the tree error of the FP32
 force against the brute-force cutoff sum (on sampled particles).  Workload
 4: the FP32 and FP64 adjoint against the oracle's gradient, and against
 central differences of the oracle's fixed-structure forward (h = 1e-6 for
-positions, a relative 1e-6 for masses) on 64 random particles.
+positions, a relative 1e-6 for masses) on 64 random particles.  Workload 5
+(1.3e7 particles): the adjoint against those differences on 12 sampled
+particles, and translation invariance over all of them.
 
 Each test prints one JSON line of statistics.
 """
@@ -115,6 +117,72 @@ def _affected_groups(ot, s, group_of_entry_p, group_of_entry_n, anc_of):
     return np.array(sorted(gs), dtype=np.int64)
 
 
+def fd_errors(ot, ps, w, picks, grads, rms_x, rms_m, richardson=False):
+    """Central differences (h = 1e-6 in position, a relative 1e-6 in mass) of
+    L = sum_i w_i . a_i through the oracle's fixed-structure forward,
+    evaluated on the groups each picked particle affects, against each
+    gradient in `grads` (tag -> (dL/dx [N,3], dL/dm [N]), input order).
+    With `richardson` the differences at h and h/2 are combined as
+    (4 D(h/2) - D(h)) / 3, which removes the h^2 term (for softening lengths
+    not far above h).  Errors per particle, relative to max(|gradient|, its
+    rms)."""
+    ng = ot.n_groups
+    gpe = np.repeat(np.arange(ng), np.diff(ot.lists.poff))
+    gne = np.repeat(np.arange(ng), np.diff(ot.lists.noff))
+    parent = ot.tree.parent
+    leaf_of = np.empty(ps.n, np.int64)
+    for c in np.nonzero(ot.tree.leaf)[0]:
+        leaf_of[ot.tree.first[c]:ot.tree.first[c] + ot.tree.count[c]] = c
+
+    def anc_of(s):
+        out = []
+        c = int(leaf_of[s])
+        while c >= 0:
+            out.append(c)
+            c = int(parent[c])
+        return np.array(out, dtype=np.int64)
+
+    inv = np.empty(ps.n, np.int64)
+    inv[ot.perm] = np.arange(ps.n)
+    wsorted = w[ot.perm]
+    fd_err = {t + sfx: [] for t in grads for sfx in ("_x", "_m")}
+    for k in picks:
+        s = int(inv[k])
+        sel = _affected_groups(ot, s, gpe, gne, anc_of)
+        rows = np.concatenate([np.arange(ot.gfirst[g], ot.gfirst[g] + ot.gcount[g]) for g in sel])
+
+        def dloss(**kw):
+            a = ot.force_sorted(sel=sel, **kw)
+            return a[rows]
+
+        def central(scale):
+            out = np.empty(4)
+            for ax_i, name in enumerate(("ux", "uy", "uz")):
+                h = 1e-6 * scale
+                cols_p = {"ux": ot.ux.copy(), "uy": ot.uy.copy(), "uz": ot.uz.copy()}
+                cols_m = {"ux": ot.ux.copy(), "uy": ot.uy.copy(), "uz": ot.uz.copy()}
+                cols_p[name][s] += h
+                cols_m[name][s] -= h
+                out[ax_i] = np.sum(wsorted[rows] * (dloss(**cols_p) - dloss(**cols_m))) / (2 * h)
+            hm = 1e-6 * scale * ot.m[s]
+            mp, mmn = ot.m.copy(), ot.m.copy()
+            mp[s] += hm
+            mmn[s] -= hm
+            out[3] = np.sum(wsorted[rows] * (dloss(m=mp) - dloss(m=mmn))) / (2 * hm)
+            return out
+
+        fd = central(1.0)
+        if richardson:
+            fd = (4.0 * central(0.5) - fd) / 3.0
+        for tag, (gx, gm) in grads.items():
+            # per-particle relative error, floored at the gradient's rms so a
+            # near-zero component does not blow it up
+            sx = max(np.abs(gx[k]).max(), rms_x)
+            fd_err[tag + "_x"].append(float(np.max(np.abs(fd[:3] - gx[k])) / sx))
+            fd_err[tag + "_m"].append(float(abs(fd[3] - gm[k]) / max(abs(gm[k]), rms_m)))
+    return fd_err
+
+
 def test_workload4_adjoint_and_finite_differences():
     t0 = time.time()
     ps = synth.make_config(4)
@@ -145,58 +213,11 @@ def test_workload4_adjoint_and_finite_differences():
                                        median=float(np.median(em)), p99=float(np.percentile(em, 99)),
                                        rms=float(np.sqrt(np.mean(em ** 2)))))
     # central differences of the oracle's fixed-structure forward
-    ng = ot.n_groups
-    gpe = np.repeat(np.arange(ng), np.diff(ot.lists.poff))
-    gne = np.repeat(np.arange(ng), np.diff(ot.lists.noff))
-    parent = ot.tree.parent
-    leaf_of = np.empty(ps.n, np.int64)
-    for c in np.nonzero(ot.tree.leaf)[0]:
-        leaf_of[ot.tree.first[c]:ot.tree.first[c] + ot.tree.count[c]] = c
-
-    def anc_of(s):
-        out = []
-        c = int(leaf_of[s])
-        while c >= 0:
-            out.append(c)
-            c = int(parent[c])
-        return np.array(out, dtype=np.int64)
-
-    inv = np.empty(ps.n, np.int64)
-    inv[ot.perm] = np.arange(ps.n)
-    wsorted = w[ot.perm]
     rms_x = float(np.sqrt(np.mean(rx ** 2)))
     rms_m = float(np.sqrt(np.mean(rm ** 2)))
-    rng = np.random.default_rng(4)
-    picks = rng.choice(ps.n, 64, replace=False)
-    fd_err = {"fp64_x": [], "fp64_m": [], "fp32_x": [], "fp32_m": [], "oracle_x": [], "oracle_m": []}
-    for k in picks:
-        s = int(inv[k])
-        sel = _affected_groups(ot, s, gpe, gne, anc_of)
-        rows = np.concatenate([np.arange(ot.gfirst[g], ot.gfirst[g] + ot.gcount[g]) for g in sel])
-
-        def dloss(**kw):
-            a = ot.force_sorted(sel=sel, **kw)
-            return a[rows]
-
-        fd = np.empty(4)
-        for ax_i, name in enumerate(("ux", "uy", "uz")):
-            h = 1e-6
-            cols_p = {"ux": ot.ux.copy(), "uy": ot.uy.copy(), "uz": ot.uz.copy()}
-            cols_m = {"ux": ot.ux.copy(), "uy": ot.uy.copy(), "uz": ot.uz.copy()}
-            cols_p[name][s] += h
-            cols_m[name][s] -= h
-            fd[ax_i] = np.sum(wsorted[rows] * (dloss(**cols_p) - dloss(**cols_m))) / (2 * h)
-        hm = 1e-6 * ot.m[s]
-        mp, mmn = ot.m.copy(), ot.m.copy()
-        mp[s] += hm
-        mmn[s] -= hm
-        fd[3] = np.sum(wsorted[rows] * (dloss(m=mp) - dloss(m=mmn))) / (2 * hm)
-        for tag, (gx, gm) in (("fp64", grads[srf.FP64]), ("fp32", grads[srf.FP32_REL]), ("oracle", (rx, rm))):
-            # per-particle relative error, floored at the gradient's rms so a
-            # near-zero component does not blow it up
-            sx = max(np.abs(gx[k]).max(), rms_x)
-            fd_err[tag + "_x"].append(float(np.max(np.abs(fd[:3] - gx[k])) / sx))
-            fd_err[tag + "_m"].append(float(abs(fd[3] - gm[k]) / max(abs(gm[k]), rms_m)))
+    picks = np.random.default_rng(4).choice(ps.n, 64, replace=False)
+    fd_err = fd_errors(ot, ps, w, picks, {"fp64": grads[srf.FP64], "fp32": grads[srf.FP32_REL], "oracle": (rx, rm)},
+                       rms_x, rms_m)
     rec["fd"] = {t: dict(median=float(np.median(v)), max=float(np.max(v))) for t, v in fd_err.items()}
     rec["seconds"] = round(time.time() - t0, 1)
     say("WORKLOAD " + json.dumps(rec))
@@ -205,3 +226,45 @@ def test_workload4_adjoint_and_finite_differences():
     for t in ("oracle", "fp64"):
         assert rec["fd"][t + "_x"]["median"] <= 1e-6 and rec["fd"][t + "_x"]["max"] <= 1e-4
         assert rec["fd"][t + "_m"]["median"] <= 1e-6 and rec["fd"][t + "_m"]["max"] <= 1e-4
+
+
+def test_workload5_adjoint_full_size():
+    """1.3e7 particles (the per-node share): the FP32 and FP64 adjoint of the
+    bench path (ShortRange) against central differences of the oracle's
+    fixed-structure forward on 12 sampled particles, and translation
+    invariance of L (sum_k dL/dx_k = 0) over all particles."""
+    t0 = time.time()
+    ps = synth.make_config(5)
+    w = synth.loss_weights(ps.n, 2005)
+    say(f"[gpu] workload 5 adjoint, n={ps.n}")
+    x = torch.tensor(ps.positions(), dtype=torch.float64, device="cuda")
+    m = torch.tensor(ps.m, dtype=torch.float64, device="cuda")
+    wd = torch.tensor(w, dtype=torch.float64, device="cuda")
+    grads = {}
+    for prec, tag in ((srf.FP32_REL, "fp32"), (srf.FP64, "fp64")):
+        p = srf.Params.of(ps.params, prec)
+        xx = x.clone().requires_grad_(True)
+        mm = m.clone().requires_grad_(True)
+        a = srf.ShortRange.apply(xx, mm, p)
+        (a * wd).sum().backward()
+        torch.cuda.synchronize()
+        grads[tag] = (xx.grad.cpu().numpy(), mm.grad.cpu().numpy())
+    rec = dict(workload=5, n=ps.n, adjoint=True)
+    for tag, (gx, _) in grads.items():
+        rec[tag + "_translation"] = float(np.linalg.norm(gx.sum(0)) / np.abs(gx).sum())
+    say(f"    gpu done at {time.time() - t0:.1f}s; oracle tree")
+    ot = oracle.OracleTree(ps.x, ps.y, ps.z, ps.m, ps.params)
+    gx64, gm64 = grads["fp64"]
+    rms_x = float(np.sqrt(np.mean(gx64 ** 2)))
+    rms_m = float(np.sqrt(np.mean(gm64 ** 2)))
+    picks = np.random.default_rng(5).choice(ps.n, 12, replace=False)
+    # eps = 2e-5 here (10x below workload 4): extrapolated differences
+    fd_err = fd_errors(ot, ps, w, picks, grads, rms_x, rms_m, richardson=True)
+    rec["fd"] = {t: dict(median=float(np.median(v)), max=float(np.max(v))) for t, v in fd_err.items()}
+    rec["seconds"] = round(time.time() - t0, 1)
+    say("WORKLOAD " + json.dumps(rec))
+    assert rec["fp32_translation"] <= 1e-6 and rec["fp64_translation"] <= 1e-10
+    assert rec["fd"]["fp64_x"]["median"] <= 1e-6 and rec["fd"]["fp64_x"]["max"] <= 1e-4
+    assert rec["fd"]["fp64_m"]["median"] <= 1e-6 and rec["fd"]["fp64_m"]["max"] <= 1e-4
+    assert rec["fd"]["fp32_x"]["median"] <= 1e-5 and rec["fd"]["fp32_x"]["max"] <= 1e-3
+    assert rec["fd"]["fp32_m"]["median"] <= 1e-5 and rec["fd"]["fp32_m"]["max"] <= 1e-3
