@@ -80,7 +80,7 @@ def parse():
     ap.add_argument("--workload", type=int, default=3, help="1..5, see synth.CONFIGS")
     ap.add_argument("--theta", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-groups", type=int, default=1500)
+    ap.add_argument("--cpu-sample-groups", type=int, default=20000)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-pm", action="store_true", help="skip the separate long-range (PM) timing")
     ap.add_argument("--no-quad", action="store_true",
@@ -104,9 +104,15 @@ def copy_calibration(mib: int):
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8}), flush=True)
 
 
-def cpu_baseline(ps, sample_groups: int):
-    """The FP64 oracle on the host cores: tree (a1-a5) over the whole set,
-    then lists and same-list force (a6-a7) for a random sample of groups."""
+def cpu_baseline(ps, sample_groups: int, w):
+    """The FP64 oracle on the host cores, timed on the step the GPU value is
+    quoted for (forward a1-a8 and backward a1-a6, a9) over a bounded sample:
+    the tree (a1-a5) over the whole set, charged pro rata to the sampled
+    groups and counted twice (forward and backward), then lists (twice),
+    same-list force and adjoint for a random sample of groups.  The adjoint's
+    work that does not depend on the sample (its per-thread scatter buffers
+    and the node chain over all cells) is timed on an empty sample and also
+    charged pro rata."""
     if "OMP_NUM_THREADS" not in os.environ:
         os.environ["OMP_NUM_THREADS"] = str(len(os.sched_getaffinity(0)))
     import oracle
@@ -125,24 +131,42 @@ def cpu_baseline(ps, sample_groups: int):
     sel = np.sort(rng.choice(gf.size, min(sample_groups, gf.size), replace=False))
     t1 = time.perf_counter()
     L = oracle.make_lists(tree, lo[sel], hi[sel], p.r_cut, p.theta)
+    t_lists = time.perf_counter() - t1
     X0, X1, X2 = (np.ascontiguousarray(X[:, k]) for k in range(3))
     ax, ay, az = (np.zeros(ps.n) for _ in range(3))
     gfs, gcs = np.ascontiguousarray(gf[sel]), np.ascontiguousarray(gc[sel])
-    _p = oracle._ptr
-    oracle.lib().or_tree_force(oracle._i64(sel.size), _p(gfs), _p(gcs), _p(L.poff), _p(L.pidx), _p(L.noff),
-                               _p(L.nidx), _p(ux), _p(uy), _p(uz), _p(m), _p(M), _p(X0), _p(X1), _p(X2),
-                               oracle._d(p.G), oracle._d(p.r_cut), oracle._d(p.eps), None, oracle._i64(-1),
-                               _p(ax), _p(ay), _p(az))
-    t_sample = time.perf_counter() - t1
+    _p, _i, _d = oracle._ptr, oracle._i64, oracle._d
+    t1 = time.perf_counter()
+    oracle.lib().or_tree_force(_i(sel.size), _p(gfs), _p(gcs), _p(L.poff), _p(L.pidx), _p(L.noff), _p(L.nidx),
+                               _p(ux), _p(uy), _p(uz), _p(m), _p(M), _p(X0), _p(X1), _p(X2), _d(p.G),
+                               _d(p.r_cut), _d(p.eps), None, _i(-1), _p(ax), _p(ay), _p(az))
+    t_force = time.perf_counter() - t1
+    ws = np.asarray(w, dtype=np.float64)[perm]
+    wx, wy, wz = (np.ascontiguousarray(ws[:, k]) for k in range(3))
+    gx, gy, gz, gm = (np.empty(ps.n) for _ in range(4))
+
+    def adjoint(ng):
+        t = time.perf_counter()
+        oracle.lib().or_tree_adjoint(_i(ps.n), _i(ng), _p(gfs), _p(gcs), _p(L.poff), _p(L.pidx), _p(L.noff),
+                                     _p(L.nidx), _i(tree.size), _p(tree.first), _p(tree.count), _p(ux), _p(uy),
+                                     _p(uz), _p(m), _p(M), _p(X0), _p(X1), _p(X2), _p(wx), _p(wy), _p(wz),
+                                     _d(p.G), _d(p.r_cut), _d(p.eps), _p(gx), _p(gy), _p(gz), _p(gm))
+        return time.perf_counter() - t
+
+    t_adj0 = adjoint(0)
+    t_adj = adjoint(sel.size)
+    t_adj_pairs = max(t_adj - t_adj0, 0.0)
     nj = np.diff(L.poff) + np.diff(L.noff)
     i_sample = int(np.sum(gcs * nj))
     frac = sel.size / gf.size
-    t_eff = t_tree * frac + t_sample
-    return dict(value=i_sample / t_eff, unit="interactions/s", cores=oracle.num_threads(), kind="oracle",
-                sample=(f"forward path of the FP64 oracle: tree over all {ps.n} particles "
-                        f"({t_tree:.2f} s, charged pro rata {frac:.4f}) + lists and same-list force for "
-                        f"{sel.size} random groups ({i_sample} interactions, {t_sample:.2f} s)"),
-                t_tree_s=t_tree, t_sample_s=t_sample)
+    t_step = 2.0 * (t_tree * frac + t_lists) + t_force + t_adj_pairs + t_adj0 * frac
+    return dict(value=i_sample / t_step, unit="interactions/s", cores=oracle.num_threads(), kind="oracle",
+                sample=(f"fwd+adjoint step of the FP64 oracle on {sel.size} random groups of {gf.size} "
+                        f"({i_sample} interactions): tree over all {ps.n} particles {t_tree:.2f} s and the "
+                        f"adjoint's sample-independent part {t_adj0:.2f} s, both charged pro rata {frac:.4f} "
+                        f"(tree twice); lists {t_lists:.2f} s (twice), force {t_force:.2f} s, adjoint pairs "
+                        f"{t_adj_pairs:.2f} s"),
+                t_tree_s=t_tree, t_lists_s=t_lists, t_force_s=t_force, t_adjoint_s=t_adj, t_adjoint_fixed_s=t_adj0)
 
 
 def main():
@@ -323,7 +347,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(ps, args.cpu_sample_groups)
+        cpu = cpu_baseline(ps, args.cpu_sample_groups, synth.loss_weights(ps.n, 2000 + args.workload))
 
     out = {
         "metric": METRIC,
