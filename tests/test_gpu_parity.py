@@ -316,6 +316,30 @@ def test_centre_of_mass_mac(name, theta):
     assert e.value.status == -5
 
 
+@pytest.mark.parametrize("n_group,n_leaf", [(1, 1), (8, 4), (16, 16), (33, 7)])
+def test_other_group_sizes(n_group, n_leaf):
+    """Groups and leaves other than the workloads' 64 / 16: bit-exact
+    structure and lists, FP32 force and adjoint against the oracle."""
+    ps = synth.small_clustered(6000, 151, r_cut=0.1, eps=2e-4, theta=0.5, per_halo=600)
+    params = synth.Params(1.0, 0.1, 2e-4, 0.5, n_group, n_leaf)
+    say(f"[gpu] n_group={n_group} n_leaf={n_leaf} n={ps.n}")
+    ot = oracle.OracleTree(ps.x, ps.y, ps.z, ps.m, params)
+    tree, lists, a32 = gpu_forward(ps, params)
+    check_structure(tree, lists, ot)
+    assert np.max(ot.gcount) <= n_group
+    st = rel_stats(a32, ot.force())
+    say(f"    force {st}")
+    assert st["rms"] <= FP32_TOL
+    w = synth.loss_weights(ps.n, 152)
+    rx, rm = ot.adjoint(w)
+    p = srf.Params.of(params)
+    gx, gm = srf.short_range_adjoint(tree, lists, p, torch.tensor(w, dtype=torch.float64, device="cuda"))
+    sx = rel_stats(gx.cpu().numpy(), rx)
+    l2m = np.linalg.norm(gm.cpu().numpy() - rm) / np.linalg.norm(rm)
+    say(f"    adjoint: dL/dx {sx}, dL/dm normwise {l2m:.3e}")
+    assert sx["rms"] <= FP32_TOL and l2m <= FP32_TOL
+
+
 def test_domain_errors_reported():
     p = srf.Params(r_cut=0.1, eps=1e-3)
     x = torch.rand((100, 3), dtype=torch.float64, device="cuda")
