@@ -340,6 +340,37 @@ def test_other_group_sizes(n_group, n_leaf):
     assert sx["rms"] <= FP32_TOL and l2m <= FP32_TOL
 
 
+def test_work_ordered_on_the_callers_stream():
+    """Every call orders its device work on torch's current stream: the path
+    run on two side streams in turn (the library's memory cache then hands
+    blocks from one stream to the other) gives the default stream's result
+    bit for bit (the force has no atomics; the adjoint's atomics are compared
+    to rounding)."""
+    ps = case_sets()["clustered-20000"]
+    p = srf.Params.of(ps.params)
+    x, m = dev_inputs(ps)
+    w = torch.tensor(synth.loss_weights(ps.n, 161), dtype=torch.float64, device="cuda")
+
+    def run():
+        tree = srf.tree_build(x, m, p)
+        lists = srf.make_lists(tree, p)
+        a = srf.short_range_force(tree, lists, p)
+        gx, gm = srf.short_range_adjoint(tree, lists, p, w)
+        return a, gx, gm
+
+    a0, gx0, gm0 = run()
+    torch.cuda.synchronize()
+    for _ in range(2):
+        for st in (torch.cuda.Stream(), torch.cuda.Stream()):
+            st.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(st):
+                a, gx, gm = run()
+            st.synchronize()
+            assert torch.equal(a, a0)
+            assert torch.allclose(gx, gx0, rtol=1e-12, atol=1e-12 * gx0.abs().max().item())
+            assert torch.allclose(gm, gm0, rtol=1e-12, atol=1e-12 * gm0.abs().max().item())
+
+
 def test_domain_errors_reported():
     p = srf.Params(r_cut=0.1, eps=1e-3)
     x = torch.rand((100, 3), dtype=torch.float64, device="cuda")
