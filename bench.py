@@ -154,6 +154,12 @@ def cpu_baseline(ps, sample_groups: int, w):
         return time.perf_counter() - t
 
     t_adj0 = adjoint(0)
+    # the brute-force cutoff sum (cell list) for a random sample of particles,
+    # in pairs within r_cut per second
+    bsel = np.sort(np.random.default_rng(1).choice(ps.n, min(100000, ps.n), replace=False))
+    t1 = time.perf_counter()
+    _, bf_pairs = oracle.brute_force_sel(ps.x, ps.y, ps.z, ps.m, p.G, p.r_cut, p.eps, bsel, count_pairs=True)
+    t_bf = time.perf_counter() - t1
     t_adj = adjoint(sel.size)
     t_adj_pairs = max(t_adj - t_adj0, 0.0)
     nj = np.diff(L.poff) + np.diff(L.noff)
@@ -166,7 +172,10 @@ def cpu_baseline(ps, sample_groups: int, w):
                         f"adjoint's sample-independent part {t_adj0:.2f} s, both charged pro rata {frac:.4f} "
                         f"(tree twice); lists {t_lists:.2f} s (twice), force {t_force:.2f} s, adjoint pairs "
                         f"{t_adj_pairs:.2f} s"),
-                t_tree_s=t_tree, t_lists_s=t_lists, t_force_s=t_force, t_adjoint_s=t_adj, t_adjoint_fixed_s=t_adj0)
+                t_tree_s=t_tree, t_lists_s=t_lists, t_force_s=t_force, t_adjoint_s=t_adj, t_adjoint_fixed_s=t_adj0,
+                bruteforce=dict(value=bf_pairs / t_bf, unit="pairs within r_cut/s", pairs=bf_pairs,
+                                sample=f"{bsel.size} random target particles, cell-list sum over all {ps.n}",
+                                seconds=t_bf))
 
 
 def main():

@@ -184,14 +184,17 @@ def brute_force(x, y, z, m, G, r_cut, eps, method="cells"):
     return np.stack([ax, ay, az], axis=1)
 
 
-def brute_force_sel(x, y, z, m, G, r_cut, eps, sel):
-    """Exact short-range accelerations of the particles sel (input indices)."""
+def brute_force_sel(x, y, z, m, G, r_cut, eps, sel, count_pairs=False):
+    """Exact short-range accelerations of the particles sel (input indices);
+    with ``count_pairs`` also the number of pairs within r_cut summed."""
     x, y, z, m = map(_f64, (x, y, z, m))
     sel = np.ascontiguousarray(sel, dtype=np.int64)
     ax, ay, az = np.empty(sel.size), np.empty(sel.size), np.empty(sel.size)
+    npairs = np.zeros(1, np.int64)
     lib().or_bf_cells_sel(_i64(x.size), _ptr(x), _ptr(y), _ptr(z), _ptr(m), _d(G), _d(r_cut), _d(eps),
-                          _ptr(sel), _i64(sel.size), _ptr(ax), _ptr(ay), _ptr(az))
-    return np.stack([ax, ay, az], axis=1)
+                          _ptr(sel), _i64(sel.size), _ptr(ax), _ptr(ay), _ptr(az), _ptr(npairs))
+    a = np.stack([ax, ay, az], axis=1)
+    return (a, int(npairs[0])) if count_pairs else a
 
 
 def pair_count(x, y, z, r_cut) -> int:

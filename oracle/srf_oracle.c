@@ -288,14 +288,17 @@ int or_bf_cells(int64_t n, const double* x, const double* y, const double* z, co
     return 0;
 }
 
-/* The same brute-force sum for a subset of target particles sel[0..nsel). */
+/* The same brute-force sum for a subset of target particles sel[0..nsel).
+ * If `pairs` is not NULL it receives the number of (target, source) pairs
+ * with 0 < r < r_cut that were summed. */
 int or_bf_cells_sel(int64_t n, const double* x, const double* y, const double* z, const double* m,
                     double G, double rc, double eps, const int64_t* sel, int64_t nsel,
-                    double* ax, double* ay, double* az) {
+                    double* ax, double* ay, double* az, int64_t* pairs) {
     cells_t cl;
     int have = cells_build(n, x, y, z, rc, &cl);
     int nc = have ? cl.nc : 0;
-    #pragma omp parallel for schedule(dynamic, 16)
+    int64_t np = 0;
+    #pragma omp parallel for schedule(dynamic, 16) reduction(+ : np)
     for (int64_t q = 0; q < nsel; ++q) {
         int64_t i = sel[q];
         double a[3] = {0, 0, 0};
@@ -308,19 +311,24 @@ int or_bf_cells_sel(int64_t n, const double* x, const double* y, const double* z
                 for (int64_t t = cl.start[c]; t < cl.start[c + 1]; ++t) {
                     int64_t j = cl.idx[t];
                     double d[3] = {mimage(x[j] - x[i]), mimage(y[j] - y[i]), mimage(z[j] - z[i])};
-                    double p = phi_of(d[0] * d[0] + d[1] * d[1] + d[2] * d[2], rc, eps);
+                    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                    double p = phi_of(r2, rc, eps);
+                    if (r2 > 0.0 && r2 < rc * rc) ++np;
                     a[0] += m[j] * d[0] * p; a[1] += m[j] * d[1] * p; a[2] += m[j] * d[2] * p;
                 }
             }
         } else {
             for (int64_t j = 0; j < n; ++j) {
                 double d[3] = {mimage(x[j] - x[i]), mimage(y[j] - y[i]), mimage(z[j] - z[i])};
-                double p = phi_of(d[0] * d[0] + d[1] * d[1] + d[2] * d[2], rc, eps);
+                double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                double p = phi_of(r2, rc, eps);
+                if (r2 > 0.0 && r2 < rc * rc) ++np;
                 a[0] += m[j] * d[0] * p; a[1] += m[j] * d[1] * p; a[2] += m[j] * d[2] * p;
             }
         }
         ax[q] = G * a[0]; ay[q] = G * a[1]; az[q] = G * a[2];
     }
+    if (pairs) *pairs = np;
     if (have) cells_free(&cl);
     return have ? 0 : 1;
 }

@@ -106,3 +106,11 @@ def test_selected_targets_match_full_sum():
     sel = np.random.default_rng(2).choice(ps.n, 300, replace=False)
     part = oracle.brute_force_sel(ps.x, ps.y, ps.z, ps.m, p.G, p.r_cut, p.eps, sel)
     assert np.array_equal(part, full[sel])
+    # pairs within r_cut summed for the sample: the direct count over its rows
+    part2, npairs = oracle.brute_force_sel(ps.x, ps.y, ps.z, ps.m, p.G, p.r_cut, p.eps, sel, count_pairs=True)
+    assert np.array_equal(part2, part)
+    pos = ps.positions()
+    d = pos[sel][:, None, :] - pos[None, :, :]
+    d -= np.rint(d)
+    r2 = np.sum(d * d, axis=2)
+    assert npairs == int(np.sum((r2 < p.r_cut ** 2) & (r2 > 0.0)))
