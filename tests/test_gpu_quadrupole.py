@@ -137,3 +137,27 @@ def test_quadrupole_errors():
     assert L.srf_short_range_quadrupole(tree.handle, lists.handle, C.byref(cp), None, ptr, ptr, 3, None) == -1
     assert L.srf_short_range_quadrupole(tree.handle, lists.handle, C.byref(cp), ptr, ptr, ptr, 0, None) == -1
     assert L.srf_short_range_quadrupole(None, lists.handle, C.byref(cp), ptr, ptr, ptr, 3, None) == -1
+
+
+def test_variants_over_centre_of_mass_lists():
+    """Quadrupole term and potential over lists built with the centre-of-mass
+    criterion, against the oracle on the same criterion."""
+    ps = CASES["clustered-20000"]()
+    params = synth.Params(1.0, ps.params.r_cut, ps.params.eps, 0.7, 64, 16, srf.MAC_COM)
+    ot = oracle.OracleTree(ps.x, ps.y, ps.z, ps.m, params)
+    p = srf.Params.of(params)
+    x = torch.tensor(ps.positions(), dtype=torch.float64, device="cuda")
+    m = torch.tensor(ps.m, dtype=torch.float64, device="cuda")
+    tree = srf.tree_build(x, m, p)
+    lists = srf.make_lists(tree, p)
+    L = lists.export()
+    for k in ("poff", "pidx", "noff", "nidx"):
+        assert np.array_equal(L[k], getattr(ot.lists, k)), k
+    a = srf.short_range_force(tree, lists, p, quadrupole=True).cpu().numpy()
+    phi = srf.short_range_potential(tree, lists, p).cpu().numpy()
+    st = oracle.relative_errors(a, ot.force_quadrupole())[1]
+    ref = ot.potential()
+    nz = ref != 0
+    ep = np.abs(phi[nz] - ref[nz]) / np.abs(ref[nz])
+    say(f"[gpu] centre-of-mass lists: quadrupole force {st['rms']:.3e}, potential {np.sqrt(np.mean(ep ** 2)):.3e}")
+    assert st["rms"] <= 1e-5 and np.sqrt(np.mean(ep ** 2)) <= 1e-5
