@@ -249,7 +249,11 @@ int srf_lists_export(const srf_lists* l, int64_t* poff, int64_t* pidx, int64_t* 
  * `srf_short_range_force` ("force") or `srf_short_range_adjoint`
  * ("adjoint") pair-kernel launch, or of the whole last `srf_pm_force`
  * ("pm"), measured with HIP events on the call's stream when timing is
- * enabled. */
+ * enabled (0 disables).  The state is process-wide and not thread-safe; the
+ * events are created on the device current at the first timed call, so
+ * time on one device only.  srf_last_kernel_ms synchronises on the end
+ * event.  Errors: SRF_EINVAL (NULL or unknown `which`, or no timed launch of
+ * that kind yet), SRF_EHIP. */
 int srf_set_kernel_timing(int enable);
 int srf_last_kernel_ms(const char* which, double* ms);
 
