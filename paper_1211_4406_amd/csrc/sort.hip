@@ -46,113 +46,196 @@ __global__ void k_keys(int64_t n, const double* __restrict__ x, const double* __
 }
 
 // ------------------------------------------------------------- radix sort
+// Eight LSD passes of 8 bits over the 64-bit key.  A block sorts a tile of
+// kTile keys; its wave w owns the kWaveKeys consecutive keys starting at
+// w * kWaveKeys, read in rounds of 64 (item r of lane l is key
+// w * kWaveKeys + 64 r + l), so a key's rank within its wave needs no
+// block-wide barrier.  Each pass: per-tile digit counts (k_hist), their
+// exclusive scan over the tiles of each digit (k_digit_scan), and the stable
+// scatter (k_scatter), which adds the scan over digits itself.
+#ifndef SRF_SORT_ITEMS
+#define SRF_SORT_ITEMS 16
+#endif
 constexpr int kThreads = 256;
-constexpr int kItems = 8;
+constexpr int kWaves = kThreads / 64;
+constexpr int kItems = SRF_SORT_ITEMS;
+constexpr int kWaveKeys = 64 * kItems;
 constexpr int kTile = kThreads * kItems;  // keys per block
 constexpr int kDigits = 256;
+static_assert(kThreads == kDigits, "one digit per thread in the per-digit steps");
 
 __global__ __launch_bounds__(kThreads) void k_hist(int64_t n, const uint64_t* __restrict__ keys, int shift,
                                                    int64_t tiles, int32_t* __restrict__ counts) {
-    __shared__ int32_t h[kDigits];
-    h[threadIdx.x] = 0;
-    __syncthreads();
-    const int64_t base = blockIdx.x * (int64_t)kTile;
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        int64_t i = base + k * kThreads + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 0xff], 1);
-    }
-    __syncthreads();
-    counts[(int64_t)threadIdx.x * tiles + blockIdx.x] = h[threadIdx.x];
-}
-
-// Stable scatter.  The keys of a tile are taken in rounds of 256 (position
-// round*256 + tid); a key's rank among equal digits is the count of that
-// digit in earlier rounds plus the count among lower threads this round.
-// The tile is then reordered by digit in LDS, so that the global writes of
-// each digit's run are contiguous.
-__global__ __launch_bounds__(kThreads) void k_scatter(int64_t n, const uint64_t* __restrict__ kin,
-                                                      const int32_t* __restrict__ vin, uint64_t* __restrict__ kout,
-                                                      int32_t* __restrict__ vout, int shift, int64_t tiles,
-                                                      const int32_t* __restrict__ offsets) {
-    __shared__ int32_t base[kDigits];
-    __shared__ int32_t run[kDigits];
-    __shared__ int32_t toff[kDigits];
-    __shared__ int32_t wc[kThreads / 64][kDigits];
-    __shared__ uint64_t skey[kTile];
-    __shared__ int32_t sval[kTile];
-    __shared__ int32_t wsum[kThreads / 64];
+    __shared__ int32_t h[kWaves][kDigits];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    base[tid] = offsets[(int64_t)tid * tiles + blockIdx.x];
-    run[tid] = 0;
 #pragma unroll
-    for (int w = 0; w < kThreads / 64; ++w) wc[w][tid] = 0;
+    for (int w = 0; w < kWaves; ++w) h[w][tid] = 0;
     __syncthreads();
-    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int64_t tbase = blockIdx.x * (int64_t)kTile;
-    uint64_t key[kItems];
-    int32_t val[kItems], dig[kItems], rank[kItems];
+    const int64_t base = blockIdx.x * (int64_t)kTile + wid * kWaveKeys + lane;
+    uint64_t k[kItems];
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
-        const int64_t i = tbase + r * kThreads + tid;
-        const bool valid = i < n;
-        key[r] = valid ? kin[i] : 0;
-        val[r] = valid ? vin[i] : 0;
-        const int d = valid ? (int)((key[r] >> shift) & 0xff) : -1;
-        dig[r] = d;
-        // lanes holding the same digit (invalid lanes match nobody valid)
-        uint64_t peers = __ballot(valid);
-        if (!valid) peers = ~peers;
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const bool bit = valid && ((d >> b) & 1);
-            const uint64_t bal = __ballot(bit);
-            peers &= bit ? bal : ~bal;
-        }
-        const int lower = __popcll(peers & lt);
-        if (valid && lower == 0) wc[wid][d] = __popcll(peers);
-        __syncthreads();
-        if (valid) {
-            int rk = run[d] + lower;
-            for (int w = 0; w < wid; ++w) rk += wc[w][d];
-            rank[r] = rk;
-        } else {
-            rank[r] = 0;
-        }
-        __syncthreads();
-        int tot = 0;
-#pragma unroll
-        for (int w = 0; w < kThreads / 64; ++w) {
-            tot += wc[w][tid];
-            wc[w][tid] = 0;
-        }
-        run[tid] += tot;
-        __syncthreads();
+        const int64_t i = base + 64 * r;
+        k[r] = i < n ? keys[i] : 0;
     }
-    // exclusive scan of the tile's digit counts (one digit per thread)
-    {
-        const int v = run[tid];
-        int incl = v;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r)
+        if (base + 64 * r < n) atomicAdd(&h[wid][(k[r] >> shift) & 0xff], 1);
+    __syncthreads();
+    int32_t c = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) c += h[w][tid];
+    counts[(int64_t)tid * tiles + blockIdx.x] = c;
+}
+
+// Exclusive scan of one digit's row of per-tile counts (block = digit), in
+// place; the digit's total goes to dtot.
+__global__ __launch_bounds__(kThreads) void k_digit_scan(int64_t tiles, int32_t* __restrict__ counts,
+                                                         int32_t* __restrict__ dtot) {
+    constexpr int kPer = 4;
+    __shared__ int32_t wsum[kWaves];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    int32_t* row = counts + (int64_t)blockIdx.x * tiles;
+    int32_t carry = 0;
+    for (int64_t c0 = 0; c0 < tiles; c0 += kThreads * kPer) {
+        const int64_t j = c0 + (int64_t)tid * kPer;
+        int32_t v[kPer];
+        int32_t s = 0;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            v[k] = j + k < tiles ? row[j + k] : 0;
+            s += v[k];
+        }
+        int32_t incl = s;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
-            const int u = __shfl_up(incl, o, 64);
+            const int32_t u = __shfl_up(incl, o, 64);
             if (lane >= o) incl += u;
         }
         if (lane == 63) wsum[wid] = incl;
         __syncthreads();
-        int off = incl - v;
-        for (int w = 0; w < wid; ++w) off += wsum[w];
-        toff[tid] = off;
+        int32_t off = carry + incl - s, total = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            off += w < wid ? wsum[w] : 0;
+            total += wsum[w];
+        }
         __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            if (j + k < tiles) row[j + k] = off;
+            off += v[k];
+        }
+        carry += total;
+    }
+    if (tid == 0) dtot[blockIdx.x] = carry;
+}
+
+// Stable scatter of one tile.  Ranking: in each round the lanes holding the
+// same digit are found by eight ballots; a key's rank is its wave's running
+// count of that digit (an LDS counter, advanced by the lowest such lane)
+// plus the number of such lanes below it.  Tile position: digits in order,
+// within a digit the waves in order, then the rank.  The tile is reordered
+// in LDS so that each digit's run is written contiguously.
+__global__ __launch_bounds__(kThreads) void k_scatter(int64_t n, const uint64_t* __restrict__ kin,
+                                                      const int32_t* __restrict__ vin, uint64_t* __restrict__ kout,
+                                                      int32_t* __restrict__ vout, int shift, int64_t tiles,
+                                                      const int32_t* __restrict__ offsets,
+                                                      const int32_t* __restrict__ dtot) {
+    __shared__ int32_t wc[kWaves][kDigits];   // running counts, then the waves' exclusive prefix
+    __shared__ int32_t toff[kDigits];         // tile-local exclusive offset of each digit
+    __shared__ int32_t gdst[kDigits];         // global position of the tile's first key of each digit
+    __shared__ int32_t wsum[kWaves][2];
+    __shared__ uint64_t skey[kTile];
+    __shared__ int32_t sval[kTile];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) wc[w][tid] = 0;
+    const int32_t tile_base = offsets[(int64_t)tid * tiles + blockIdx.x];
+    const int32_t digit_total = dtot[tid];
+    __syncthreads();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t wbase = blockIdx.x * (int64_t)kTile + wid * kWaveKeys + lane;
+    uint64_t key[kItems];
+    int32_t val[kItems], rank[kItems];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const int64_t i = wbase + 64 * r;
+        key[r] = i < n ? kin[i] : 0;
+        val[r] = i < n ? vin[i] : 0;
     }
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
-        if (dig[r] < 0) continue;
-        const int p = toff[dig[r]] + rank[r];
-        skey[p] = key[r];
-        sval[p] = val[r];
+        const bool valid = wbase + 64 * r < n;
+        const int d = (int)((key[r] >> shift) & 0xff);
+        // lanes holding the same digit (invalid lanes match only each other)
+        uint64_t peers = __ballot(valid);
+        if (!valid) peers = ~peers;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1;
+            const uint64_t bal = __ballot(bit);
+            peers &= bit ? bal : ~bal;
+        }
+        const int lower = __popcll(peers & lt);
+        int32_t old = 0;
+        if (valid) old = wc[wid][d];
+        rank[r] = old + lower;
+        if (valid && lower == 0) wc[wid][d] = old + __popcll(peers);
+        // the next round's reads must see this round's counter (one wave:
+        // LDS operations complete in order; this keeps the compiler's too)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     __syncthreads();
+    // per digit (one per thread): the waves' exclusive prefix and the tile
+    // total, then exclusive scans over digits of the tile totals and of the
+    // global digit totals
+    int32_t tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        const int32_t c = wc[w][tid];
+        wc[w][tid] = tot;
+        tot += c;
+    }
+    int32_t it = tot, ig = digit_total;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t ut = __shfl_up(it, o, 64), ug = __shfl_up(ig, o, 64);
+        if (lane >= o) {
+            it += ut;
+            ig += ug;
+        }
+    }
+    if (lane == 63) {
+        wsum[wid][0] = it;
+        wsum[wid][1] = ig;
+    }
+    __syncthreads();
+    int32_t ot = it - tot, og = ig - digit_total;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        if (w < wid) {
+            ot += wsum[w][0];
+            og += wsum[w][1];
+        }
+    }
+    toff[tid] = ot;
+    gdst[tid] = og + tile_base;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        if (wbase + 64 * r >= n) continue;
+        const int d = (int)((key[r] >> shift) & 0xff);
+        const int p = toff[d] + wc[wid][d] + rank[r];
+        if ((unsigned)p < (unsigned)kTile) {
+            skey[p] = key[r];
+            sval[p] = val[r];
+        }
+    }
+    __syncthreads();
+    const int64_t tbase = blockIdx.x * (int64_t)kTile;
     const int cnt = (int)((n - tbase) < kTile ? (n - tbase) : kTile);
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
@@ -160,9 +243,11 @@ __global__ __launch_bounds__(kThreads) void k_scatter(int64_t n, const uint64_t*
         if (p < cnt) {
             const uint64_t k = skey[p];
             const int d = (int)((k >> shift) & 0xff);
-            const int64_t dst = (int64_t)base[d] + (p - toff[d]);
-            kout[dst] = k;
-            vout[dst] = sval[p];
+            const int64_t dst = (int64_t)gdst[d] + (p - toff[d]);
+            if ((uint64_t)dst < (uint64_t)n) {   // always, by construction; never a stray store
+                kout[dst] = k;
+                vout[dst] = sval[p];
+            }
         }
     }
 }
@@ -194,6 +279,7 @@ void build_sorted(Tree& t, const double* x, const double* y, const double* z, in
     SRF_HIP(hipGetLastError());
     const int64_t tiles = (n + kTile - 1) / kTile;
     DevBuf<int32_t> counts(kDigits * tiles, st);
+    DevBuf<int32_t> dtot(kDigits, st);
     uint64_t* ka = t.keys.get();
     int32_t* va = t.perm.get();
     uint64_t* kk = kb.get();
@@ -202,9 +288,10 @@ void build_sorted(Tree& t, const double* x, const double* y, const double* z, in
         const int shift = 8 * pass;
         hipLaunchKernelGGL(k_hist, dim3((unsigned)tiles), dim3(kThreads), 0, st, n, ka, shift, tiles, counts.get());
         SRF_HIP(hipGetLastError());
-        exclusive_scan_i32(counts.get(), kDigits * tiles, false, st);
+        hipLaunchKernelGGL(k_digit_scan, dim3(kDigits), dim3(kThreads), 0, st, tiles, counts.get(), dtot.get());
+        SRF_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_scatter, dim3((unsigned)tiles), dim3(kThreads), 0, st, n, ka, va, kk, vv, shift, tiles,
-                           counts.get());
+                           counts.get(), dtot.get());
         SRF_HIP(hipGetLastError());
         std::swap(ka, kk);
         std::swap(va, vv);
