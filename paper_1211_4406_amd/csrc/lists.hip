@@ -233,16 +233,21 @@ __global__ __launch_bounds__(128) void k_lists(int64_t ng, const double* __restr
 // Expansion: one wave per group turns its items into entries.  Items are
 // taken 64 at a time (one per lane); a leaf item stands for its particles
 // first..first+count-1, a cell item for itself.  An inclusive scan of the
-// item sizes places each item; then lane k writes entries k, k + 64, ... of
-// the chunk, finding its item by binary search over the scan in LDS, so
-// every store of the wave covers 64 consecutive entries.
+// item sizes places each item in the chunk.  When the chunk's entries fit
+// the LDS buffer, each lane writes its own item's entries there and the
+// wave copies the buffer out, 64 consecutive entries per store; otherwise
+// lane k writes entries k, k + 64, ... of the chunk directly, finding its
+// item by binary search over the scan.
 // Items of group g: icnt[g] of them from g * slot when slot > 0, else
 // [ioff[g], ioff[g + 1]).
+constexpr int kExpandBuf = 1024;
+
 __global__ __launch_bounds__(64) void k_expand(int64_t ng, int64_t slot, const int64_t* __restrict__ icnt,
                                                const int64_t* __restrict__ ioff, const int32_t* __restrict__ items,
                                                const NodeRange* __restrict__ rng, const int64_t* __restrict__ off,
                                                int32_t* __restrict__ ent) {
     __shared__ int32_t s_end[64], s_first[64];
+    __shared__ int32_t s_ent[kExpandBuf];
     const int64_t g = xcd_block(blockIdx.x, gridDim.x);
     if (g >= ng) return;
     const int lane = threadIdx.x;
@@ -270,21 +275,33 @@ __global__ __launch_bounds__(64) void k_expand(int64_t ng, int64_t slot, const i
             if (lane >= o) incl += u;
         }
         const int total = __shfl(incl, 63, 64);
-        __syncthreads();
-        s_end[lane] = incl;
-        // a leaf's entry q is first + q; a cell's only entry is its code,
-        // stored as first - 0 with the leaf flag clear
-        s_first[lane] = v >= 0 ? first - (incl - n) : first;
-        __syncthreads();
-        const uint64_t leafmask = __ballot(v >= 0 && n > 0);
-        for (int k = lane; k < total; k += 64) {
-            // first item whose end exceeds k
-            int lo = 0;
+        if (total <= kExpandBuf) {
+            // a leaf's entries are first, first + 1, ...; a cell's only
+            // entry is its code
+            const int b = incl - n;
+            if (v >= 0) {
+                for (int q = 0; q < n; ++q) s_ent[b + q] = first + q;
+            } else if (n > 0) {
+                s_ent[b] = first;
+            }
+            __syncthreads();
+            for (int k = lane; k < total; k += 64) dst[k] = s_ent[k];
+            __syncthreads();
+        } else {
+            __syncthreads();
+            s_end[lane] = incl;
+            s_first[lane] = v >= 0 ? first - (incl - n) : first;
+            __syncthreads();
+            const uint64_t leafmask = __ballot(v >= 0 && n > 0);
+            for (int k = lane; k < total; k += 64) {
+                // first item whose end exceeds k
+                int lo = 0;
 #pragma unroll
-            for (int step = 32; step >= 1; step >>= 1)
-                if (s_end[lo + step - 1] <= k) lo += step;
-            const int32_t f = s_first[lo];
-            dst[k] = ((leafmask >> lo) & 1ull) ? f + k : f;
+                for (int step = 32; step >= 1; step >>= 1)
+                    if (s_end[lo + step - 1] <= k) lo += step;
+                const int32_t f = s_first[lo];
+                dst[k] = ((leafmask >> lo) & 1ull) ? f + k : f;
+            }
         }
         dst += total;
     }

@@ -147,39 +147,57 @@ __global__ void k_leaf_fix(int64_t begin, int64_t m, int32_t* __restrict__ child
     child_cnt[begin + k] = 0;
 }
 
-// Bottom-up monopoles: mass and mass-weighted position sums.
-__global__ void k_moments(int64_t begin, int64_t m, const int32_t* __restrict__ first, const int32_t* __restrict__ count,
-                          const int32_t* __restrict__ child_begin, const int32_t* __restrict__ child_cnt,
-                          const double* __restrict__ px, const double* __restrict__ py, const double* __restrict__ pz,
-                          const double* __restrict__ pm, double* __restrict__ M, double* __restrict__ SX,
-                          double* __restrict__ SY, double* __restrict__ SZ) {
-    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (k >= m) return;
-    int64_t c = begin + k;
+// Bottom-up monopoles of one level: mass and mass-weighted position sums,
+// 16 lanes per cell.  A leaf's lane j takes its particles j, j + 16, ...
+// (consecutive lanes read consecutive particles); an inner cell's lane j
+// takes child j.  The row's 16 partial sums are then added by shuffles.
+constexpr int kMomLanes = 16;
+
+__global__ __launch_bounds__(256) void k_moments(int64_t begin, int64_t m, const int32_t* __restrict__ first,
+                                                 const int32_t* __restrict__ count,
+                                                 const int32_t* __restrict__ child_begin,
+                                                 const int32_t* __restrict__ child_cnt, const double* __restrict__ px,
+                                                 const double* __restrict__ py, const double* __restrict__ pz,
+                                                 const double* __restrict__ pm, double* __restrict__ M,
+                                                 double* __restrict__ SX, double* __restrict__ SY,
+                                                 double* __restrict__ SZ) {
+    const int64_t k = blockIdx.x * (int64_t)(256 / kMomLanes) + threadIdx.x / kMomLanes;
+    const int j = threadIdx.x & (kMomLanes - 1);
+    const bool on = k < m;
+    const int64_t c = begin + (on ? k : 0);
     double sm = 0, sx = 0, sy = 0, sz = 0;
-    int32_t nch = child_cnt[c];
-    if (nch == 0) {
-        int32_t f = first[c], e = first[c] + count[c];
-        for (int32_t s = f; s < e; ++s) {
-            double mm = pm[s];
-            sm += mm;
-            sx += mm * px[s];
-            sy += mm * py[s];
-            sz += mm * pz[s];
-        }
-    } else {
-        int32_t cb = child_begin[c];
-        for (int32_t q = cb; q < cb + nch; ++q) {
-            sm += M[q];
-            sx += SX[q];
-            sy += SY[q];
-            sz += SZ[q];
+    if (on) {
+        const int32_t nch = child_cnt[c];
+        if (nch == 0) {
+            const int32_t f = first[c], e = first[c] + count[c];
+            for (int32_t s = f + j; s < e; s += kMomLanes) {
+                const double mm = pm[s];
+                sm += mm;
+                sx += mm * px[s];
+                sy += mm * py[s];
+                sz += mm * pz[s];
+            }
+        } else if (j < nch) {
+            const int32_t q = child_begin[c] + j;
+            sm = M[q];
+            sx = SX[q];
+            sy = SY[q];
+            sz = SZ[q];
         }
     }
-    M[c] = sm;
-    SX[c] = sx;
-    SY[c] = sy;
-    SZ[c] = sz;
+#pragma unroll
+    for (int o = kMomLanes / 2; o >= 1; o >>= 1) {
+        sm += __shfl_xor(sm, o, kMomLanes);
+        sx += __shfl_xor(sx, o, kMomLanes);
+        sy += __shfl_xor(sy, o, kMomLanes);
+        sz += __shfl_xor(sz, o, kMomLanes);
+    }
+    if (on && j == 0) {
+        M[c] = sm;
+        SX[c] = sx;
+        SY[c] = sy;
+        SZ[c] = sz;
+    }
 }
 
 // Preorder numbering: the cells starting at sorted index f form one chain
@@ -407,9 +425,9 @@ void build_cells_and_groups(Tree& t, int32_t* d_flag, hipStream_t st) {
     DevBuf<double> M(nn, st), SX(nn, st), SY(nn, st), SZ(nn, st);
     for (int L = (int)lvl_off.size() - 2; L >= 0; --L) {
         const int64_t beg = lvl_off[L], m = lvl_off[L + 1] - lvl_off[L];
-        hipLaunchKernelGGL(k_moments, dim3(grid_for(m, B, 1 << 30)), dim3(B), 0, st, beg, m, b.first.get(),
-                           b.count.get(), b.child_begin.get(), b.child_cnt.get(), t.px.get(), t.py.get(), t.pz.get(),
-                           t.pm.get(), M.get(), SX.get(), SY.get(), SZ.get());
+        hipLaunchKernelGGL(k_moments, dim3(grid_for(m, 256 / kMomLanes, 1 << 30)), dim3(256), 0, st, beg, m,
+                           b.first.get(), b.count.get(), b.child_begin.get(), b.child_cnt.get(), t.px.get(),
+                           t.py.get(), t.pz.get(), t.pm.get(), M.get(), SX.get(), SY.get(), SZ.get());
         SRF_HIP(hipGetLastError());
     }
 
