@@ -203,13 +203,24 @@ __global__ __launch_bounds__(256) void k_moments(int64_t begin, int64_t m, const
 // Preorder numbering: the cells starting at sorted index f form one chain
 // of consecutive levels (each the first child of the previous), so
 // pre(c) = start[f] + level(c) - minlevel(f), with start[] the exclusive
-// scan of the number of cells starting at each index.
+// scan of the number of cells starting at each index.  Every chain ends in
+// the leaf that starts at f, so each leaf walks up its chain (while the
+// parent starts at the same index) and stores the chain's length and top
+// level: one plain store per index, no atomics.
 __global__ void k_pre_count(int64_t nn, const int32_t* __restrict__ first, const int32_t* __restrict__ level,
+                            const int32_t* __restrict__ parent, const int32_t* __restrict__ child_cnt,
                             int32_t* __restrict__ cntf, int32_t* __restrict__ minlv) {
     int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (c >= nn) return;
-    atomicAdd(&cntf[first[c]], 1);
-    atomicMin(&minlv[first[c]], level[c]);
+    if (c >= nn || child_cnt[c] != 0) return;
+    const int32_t f = first[c];
+    int32_t top = level[c];
+    int32_t p = parent[c];
+    while (p >= 0 && first[p] == f) {
+        top = level[p];
+        p = parent[p];
+    }
+    cntf[f] = level[c] - top + 1;
+    minlv[f] = top;
 }
 
 __global__ void k_pre_assign(int64_t nn, const int32_t* __restrict__ first, const int32_t* __restrict__ level,
@@ -330,34 +341,44 @@ __global__ void k_group_count(int64_t ng, int64_t n, const int32_t* __restrict__
     gcount[g] = e - gfirst[g];
 }
 
-// Tight boxes: one wave per group (a group has at most 64 particles).
+// Tight boxes: 16 lanes per group, lane j taking the group's particles
+// j, j + 16, ... (min and max are exact in any order).
+constexpr int kBoxLanes = 16;
+
 __global__ __launch_bounds__(256) void k_group_bbox(int64_t ng, const int32_t* __restrict__ gfirst,
                                                     const int32_t* __restrict__ gcount, const double* __restrict__ px,
                                                     const double* __restrict__ py, const double* __restrict__ pz,
                                                     double* __restrict__ lo, double* __restrict__ hi) {
-    int64_t g = blockIdx.x * 4 + (threadIdx.x >> 6);
-    int lane = threadIdx.x & 63;
-    if (g >= ng) return;
-    int32_t f = gfirst[g], cnt = gcount[g];
-    int32_t s = f + (lane < cnt ? lane : 0);
-    double v[3] = {px[s], py[s], pz[s]};
+    const int64_t g = blockIdx.x * (int64_t)(256 / kBoxLanes) + threadIdx.x / kBoxLanes;
+    const int j = threadIdx.x & (kBoxLanes - 1);
     double a[3], b[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        a[k] = v[k];
-        b[k] = v[k];
+        a[k] = INFINITY;
+        b[k] = -INFINITY;
+    }
+    if (g < ng) {
+        const int32_t f = gfirst[g], cnt = gcount[g];
+        for (int32_t q = j; q < cnt; q += kBoxLanes) {
+            const double v[3] = {px[f + q], py[f + q], pz[f + q]};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                a[k] = v[k] < a[k] ? v[k] : a[k];
+                b[k] = v[k] > b[k] ? v[k] : b[k];
+            }
+        }
     }
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
+    for (int o = kBoxLanes / 2; o >= 1; o >>= 1) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            double u = __shfl_xor(a[k], o, 64);
-            double w = __shfl_xor(b[k], o, 64);
+            const double u = __shfl_xor(a[k], o, kBoxLanes);
+            const double w = __shfl_xor(b[k], o, kBoxLanes);
             a[k] = u < a[k] ? u : a[k];
             b[k] = w > b[k] ? w : b[k];
         }
     }
-    if (lane == 0) {
+    if (g < ng && j == 0) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             lo[g * 3 + k] = a[k];
@@ -434,9 +455,8 @@ void build_cells_and_groups(Tree& t, int32_t* d_flag, hipStream_t st) {
     // preorder renumbering
     DevBuf<int32_t> cntf(n + 1, st), minlv(n + 1, st), bfs2pre(nn, st);
     fill_i32(cntf.get(), 0, n + 1, st);
-    fill_i32(minlv.get(), 1 << 20, n + 1, st);
     hipLaunchKernelGGL(k_pre_count, dim3(grid_for(nn, B, 1 << 30)), dim3(B), 0, st, nn, b.first.get(), b.level.get(),
-                       cntf.get(), minlv.get());
+                       b.parent.get(), b.child_cnt.get(), cntf.get(), minlv.get());
     SRF_HIP(hipGetLastError());
     exclusive_scan_i32(cntf.get(), n, true, st);  // cntf[n] = nn
     hipLaunchKernelGGL(k_pre_assign, dim3(grid_for(nn, B, 1 << 30)), dim3(B), 0, st, nn, b.first.get(),
@@ -476,7 +496,7 @@ void build_cells_and_groups(Tree& t, int32_t* d_flag, hipStream_t st) {
     hipLaunchKernelGGL(k_group_count, dim3(grid_for(ng, B, 1 << 30)), dim3(B), 0, st, ng, n, t.gfirst.get(),
                        t.gcount.get());
     SRF_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_group_bbox, dim3((unsigned)((ng + 3) / 4)), dim3(256), 0, st, ng, t.gfirst.get(),
+    hipLaunchKernelGGL(k_group_bbox, dim3(grid_for(ng, 256 / kBoxLanes, 1 << 30)), dim3(256), 0, st, ng, t.gfirst.get(),
                        t.gcount.get(), t.px.get(), t.py.get(), t.pz.get(), t.glo.get(), t.ghi.get());
     SRF_HIP(hipGetLastError());
 }
