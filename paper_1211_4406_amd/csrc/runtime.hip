@@ -167,25 +167,39 @@ __device__ T block_excl_scan(T v, T* total) {
     return off + incl - v;
 }
 
+// The tile goes through LDS: read and written by the block in coalesced
+// rounds (value k * 256 + t by thread t), scanned as 8 consecutive values
+// per thread.
 template <class T>
 __global__ __launch_bounds__(kScanThreads) void k_scan_local(T* __restrict__ data, int64_t n_read, int64_t n_write,
                                                              T* __restrict__ sums) {
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    __shared__ T buf[kScanTile];
+    const int64_t b0 = (int64_t)blockIdx.x * kScanTile;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = b0 + k * kScanThreads + threadIdx.x;
+        buf[k * kScanThreads + threadIdx.x] = i < n_read ? data[i] : T(0);
+    }
+    __syncthreads();
     T v[kScanItems];
     T s = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        int64_t i = base + k;
-        v[k] = i < n_read ? data[i] : T(0);
+        v[k] = buf[threadIdx.x * kScanItems + k];
         s += v[k];
     }
     T tot;
-    T off = block_excl_scan(s, &tot);
+    T off = block_excl_scan(s, &tot);   // its barriers also order the reads above before the writes below
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        int64_t i = base + k;
-        if (i < n_write) data[i] = off;
+        buf[threadIdx.x * kScanItems + k] = off;
         off += v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = b0 + k * kScanThreads + threadIdx.x;
+        if (i < n_write) data[i] = buf[k * kScanThreads + threadIdx.x];
     }
     if (threadIdx.x == 0 && sums) sums[blockIdx.x] = tot;
 }

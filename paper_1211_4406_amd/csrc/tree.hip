@@ -148,10 +148,10 @@ __global__ void k_leaf_fix(int64_t begin, int64_t m, int32_t* __restrict__ child
 }
 
 // Bottom-up monopoles of one level: mass and mass-weighted position sums,
-// 16 lanes per cell.  A leaf's lane j takes its particles j, j + 16, ...
-// (consecutive lanes read consecutive particles); an inner cell's lane j
-// takes child j.  The row's 16 partial sums are then added by shuffles.
-constexpr int kMomLanes = 16;
+// 4 lanes per cell.  A leaf's lane j takes its particles j, j + 4, ...
+// (consecutive lanes read consecutive particles), an inner cell's lane j
+// its children j, j + 4.  The 4 partial sums are then added by shuffles.
+constexpr int kMomLanes = 4;
 
 __global__ __launch_bounds__(256) void k_moments(int64_t begin, int64_t m, const int32_t* __restrict__ first,
                                                  const int32_t* __restrict__ count,
@@ -177,12 +177,14 @@ __global__ __launch_bounds__(256) void k_moments(int64_t begin, int64_t m, const
                 sy += mm * py[s];
                 sz += mm * pz[s];
             }
-        } else if (j < nch) {
-            const int32_t q = child_begin[c] + j;
-            sm = M[q];
-            sx = SX[q];
-            sy = SY[q];
-            sz = SZ[q];
+        } else {
+            const int32_t cb = child_begin[c];
+            for (int32_t q = cb + j; q < cb + nch; q += kMomLanes) {
+                sm += M[q];
+                sx += SX[q];
+                sy += SY[q];
+                sz += SZ[q];
+            }
         }
     }
 #pragma unroll
