@@ -316,6 +316,40 @@ def test_centre_of_mass_mac(name, theta):
     assert e.value.status == -5
 
 
+def max_expand_chunk(ot):
+    """Largest number of entries in 64 consecutive items (leaves and accepted
+    cells, in preorder) of any group's list, from the oracle's structure."""
+    t, L = ot.tree, ot.lists
+    leaf_of = np.full(ot.n, -1)
+    for i in np.nonzero(t.leaf)[0]:
+        leaf_of[t.first[i]:t.first[i] + t.count[i]] = i
+    best = 0
+    for g in range(ot.n_groups):
+        leaves = np.unique(leaf_of[L.pidx[L.poff[g]:L.poff[g + 1]]])
+        cells = L.nidx[L.noff[g]:L.noff[g + 1]]
+        ids = np.concatenate([leaves, cells])
+        size = np.concatenate([t.count[leaves], np.ones(cells.size, np.int64)])[np.argsort(ids, kind="stable")]
+        for c0 in range(0, size.size, 64):
+            best = max(best, int(size[c0:c0 + 64].sum()))
+    return best
+
+
+def test_lists_with_leaves_of_64():
+    """Leaves of up to 64 particles: some chunks of 64 items expand to more
+    entries than the expansion's LDS buffer holds (1024) and take its direct
+    path; the lists must equal the oracle's bit for bit."""
+    ps = synth.small_clustered(20000, 101, r_cut=0.1, eps=2e-4, theta=0.5, per_halo=1000)
+    params = synth.Params(1.0, 0.1, 2e-4, 0.5, 64, 64)
+    say(f"[gpu] n_leaf=64 n={ps.n}")
+    ot = oracle.OracleTree(ps.x, ps.y, ps.z, ps.m, params)
+    assert max_expand_chunk(ot) > 1024
+    tree, lists, a32 = gpu_forward(ps, params)
+    check_structure(tree, lists, ot)
+    st = rel_stats(a32, ot.force())
+    say(f"    force {st}")
+    assert st["rms"] <= FP32_TOL
+
+
 @pytest.mark.parametrize("n_group,n_leaf", [(1, 1), (8, 4), (16, 16), (33, 7)])
 def test_other_group_sizes(n_group, n_leaf):
     """Groups and leaves other than the workloads' 64 / 16: bit-exact
