@@ -129,9 +129,10 @@ struct ItemWriter {
 // counted in totals[3], and the lists are then rebuilt with WRITE = true:
 // a second walk that stores the items of every group compactly at ioff).
 constexpr int64_t kSlot = 2048;
+constexpr int kListThreads = 64;   // one wave per block (128 and 256 measured slower)
 
 template <int G, bool WRITE, bool COM>
-__global__ __launch_bounds__(128) void k_lists(int64_t ng, const double* __restrict__ glo,
+__global__ __launch_bounds__(kListThreads) void k_lists(int64_t ng, const double* __restrict__ glo,
                                                const double* __restrict__ ghi, const int32_t* __restrict__ gcount,
                                                const uint4* __restrict__ pack, const NodeRange* __restrict__ rng,
                                                const double* __restrict__ nX, const double* __restrict__ nY,
@@ -142,7 +143,7 @@ __global__ __launch_bounds__(128) void k_lists(int64_t ng, const double* __restr
     static_assert(G * kLevels <= 64, "level masks must fit one word");
     const int64_t t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int64_t g0 = t * G;
-    __shared__ int32_t wbuf[128 * G * kWcStride];
+    __shared__ int32_t wbuf[kListThreads * G * kWcStride];
     Frame f[G];
     int64_t np[G], nc[G], w[G];
     ItemWriter out[G];
@@ -321,7 +322,7 @@ void build_lists(const Tree& t, Lists& l, hipStream_t st) {
     DevBuf<int32_t> slots(ng * kSlot > 0 ? ng * kSlot : 1, st);
     DevBuf<unsigned long long> totals(4, st);
     fill_u64(totals.get(), 0ull, 4, st);
-    const int B = 128;
+    const int B = kListThreads;
     constexpr int G = kGroupsPerThread;
     const int64_t nthreads = (ng + G - 1) / G;
     if (l.mac == SRF_MAC_COM)
