@@ -268,9 +268,10 @@ __global__ void k_green(double2* __restrict__ mesh, int n, double r_cut, double 
     mesh[idx] = make_double2(v.x * g, v.y * g);
 }
 
-// 5. a = -grad phi, fourth-order central differences, from the real parts
-__global__ void k_fd4(const double2* __restrict__ phi, int n, double* __restrict__ ax, double* __restrict__ ay,
-                      double* __restrict__ az) {
+// 5. a = -grad phi, fourth-order central differences, from the real parts;
+// the three components of a mesh point side by side (x, y, z, unused), so
+// that the interpolation reads one 32-byte record per stencil point
+__global__ void k_fd4(const double2* __restrict__ phi, int n, double4* __restrict__ acc) {
     const int64_t nn = n;
     const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (idx >= nn * nn * nn) return;
@@ -282,16 +283,18 @@ __global__ void k_fd4(const double2* __restrict__ phi, int n, double* __restrict
         return phi[((int64_t)x * nn + y) * nn + z].x;
     };
     const double c1 = 2.0 / 3.0 * n, c2 = 1.0 / 12.0 * n;
-    ax[idx] = -(c1 * (at(ix + 1, iy, iz) - at(ix - 1, iy, iz)) - c2 * (at(ix + 2, iy, iz) - at(ix - 2, iy, iz)));
-    ay[idx] = -(c1 * (at(ix, iy + 1, iz) - at(ix, iy - 1, iz)) - c2 * (at(ix, iy + 2, iz) - at(ix, iy - 2, iz)));
-    az[idx] = -(c1 * (at(ix, iy, iz + 1) - at(ix, iy, iz - 1)) - c2 * (at(ix, iy, iz + 2) - at(ix, iy, iz - 2)));
+    double4 a;
+    a.x = -(c1 * (at(ix + 1, iy, iz) - at(ix - 1, iy, iz)) - c2 * (at(ix + 2, iy, iz) - at(ix - 2, iy, iz)));
+    a.y = -(c1 * (at(ix, iy + 1, iz) - at(ix, iy - 1, iz)) - c2 * (at(ix, iy + 2, iz) - at(ix, iy - 2, iz)));
+    a.z = -(c1 * (at(ix, iy, iz + 1) - at(ix, iy, iz - 1)) - c2 * (at(ix, iy, iz + 2) - at(ix, iy, iz - 2)));
+    a.w = 0.0;
+    acc[idx] = a;
 }
 
 // 6. TSC interpolation at the sorted particles; output in input order
 __global__ void k_tsc_interp(int64_t np, const double* __restrict__ px, const double* __restrict__ py,
                              const double* __restrict__ pz, const int32_t* __restrict__ perm, int n,
-                             const double* __restrict__ mx, const double* __restrict__ my,
-                             const double* __restrict__ mz, double* __restrict__ ax, double* __restrict__ ay,
+                             const double4* __restrict__ acc, double* __restrict__ ax, double* __restrict__ ay,
                              double* __restrict__ az, int64_t os) {
     const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= np) return;
@@ -307,10 +310,10 @@ __global__ void k_tsc_interp(int64_t np, const double* __restrict__ px, const do
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const double w = wij * c.w[k];
-                const int64_t q = row + c.i[k];
-                fx += w * mx[q];
-                fy += w * my[q];
-                fz += w * mz[q];
+                const double4 m = acc[row + c.i[k]];
+                fx += w * m.x;
+                fy += w * m.y;
+                fz += w * m.z;
             }
         }
     const int64_t o = (int64_t)perm[s] * os;
@@ -340,7 +343,7 @@ void launch_pm(const Tree& t, double G, double r_cut, int n, double* ax, double*
     const int64_t cells = (int64_t)n * n * n;
     DevBuf<double2> mesh(cells, st);
     DevBuf<double2> tw(n / 2, st);
-    DevBuf<double> acc(3 * cells, st);
+    DevBuf<double4> acc(cells, st);
     if (ev0) SRF_HIP(hipEventRecord(ev0, st));
     fill_f64(reinterpret_cast<double*>(mesh.get()), 0.0, 2 * cells, st);
     hipLaunchKernelGGL(k_twiddle, dim3((unsigned)((n / 2 + 255) / 256)), dim3(256), 0, st, n, tw.get());
@@ -352,13 +355,10 @@ void launch_pm(const Tree& t, double G, double r_cut, int n, double* ax, double*
     hipLaunchKernelGGL(k_green, dim3(grid_for(cells, 256, 1 << 30)), dim3(256), 0, st, mesh.get(), n, r_cut, G);
     SRF_HIP(hipGetLastError());
     fft3(mesh.get(), n, tw.get(), true, st);
-    double* mx = acc.get();
-    double* my = mx + cells;
-    double* mz = my + cells;
-    hipLaunchKernelGGL(k_fd4, dim3(grid_for(cells, 256, 1 << 30)), dim3(256), 0, st, mesh.get(), n, mx, my, mz);
+    hipLaunchKernelGGL(k_fd4, dim3(grid_for(cells, 256, 1 << 30)), dim3(256), 0, st, mesh.get(), n, acc.get());
     SRF_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_tsc_interp, dim3(grid_for(np, 256, 1 << 30)), dim3(256), 0, st, np, t.px.get(), t.py.get(),
-                       t.pz.get(), t.perm.get(), n, mx, my, mz, ax, ay, az, os);
+                       t.pz.get(), t.perm.get(), n, acc.get(), ax, ay, az, os);
     SRF_HIP(hipGetLastError());
     if (ev1) SRF_HIP(hipEventRecord(ev1, st));
 }
