@@ -179,6 +179,25 @@ def test_edge_cases():
         assert s32["l2"] <= 1e-5 and s32["median"] <= 1e-5
 
 
+@pytest.mark.parametrize("n,distinct", [(4096, 4096), (4097, 4097), (8191, 8191), (100_000, 1000), (70_000, 7)])
+def test_sort_tiles_and_repeated_keys(n, distinct):
+    """The radix sort at exactly one tile of 4096 keys, one past it, one
+    short of two tiles, and with heavily repeated keys (each of `distinct`
+    positions taken by many particles, so long runs of equal digits inside
+    every tile and level-21 cells cut into groups): keys, permutation (ties
+    by input index), cells, groups and lists equal the oracle's."""
+    rng = np.random.default_rng(900 + distinct)
+    base = rng.random((distinct, 3))
+    pos = base[rng.integers(0, distinct, n)] if distinct < n else base
+    say(f"[gpu] sort n={n} distinct={distinct}")
+    p = synth.Params(1.0, 0.05, 1e-3, 0.5, 64, 16)
+    ps = synth.ParticleSet(pos[:, 0].copy(), pos[:, 1].copy(), pos[:, 2].copy(), np.full(n, 1.0 / n), p)
+    ot = oracle.OracleTree(ps.x, ps.y, ps.z, ps.m, p)
+    tree, lists, a32 = gpu_forward(ps, p)
+    check_structure(tree, lists, ot)
+    assert np.all(np.isfinite(a32))
+
+
 def test_lists_with_more_items_than_a_slot():
     """With single-particle leaves and a wide cutoff every group's list holds
     more than 2048 leaves and cells, which overflows the per-group slot of
