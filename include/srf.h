@@ -112,10 +112,12 @@ int srf_tree_build(int64_t n, const double* x, const double* y, const double* z,
 /* Step a6: per-group interaction lists.  A cell is pruned if its periodic
  * box-to-box distance to the group's bounding box is >= r_cut, accepted as
  * one monopole if side^2 < theta^2 d^2 (d: distance from the group box to
- * the cell centre), expanded to its particles if it is a leaf, and opened
- * otherwise (the decisions are made in FP64 without fused multiply-add).
+ * the cell centre, or to its centre of mass with SRF_MAC_COM), expanded to
+ * its particles if it is a leaf, and opened otherwise (the decisions are
+ * made in FP64 without fused multiply-add).
  * p must carry the n_group and n_leaf the tree was built with.
- * Synchronises `stream` once (to size the list buffer).
+ * Synchronises `stream` once (to size the list buffer), twice when some
+ * group's list holds more than 2048 leaves and accepted cells.
  * Errors: SRF_EINVAL, SRF_EMISMATCH, SRF_ENOMEM, SRF_EHIP. */
 int srf_make_lists(const srf_tree* t, const srf_params* p, void* stream, srf_lists** out);
 
