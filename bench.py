@@ -369,7 +369,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 pairs, f64 positions/moments/accumulation",
+        "dtype": "f32",
+        "precision": "f32 pair arithmetic on group-relative offsets; f64 positions, moments and accumulation",
         "data": "synthetic",
         "config": {"workload": f"{ps.name}: N={ps.n}, r_cut={ps.params.r_cut:.6g}, eps={ps.params.eps:g}, "
                                f"theta={ps.params.theta}, n_group={ps.params.n_group}, n_leaf={ps.params.n_leaf}",
