@@ -427,18 +427,32 @@ class OracleTree:
         a[self.perm] = self.force_sorted() + self.quad_correction_sorted()
         return a
 
-    def adjoint(self, w):
-        """a9: (dL/dx [N,3], dL/dm [N]) in input order for L = sum_i w_i . a_i."""
+    def _inputs(self, ux, uy, uz, m):
+        """Sorted positions and masses (the tree's own unless replaced, with
+        the structure held fixed) and the cell moments of them."""
+        ux = self.ux if ux is None else _f64(ux)
+        uy = self.uy if uy is None else _f64(uy)
+        uz = self.uz if uz is None else _f64(uz)
+        m = self.m if m is None else _f64(m)
+        if ux is self.ux and uy is self.uy and uz is self.uz and m is self.m:
+            M, X = self.M, self.X
+        else:
+            M, X = moments(self.tree, ux, uy, uz, m)
+        return ux, uy, uz, m, M, [np.ascontiguousarray(X[:, k]) for k in range(3)]
+
+    def adjoint(self, w, ux=None, uy=None, uz=None):
+        """a9: (dL/dx [N,3], dL/dm [N]) in input order for L = sum_i w_i . a_i
+        (optionally at other sorted positions, structure held fixed)."""
         p = self.params
         w = _f64(w)[self.perm]
         wx, wy, wz = (np.ascontiguousarray(w[:, k]) for k in range(3))
-        X0, X1, X2 = (np.ascontiguousarray(self.X[:, k]) for k in range(3))
+        ux, uy, uz, m, M, (X0, X1, X2) = self._inputs(ux, uy, uz, None)
         gx, gy, gz, gm = (np.empty(self.n) for _ in range(4))
         L = self.lists
         lib().or_tree_adjoint(_i64(self.n), _i64(self.n_groups), _ptr(self.gfirst), _ptr(self.gcount),
                               _ptr(L.poff), _ptr(L.pidx), _ptr(L.noff), _ptr(L.nidx),
                               _i64(self.tree.size), _ptr(self.tree.first), _ptr(self.tree.count),
-                              _ptr(self.ux), _ptr(self.uy), _ptr(self.uz), _ptr(self.m), _ptr(self.M),
+                              _ptr(ux), _ptr(uy), _ptr(uz), _ptr(m), _ptr(M),
                               _ptr(X0), _ptr(X1), _ptr(X2), _ptr(wx), _ptr(wy), _ptr(wz),
                               _d(p.G), _d(p.r_cut), _d(p.eps), _ptr(gx), _ptr(gy), _ptr(gz), _ptr(gm))
         gxs = np.stack([gx, gy, gz], axis=1)
@@ -447,6 +461,60 @@ class OracleTree:
         out_x[self.perm] = gxs
         out_m[self.perm] = gm
         return out_x, out_m
+
+    def force_bound_sorted(self, u_k, u_c=2.0 ** -53, e_abs=0.0, sel=None):
+        """Per-particle error magnitude E of the same-list force (sorted order;
+        only the groups `sel` if given): the sum over the list of
+        m_j ||J|| e_j, e_j the uncertainty of the pair's offset when the group-
+        relative offsets and their difference are rounded with unit roundoff
+        u_k, every offset is further moved by up to e_abs, and cell centres of
+        mass carry their FP64 summation error u_c (2 n_c + 2).  A kernel that
+        sums K terms in working precision is then within about (K + pair
+        roundings) * E of the exact result."""
+        p = self.params
+        X0, X1, X2 = (np.ascontiguousarray(self.X[:, k]) for k in range(3))
+        E = np.zeros(self.n)
+        L = self.lists
+        if sel is None:
+            sel_arr, nsel = None, -1
+        else:
+            sel_arr = np.ascontiguousarray(sel, dtype=np.int64)
+            nsel = sel_arr.size
+        lib().or_tree_force_bound(_i64(self.n_groups), _ptr(self.gfirst), _ptr(self.gcount), _ptr(L.poff),
+                                  _ptr(L.pidx), _ptr(L.noff), _ptr(L.nidx), _ptr(self.ux), _ptr(self.uy),
+                                  _ptr(self.uz), _ptr(self.m), _ptr(self.M), _ptr(X0), _ptr(X1), _ptr(X2),
+                                  _ptr(self.tree.count), _ptr(self.lo), _ptr(self.hi), _d(p.G), _d(p.r_cut),
+                                  _d(p.eps), _d(u_k), _d(u_c), _d(e_abs), _ptr(sel_arr), _i64(nsel), _ptr(E))
+        return E
+
+    def force_bound(self, u_k, u_c=2.0 ** -53, e_abs=0.0):
+        """force_bound_sorted in input order."""
+        out = np.empty(self.n)
+        out[self.perm] = self.force_bound_sorted(u_k, u_c, e_abs)
+        return out
+
+    def adjoint_bound(self, w, u_k, u_c=2.0 ** -53, e_abs=0.0):
+        """Per-particle error magnitudes (Ex, Em) of dL/dx and dL/dm, input
+        order, under the perturbations of force_bound_sorted: per pair the
+        error of J w is |w| (u_k ||J|| + ||dJ/dd|| e) and that of w . F is
+        |w| ||J|| e, passed from cells to their particles by the chain rule."""
+        p = self.params
+        w = _f64(w)[self.perm]
+        wx, wy, wz = (np.ascontiguousarray(w[:, k]) for k in range(3))
+        X0, X1, X2 = (np.ascontiguousarray(self.X[:, k]) for k in range(3))
+        Ex, Em = np.empty(self.n), np.empty(self.n)
+        L = self.lists
+        lib().or_tree_adjoint_bound(_i64(self.n), _i64(self.n_groups), _ptr(self.gfirst), _ptr(self.gcount),
+                                    _ptr(L.poff), _ptr(L.pidx), _ptr(L.noff), _ptr(L.nidx),
+                                    _i64(self.tree.size), _ptr(self.tree.first), _ptr(self.tree.count),
+                                    _ptr(self.ux), _ptr(self.uy), _ptr(self.uz), _ptr(self.m), _ptr(self.M),
+                                    _ptr(X0), _ptr(X1), _ptr(X2), _ptr(wx), _ptr(wy), _ptr(wz), _ptr(self.lo),
+                                    _ptr(self.hi), _d(p.G), _d(p.r_cut), _d(p.eps), _d(u_k), _d(u_c), _d(e_abs),
+                                    _ptr(Ex), _ptr(Em))
+        ox, om = np.empty(self.n), np.empty(self.n)
+        ox[self.perm] = Ex
+        om[self.perm] = Em
+        return ox, om
 
     def loss(self, w, ux=None, uy=None, uz=None, m=None):
         """L = sum_i w_i . a_i with the structure fixed; w in input order."""

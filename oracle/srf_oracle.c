@@ -981,3 +981,176 @@ void or_tree_adjoint(int64_t n, int64_t ng, const int64_t* gfirst, const int64_t
     }
     free(P); free(Q);
 }
+
+/* ================================================================== */
+/* First-order error magnitudes of the same-list force and gradient    */
+/* ================================================================== */
+
+/* The parity tests compare a kernel that evaluates each pair on offsets from
+ * its group's centre, rounded to a working precision with unit roundoff
+ * u_k, against the FP64 results above.  These functions return, for every
+ * particle, a magnitude E such that a result whose every pair term carries
+ * errors of the sizes below differs from the exact one by at most a small
+ * multiple of E (the multiple, set by how many terms are summed in working
+ * precision, is the test's constant):
+ *   - each position enters the pair through d = o_s - o_i, o_i = x_i - c_g,
+ *     o_s = image of x_s - c_g (c_g the centre of the group's box); rounding
+ *     o_i, o_s and d perturbs d by at most u_k (|d| + |o_i| + |o_s|);
+ *   - e_abs: a further absolute perturbation of every d (a test moves every
+ *     particle by at most e_abs / 2);
+ *   - a cell's centre of mass and mass are sums of its n_c particles, exact
+ *     up to u_c (2 n_c + 2) in position (|x| <= 1) and relative in mass.
+ * With J = dF/dd = phi I + psi d d^T (psi = phi'/r, chi = psi'/r):
+ *   ||J|| <= nJ = |phi| + |psi| r^2,
+ *   ||dJ/dd|| (as a map of two vectors) <= nH = 3 |psi| r + |chi| r^3,
+ * so a perturbation e of d changes F by at most nJ e and J w by at most
+ * nH e |w|; a relative rounding u_k of the pair arithmetic changes F by at
+ * most u_k nJ |d| and J w by u_k nJ |w|.  Self pairs (d = 0 from the same
+ * particle) contribute nothing and are skipped, as in the sums. */
+static void bound_coefs(double r2, double rc, double eps, double* nJ, double* nH) {
+    *nJ = *nH = 0.0;
+    if (!(r2 < rc * rc)) return;
+    double p = phi_of(r2, rc, eps);
+    if (!(r2 > 0.0)) { *nJ = fabs(p); return; }
+    double psi, chi, r = sqrt(r2);
+    quad_coefs(r2, rc, eps, &psi, &chi);
+    *nJ = fabs(p) + fabs(psi) * r2;
+    *nH = 3.0 * fabs(psi) * r + fabs(chi) * r * r2;
+}
+
+static double norm3(double a, double b, double c) { return sqrt(a * a + b * b + c * c); }
+
+/* Position uncertainty of one pair (see above); `nc` < 0 for a particle source. */
+static double pair_unc(const double d[3], const double oi[3], const double os[3], double u_k, double u_c,
+                       double e_abs, int64_t nc) {
+    double e = u_k * (norm3(d[0], d[1], d[2]) + norm3(oi[0], oi[1], oi[2]) + norm3(os[0], os[1], os[2])) + e_abs;
+    if (nc >= 0) e += u_c * (2.0 * (double)nc + 2.0);
+    return e;
+}
+
+/* Force: E_i = |G| sum over the list of mu nJ e_pair (sorted order; sel/nsel
+ * as in or_tree_force). */
+void or_tree_force_bound(int64_t ng, const int64_t* gfirst, const int64_t* gcount,
+                         const int64_t* poff, const int64_t* pidx, const int64_t* noff, const int64_t* nidx,
+                         const double* ux, const double* uy, const double* uz, const double* m,
+                         const double* NM, const double* NX, const double* NY, const double* NZ,
+                         const int64_t* ncount, const double* lo, const double* hi,
+                         double G, double rc, double eps, double u_k, double u_c, double e_abs,
+                         const int64_t* sel, int64_t nsel, double* E) {
+    int64_t todo = nsel < 0 ? ng : nsel;
+    #pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < todo; ++q) {
+        int64_t g = nsel < 0 ? q : sel[q];
+        double cg[3], hg[3];
+        group_frame(lo, hi, g, cg, hg);
+        for (int64_t i = gfirst[g]; i < gfirst[g] + gcount[g]; ++i) {
+            double oi[3] = {ux[i] - cg[0], uy[i] - cg[1], uz[i] - cg[2]};
+            double acc = 0.0, nJ, nH;
+            for (int64_t e = poff[g]; e < poff[g + 1]; ++e) {
+                int64_t j = pidx[e];
+                if (j == i) continue;
+                double d[3] = {mimage(ux[j] - ux[i]), mimage(uy[j] - uy[i]), mimage(uz[j] - uz[i])};
+                double os[3] = {mimage(ux[j] - cg[0]), mimage(uy[j] - cg[1]), mimage(uz[j] - cg[2])};
+                bound_coefs(d[0] * d[0] + d[1] * d[1] + d[2] * d[2], rc, eps, &nJ, &nH);
+                acc += m[j] * nJ * pair_unc(d, oi, os, u_k, u_c, e_abs, -1);
+            }
+            for (int64_t e = noff[g]; e < noff[g + 1]; ++e) {
+                int64_t c = nidx[e];
+                double d[3] = {mimage(NX[c] - ux[i]), mimage(NY[c] - uy[i]), mimage(NZ[c] - uz[i])};
+                double os[3] = {mimage(NX[c] - cg[0]), mimage(NY[c] - cg[1]), mimage(NZ[c] - cg[2])};
+                bound_coefs(d[0] * d[0] + d[1] * d[1] + d[2] * d[2], rc, eps, &nJ, &nH);
+                acc += NM[c] * nJ * pair_unc(d, oi, os, u_k, u_c, e_abs, ncount[c]);
+            }
+            E[i] = fabs(G) * acc;
+        }
+    }
+}
+
+/* Gradient: per pair (target i with weight w, source of mass mu), with e the
+ * pair's position uncertainty,
+ *   error of J w:      |w| (u_k nJ + nH e)  -> to dL/dx of the target (x mu) and of the source,
+ *   error of w . F:    |w| nJ e             -> to dL/dm of the source;
+ * a cell source collects them (EX with its mass, EM) together with
+ * GX >= |dL/dX_c| and passes them to its particles k as the chain rule does:
+ *   Ex_k += (m_k / M_c) (EX + GX u_c (2 n_c + 2)),
+ *   Em_k += EM + |x_k - X_c| EX / M_c + (GX / M_c) (e_abs + u_c (2 n_c + 2)).
+ * Outputs in sorted order, times |G|. */
+void or_tree_adjoint_bound(int64_t n, int64_t ng, const int64_t* gfirst, const int64_t* gcount,
+                           const int64_t* poff, const int64_t* pidx, const int64_t* noff, const int64_t* nidx,
+                           int64_t nnodes, const int64_t* nfirst, const int64_t* ncount,
+                           const double* ux, const double* uy, const double* uz, const double* m,
+                           const double* NM, const double* NX, const double* NY, const double* NZ,
+                           const double* wx, const double* wy, const double* wz, const double* lo, const double* hi,
+                           double G, double rc, double eps, double u_k, double u_c, double e_abs,
+                           double* Ex, double* Em) {
+    int nt = or_num_threads();
+    /* per-thread accumulators: particles (Ex, Em) and cells (EX, EM, GX) */
+    double* pbuf = (double*)calloc((size_t)nt * (size_t)n * 2, sizeof(double));
+    double* nbuf = (double*)calloc((size_t)nt * (size_t)nnodes * 3, sizeof(double));
+    #pragma omp parallel
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double* pb = pbuf + (size_t)tid * (size_t)n * 2;
+        double* nb = nbuf + (size_t)tid * (size_t)nnodes * 3;
+        #pragma omp for schedule(dynamic, 4)
+        for (int64_t g = 0; g < ng; ++g) {
+            double cg[3], hg[3];
+            group_frame(lo, hi, g, cg, hg);
+            for (int64_t i = gfirst[g]; i < gfirst[g] + gcount[g]; ++i) {
+                double oi[3] = {ux[i] - cg[0], uy[i] - cg[1], uz[i] - cg[2]};
+                double wn = norm3(wx[i], wy[i], wz[i]), nJ, nH;
+                for (int64_t e = poff[g]; e < poff[g + 1]; ++e) {
+                    int64_t j = pidx[e];
+                    if (j == i) continue;
+                    double d[3] = {mimage(ux[j] - ux[i]), mimage(uy[j] - uy[i]), mimage(uz[j] - uz[i])};
+                    double os[3] = {mimage(ux[j] - cg[0]), mimage(uy[j] - cg[1]), mimage(uz[j] - cg[2])};
+                    bound_coefs(d[0] * d[0] + d[1] * d[1] + d[2] * d[2], rc, eps, &nJ, &nH);
+                    double un = pair_unc(d, oi, os, u_k, u_c, e_abs, -1);
+                    double tV = wn * (u_k * nJ + nH * un);
+                    pb[2 * i] += m[j] * tV;
+                    pb[2 * j] += m[j] * tV;
+                    pb[2 * j + 1] += wn * nJ * un;
+                }
+                for (int64_t e = noff[g]; e < noff[g + 1]; ++e) {
+                    int64_t c = nidx[e];
+                    double d[3] = {mimage(NX[c] - ux[i]), mimage(NY[c] - uy[i]), mimage(NZ[c] - uz[i])};
+                    double os[3] = {mimage(NX[c] - cg[0]), mimage(NY[c] - cg[1]), mimage(NZ[c] - cg[2])};
+                    bound_coefs(d[0] * d[0] + d[1] * d[1] + d[2] * d[2], rc, eps, &nJ, &nH);
+                    double un = pair_unc(d, oi, os, u_k, u_c, e_abs, ncount[c]);
+                    double tV = wn * (u_k * nJ + nH * un);
+                    pb[2 * i] += NM[c] * tV;
+                    nb[3 * c] += NM[c] * tV;
+                    nb[3 * c + 1] += wn * nJ * un;
+                    nb[3 * c + 2] += NM[c] * wn * nJ;
+                }
+            }
+        }
+    }
+    double* P = (double*)calloc((size_t)n * 2, sizeof(double));
+    double* Q = (double*)calloc((size_t)nnodes * 3, sizeof(double));
+    #pragma omp parallel for
+    for (int64_t k = 0; k < n * 2; ++k)
+        for (int t = 0; t < nt; ++t) P[k] += pbuf[(size_t)t * (size_t)n * 2 + k];
+    #pragma omp parallel for
+    for (int64_t k = 0; k < nnodes * 3; ++k)
+        for (int t = 0; t < nt; ++t) Q[k] += nbuf[(size_t)t * (size_t)nnodes * 3 + k];
+    free(pbuf); free(nbuf);
+    for (int64_t c = 0; c < nnodes; ++c) {
+        double EXc = Q[3 * c], EMc = Q[3 * c + 1], GXc = Q[3 * c + 2];
+        if (EXc == 0.0 && EMc == 0.0 && GXc == 0.0) continue;
+        double uc = u_c * (2.0 * (double)ncount[c] + 2.0);
+        for (int64_t k = nfirst[c]; k < nfirst[c] + ncount[c]; ++k) {
+            P[2 * k] += (m[k] / NM[c]) * (EXc + GXc * uc);
+            P[2 * k + 1] += EMc + norm3(ux[k] - NX[c], uy[k] - NY[c], uz[k] - NZ[c]) * EXc / NM[c]
+                          + (GXc / NM[c]) * (e_abs + uc);
+        }
+    }
+    for (int64_t k = 0; k < n; ++k) {
+        Ex[k] = fabs(G) * P[2 * k];
+        Em[k] = fabs(G) * P[2 * k + 1];
+    }
+    free(P); free(Q);
+}
