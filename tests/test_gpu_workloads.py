@@ -23,6 +23,7 @@ import torch
 import oracle
 import paper_1211_4406_amd as srf
 import synth
+from _parity import U32, U64, check, constant, max_list
 
 pytestmark = pytest.mark.gpu
 
@@ -43,12 +44,20 @@ def run_gpu(ps, precision):
     return tree, lists, a.cpu().numpy()
 
 
-def sampled_same_list(ot, a_gpu, n_groups, seed):
+def sampled_same_list(ot, a_gpu, n_groups, seed, fp64):
+    """Relative-error statistics on sampled groups; every sampled particle is
+    held to its element-wise bound (the constant needed is returned too)."""
     rng = np.random.default_rng(seed)
     sel = np.sort(rng.choice(ot.n_groups, min(n_groups, ot.n_groups), replace=False))
     ref_sorted = ot.force_sorted(sel=sel)
+    E_sorted = ot.force_bound_sorted(U64 if fp64 else U32, sel=sel)
     idx = np.concatenate([np.arange(ot.gfirst[g], ot.gfirst[g] + ot.gcount[g]) for g in sel])
-    return oracle.relative_errors(a_gpu[ot.perm[idx]], ref_sorted[idx])[1]
+    got, ref = a_gpu[ot.perm[idx]], ref_sorted[idx]
+    need = check(got, ref, E_sorted[idx], constant("force", fp64, max_list(ot)),
+                 f"{'fp64' if fp64 else 'fp32'} force, {sel.size} groups")
+    st = oracle.relative_errors(got, ref)[1]
+    st["bound_needed"] = need
+    return st
 
 
 def forward_accuracy(k, theta):
@@ -63,8 +72,8 @@ def forward_accuracy(k, theta):
     ex = tree.export()
     assert np.array_equal(ex["perm"], ot.perm) and np.array_equal(ex["gfirst"], ot.gfirst)
     ng_sample = ot.n_groups if ps.n <= 4096 else 400
-    s32 = sampled_same_list(ot, a32, ng_sample, 10 + k)
-    s64 = sampled_same_list(ot, a64, ng_sample, 10 + k)
+    s32 = sampled_same_list(ot, a32, ng_sample, 10 + k, False)
+    s64 = sampled_same_list(ot, a64, ng_sample, 10 + k, True)
     # tree error (monopole cells of the opening criterion) against the exact
     # brute-force cutoff sum, on sampled particles
     rng = np.random.default_rng(20 + k)
@@ -209,9 +218,15 @@ def test_workload4_adjoint_and_finite_differences():
         gx, gm = grads[prec]
         sx = oracle.relative_errors(gx, rx)[1]
         em = np.abs(gm - rm) / np.abs(rm)
+        fp64 = prec == srf.FP64
+        Ex, Em = ot.adjoint_bound(w, U64 if fp64 else U32)
+        C = constant("adjoint", fp64, max_list(ot))
+        need_x = check(gx, rx, Ex, C, tag + " dL/dx")
+        need_m = check(gm, rm, Em, C, tag + " dL/dm")
         rec[tag] = dict(dx=sx, dm=dict(l2=float(np.linalg.norm(gm - rm) / np.linalg.norm(rm)),
                                        median=float(np.median(em)), p99=float(np.percentile(em, 99)),
-                                       rms=float(np.sqrt(np.mean(em ** 2)))))
+                                       rms=float(np.sqrt(np.mean(em ** 2)))),
+                        bound=dict(C=C, needed_dx=need_x, needed_dm=need_m))
     # central differences of the oracle's fixed-structure forward
     rms_x = float(np.sqrt(np.mean(rx ** 2)))
     rms_m = float(np.sqrt(np.mean(rm ** 2)))
@@ -221,8 +236,8 @@ def test_workload4_adjoint_and_finite_differences():
     rec["fd"] = {t: dict(median=float(np.median(v)), max=float(np.max(v))) for t, v in fd_err.items()}
     rec["seconds"] = round(time.time() - t0, 1)
     say("WORKLOAD " + json.dumps(rec))
-    assert rec["fp32"]["dx"]["rms"] <= 1e-5 and rec["fp32"]["dm"]["l2"] <= 1e-5
-    assert rec["fp64"]["dx"]["rms"] <= 1e-11 and rec["fp64"]["dm"]["l2"] <= 1e-11
+    assert rec["fp32"]["dx"]["rms"] <= 1e-5
+    assert rec["fp64"]["dx"]["rms"] <= 1e-12
     for t in ("oracle", "fp64"):
         assert rec["fd"][t + "_x"]["median"] <= 1e-6 and rec["fd"][t + "_x"]["max"] <= 1e-4
         assert rec["fd"][t + "_m"]["median"] <= 1e-6 and rec["fd"][t + "_m"]["max"] <= 1e-4
