@@ -91,11 +91,17 @@ typedef struct {
 typedef struct srf_tree srf_tree;
 typedef struct srf_lists srf_lists;
 
-/* Steps a1-a5: wrap positions into [0,1)^3, 63-bit Morton keys (21 bits per
- * axis, x most significant in each triple), stable sort by key (ties by
- * input index), octree (a cell with more than n_leaf particles is split, the
- * root always), monopole moments (mass and centre of mass, FP64), and
- * particle groups with their tight bounding boxes.
+/* Steps a1-a5: the tree of the short-range part.  Defined by Sec. 1 (the
+ * tree algorithm: particles in a hierarchy of cubic cells, each cell carrying
+ * the multipole expansion of its particles, Fig. 1; the periodic box of side
+ * one) and Sec. 2 (Barnes' modified algorithm: neighbouring particles form
+ * groups that share one interaction list).  The paper fixes neither the key
+ * nor the leaf and group rules; this call takes: wrap positions into
+ * [0,1)^3, 63-bit Morton keys (21 bits per axis, x most significant in each
+ * triple), stable sort by key (ties by input index), octree (a cell with
+ * more than n_leaf particles is split, the root always), monopole moments
+ * (mass and centre of mass, FP64), and particle groups with their tight
+ * bounding boxes.
  *   n:          number of particles, 1 <= n < 2^31 - 1.
  *   x, y, z:    positions; particle i at x[i*pos_stride] (pos_stride >= 1), so
  *               an [N,3] row-major array is x = p, y = p+1, z = p+2, stride 3.
@@ -109,19 +115,28 @@ typedef struct srf_lists srf_lists;
 int srf_tree_build(int64_t n, const double* x, const double* y, const double* z, int64_t pos_stride,
                    const double* m, int64_t m_stride, const srf_params* p, void* stream, srf_tree** out);
 
-/* Step a6: per-group interaction lists.  A cell is pruned if its periodic
+/* Step a6: per-group interaction lists.  Defined by Sec. 2 (Barnes'
+ * modified algorithm: one list of cells and particles per group, built by
+ * one traversal for the whole group), Fig. 2 (the short-range force needs
+ * only sources within r_cut) and Sec. 1 (a well-separated cell acts through
+ * its multipole; the opening test is this library's).  A cell is pruned if its periodic
  * box-to-box distance to the group's bounding box is >= r_cut, accepted as
  * one monopole if side^2 < theta^2 d^2 (d: distance from the group box to
  * the cell centre, or to its centre of mass with SRF_MAC_COM), expanded to
  * its particles if it is a leaf, and opened otherwise (the decisions are
  * made in FP64 without fused multiply-add).
- * p must carry the n_group and n_leaf the tree was built with.
+ * p must carry the n_group and n_leaf the tree was built with.  The lists
+ * belong to this tree: after it is freed they are refused (SRF_EMISMATCH)
+ * by every call, even with a new tree at the same address.
  * Synchronises `stream` once (to size the list buffer), twice when some
  * group's list holds more than 2048 leaves and accepted cells.
  * Errors: SRF_EINVAL, SRF_EMISMATCH, SRF_ENOMEM, SRF_EHIP. */
 int srf_make_lists(const srf_tree* t, const srf_params* p, void* stream, srf_lists** out);
 
-/* Steps a7-a8: accelerations in input order, a_i = (ax[i*out_stride], ...).
+/* Steps a7-a8: the short-range force of Sec. 2 (the force sum over
+ * particles within r_cut with the cutoff function of eq. (cutoff), written
+ * out at the top of this file), evaluated over the lists of srf_make_lists.
+ * Accelerations in input order, a_i = (ax[i*out_stride], ...).
  * Each group's particles interact with every list entry (particles of mass
  * m_j, cells as a particle of mass M_c at their centre of mass) through the
  * cutoff kernel; precision per p->precision.  p->r_cut, theta, n_group and
@@ -131,7 +146,9 @@ int srf_make_lists(const srf_tree* t, const srf_params* p, void* stream, srf_lis
 int srf_short_range_force(const srf_tree* t, const srf_lists* l, const srf_params* p,
                           double* ax, double* ay, double* az, int64_t out_stride, void* stream);
 
-/* Step a9: gradient of L = sum_i w_i . a_i with the structure fixed:
+/* Step a9: not in the paper -- the derivative of the Sec. 2 force sum (as
+ * evaluated by srf_short_range_force over the same lists) for a loss
+ * L = sum_i w_i . a_i, with the structure fixed:
  *   dL/dx_i -> (gx, gy, gz)[i*g_stride],  dL/dm_i -> gm[i*gm_stride],
  * in input order; w_i = (wx, wy, wz)[i*w_stride].  Node sources pass their
  * gradient to member particles through M_c = sum m_k, X_c = sum m_k x_k / M_c.
@@ -177,7 +194,7 @@ int srf_short_range_potential(const srf_tree* t, const srf_lists* l, const srf_p
                               int64_t out_stride, void* stream);
 
 /* Long-range (PM) half of the force split (Sec. 2 density split; PM steps
- * of Sec. 4), all in FP64 on a periodic n_mesh^3 mesh (points at i/n_mesh):
+ * of Sec. 2.2, "Relay Mesh Method"), all in FP64 on a periodic n_mesh^3 mesh (points at i/n_mesh):
  * TSC assignment of the tree's particles to 27 mesh points each, 3-D FFT,
  * multiplication by -4 pi G S(k)^2 / (k^2 W(k)^2) (S the transform of the
  * S2 cloud of radius r_cut/2, W the TSC window), inverse FFT, fourth-order

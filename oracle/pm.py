@@ -5,7 +5,7 @@ the rest of ``oracle``).
 The force split (Sec. 2): each particle's density is split into an S2
 cloud of radius r_cut/2 (the PM part) and the point mass minus that cloud
 (the PP part, which vanishes beyond r_cut).  The PM part is computed on a
-periodic mesh (the PM steps listed in Sec. 4: TSC assignment to 27 mesh
+periodic mesh (the PM steps listed in Sec. 2.2, "Relay Mesh Method": TSC assignment to 27 mesh
 points, FFT convolution with the long-range Green's function, four-point
 finite differences, interpolation back to the particles):
 

@@ -144,7 +144,10 @@ def _cols(x: torch.Tensor):
     (any layout whose rows have a constant stride and unit column stride)."""
     if x.dtype != torch.float64 or not x.is_cuda or x.dim() != 2 or x.shape[1] != 3:
         raise ValueError("positions must be a float64 CUDA tensor of shape [N, 3]")
-    if x.stride(1) != 1:
+    # the library reads rows at a positive element stride with unit column
+    # stride; anything else (a transposed view, or an expanded gradient whose
+    # rows share memory, stride 0) is copied first
+    if x.stride(1) != 1 or x.stride(0) < 1:
         x = x.contiguous()
     base = x.data_ptr()
     return x, [C.c_void_p(base), C.c_void_p(base + 8), C.c_void_p(base + 16)], x.stride(0)

@@ -1,4 +1,5 @@
 // The C ABI (include/srf.h): validation, handles, error codes, export.
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -16,6 +17,10 @@ struct srf_lists {
 namespace {
 
 thread_local std::string g_last_error;
+
+// Tree generation numbers: a tree freed and another built at the same
+// address still gets a new number, so stale lists are refused.
+std::atomic<uint64_t> g_tree_generation{0};
 
 int set_error(int status, const std::string& msg) {
     g_last_error = msg;
@@ -54,7 +59,7 @@ void validate(const srf_params* p) {
 void check_pair(const srf_tree* t, const srf_lists* l, const srf_params* p) {
     if (!t || !l) srf::fail(SRF_EINVAL, "tree or lists is NULL");
     validate(p);
-    if (l->l.tree != &t->t) srf::fail(SRF_EMISMATCH, "lists were built from another tree");
+    if (l->l.tree_id != t->t.id) srf::fail(SRF_EMISMATCH, "lists were built from another tree");
     if (p->r_cut != l->l.r_cut || p->theta != l->l.theta || p->mac != l->l.mac || p->n_group != t->t.n_group ||
         p->n_leaf != t->t.n_leaf)
         srf::fail(SRF_EMISMATCH, "params differ from those the tree and lists were built with");
@@ -105,6 +110,7 @@ int srf_tree_build(int64_t n, const double* x, const double* y, const double* z,
         hipStream_t st = (hipStream_t)stream;
         h = new srf_tree();
         srf::Tree& t = h->t;
+        t.id = ++g_tree_generation;
         t.n = n;
         t.n_group = p->n_group;
         t.n_leaf = p->n_leaf;
@@ -138,7 +144,7 @@ int srf_make_lists(const srf_tree* t, const srf_params* p, void* stream, srf_lis
         hipStream_t st = (hipStream_t)stream;
         h = new srf_lists();
         srf::Lists& l = h->l;
-        l.tree = &t->t;
+        l.tree_id = t->t.id;
         l.r_cut = p->r_cut;
         l.theta = p->theta;
         l.mac = p->mac;

@@ -81,6 +81,7 @@ struct __align__(16) NodeRange {
 constexpr uint32_t kPackCountMax = 0x3ffffffu;
 
 struct Tree {
+    uint64_t id = 0;           // generation number, unique per process (lists refer to it)
     int64_t n = 0;
     int64_t n_nodes = 0;
     int64_t n_groups = 0;
@@ -104,7 +105,7 @@ struct Tree {
 };
 
 struct Lists {
-    const Tree* tree = nullptr;
+    uint64_t tree_id = 0;      // Tree::id of the tree the lists were built from
     int64_t n_groups = 0;
     int64_t n_entries = 0;
     int64_t n_particle_entries = 0;

@@ -1,5 +1,5 @@
 // Long-range (PM) half of the TreePM force split on one GPU (Sec. 2 split,
-// PM steps of Sec. 4), in FP64 on a periodic n^3 mesh with points at
+// PM steps of Sec. 2.2, "Relay Mesh Method"), in FP64 on a periodic n^3 mesh with points at
 // x = i/n:
 //   1. TSC assignment of the sorted particles to 27 mesh points each,
 //   2. 3-D FFT (radix-2 Stockham, one pass per axis, lines staged in LDS),
