@@ -161,6 +161,29 @@ int srf_short_range_adjoint(const srf_tree* t, const srf_lists* l, const srf_par
                             double* gx, double* gy, double* gz, int64_t g_stride,
                             double* gm, int64_t gm_stride, void* stream);
 
+/* Device workspace that srf_short_range_adjoint_noalloc holds on each GPU
+ * it runs on, from its first call there until the process ends. */
+#define SRF_NOALLOC_WORKSPACE_BYTES (128ull << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * computation, arguments and results of srf_short_range_adjoint, with every
+ * workspace (the j-side and i-side partial gradients and the cells' chain
+ * sums, 8 (7 n + 8 n_cells) bytes plus alignment, i.e. about 2 million
+ * particles at the usual 0.15 cells per particle) taken from a static device
+ * array of SRF_NOALLOC_WORKSPACE_BYTES per GPU.  It calls no hipMalloc or
+ * hipFree; its first call on a device looks up that device's copy of the
+ * array.  Every call on one GPU uses the same array, which keeps the last
+ * call's contents (this call clears what must start at zero): calls that
+ * overlap on one GPU, on other streams or threads, race.  The tree and lists
+ * are built as usual (those calls allocate).  No kernel timing is recorded.
+ * Errors: as srf_short_range_adjoint, and SRF_EINVAL when the tree needs
+ * more workspace than the array holds (nothing is launched then). */
+int srf_short_range_adjoint_noalloc(const srf_tree* t, const srf_lists* l, const srf_params* p,
+                                    const double* wx, const double* wy, const double* wz, int64_t w_stride,
+                                    double* gx, double* gy, double* gz, int64_t g_stride,
+                                    double* gm, int64_t gm_stride, void* stream);
+
 /* Quadrupole term of the cells (the cell expansion of Sec. 1 taken one
  * order past the monopole), ADDED to (ax, ay, az)[i*out_stride] in input
  * order: for every cell c in the list of particle i's group,

@@ -24,7 +24,7 @@ import torch
 
 __all__ = [
     "Params", "Tree", "Lists", "SrfError", "FP32_REL", "FP64", "MAC_CENTRE", "MAC_COM", "lib", "lib_path", "tree_build", "make_lists",
-    "short_range_force", "short_range_adjoint", "short_range_potential", "short_range_quadrupole", "ShortRange", "short_range", "pm_force", "kick", "drift",
+    "short_range_force", "short_range_adjoint", "short_range_adjoint_noalloc", "short_range_potential", "short_range_quadrupole", "ShortRange", "short_range", "pm_force", "kick", "drift",
     "TreePMIntegrator", "set_kernel_timing", "last_kernel_ms",
 ]
 
@@ -95,6 +95,7 @@ def lib():
     L.srf_make_lists.argtypes = [vp, pp, vp, C.POINTER(vp)]
     L.srf_short_range_force.argtypes = [vp, vp, pp, vp, vp, vp, i64, vp]
     L.srf_short_range_adjoint.argtypes = [vp, vp, pp, vp, vp, vp, i64, vp, vp, vp, i64, vp, i64, vp]
+    L.srf_short_range_adjoint_noalloc.argtypes = [vp, vp, pp, vp, vp, vp, i64, vp, vp, vp, i64, vp, i64, vp]
     L.srf_tree_free.argtypes = [vp]
     L.srf_tree_free.restype = None
     L.srf_lists_free.argtypes = [vp]
@@ -292,6 +293,22 @@ def short_range_adjoint(tree: Tree, lists: Lists, params: Params, w: torch.Tenso
     _check(lib().srf_short_range_adjoint(tree.handle, lists.handle, C.byref(cp), *wcols, C.c_int64(ws), *gcols,
                                          C.c_int64(gs), _dptr(gm), C.c_int64(1), _stream()))
     return gx, gm
+
+
+def short_range_adjoint_noalloc(tree: Tree, lists: Lists, params: Params, w: torch.Tensor, gx: torch.Tensor,
+                                gm: torch.Tensor) -> None:
+    """a9 into caller-provided outputs gx [N,3] and gm [N] (float64, device),
+    with the library's static device workspace: no device allocation."""
+    w, wcols, ws = _cols(w)
+    gx_, gcols, gs = _cols(gx)
+    if gx_.data_ptr() != gx.data_ptr():
+        raise ValueError("gx must have unit column stride")
+    if gm.dtype != torch.float64 or gm.dim() != 1 or gm.shape[0] != tree.n or not gm.is_cuda:
+        raise ValueError("gm must be a float64 CUDA vector of length n")
+    cp = params.c()
+    _check(lib().srf_short_range_adjoint_noalloc(tree.handle, lists.handle, C.byref(cp), *wcols, C.c_int64(ws),
+                                                 *gcols, C.c_int64(gs), _dptr(gm), C.c_int64(gm.stride(0)),
+                                                 _stream()))
 
 
 def short_range_potential(tree: Tree, lists: Lists, params: Params, out: torch.Tensor | None = None,

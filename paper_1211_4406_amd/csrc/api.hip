@@ -189,6 +189,20 @@ int srf_short_range_adjoint(const srf_tree* t, const srf_lists* l, const srf_par
     });
 }
 
+int srf_short_range_adjoint_noalloc(const srf_tree* t, const srf_lists* l, const srf_params* p, const double* wx,
+                                    const double* wy, const double* wz, int64_t w_stride, double* gx, double* gy,
+                                    double* gz, int64_t g_stride, double* gm, int64_t gm_stride, void* stream) {
+    return guarded([&] {
+        check_pair(t, l, p);
+        if (!wx || !wy || !wz || !gx || !gy || !gz || !gm) srf::fail(SRF_EINVAL, "NULL pointer");
+        if (w_stride < 1 || g_stride < 1 || gm_stride < 1) srf::fail(SRF_EINVAL, "strides must be >= 1");
+        if (t->t.n + t->t.n_nodes > INT32_MAX)
+            srf::fail(SRF_EINVAL, "the adjoint indexes particles and cells with 32-bit rows: n + n_cells too large");
+        srf::launch_adjoint_noalloc(t->t, l->l, *p, wx, wy, wz, w_stride, gx, gy, gz, g_stride, gm, gm_stride,
+                                    (hipStream_t)stream);
+    });
+}
+
 int srf_short_range_quadrupole(const srf_tree* t, const srf_lists* l, const srf_params* p, double* ax, double* ay,
                                double* az, int64_t out_stride, void* stream) {
     return guarded([&] {

@@ -162,6 +162,12 @@ void launch_quadrupole(const Tree& t, const Lists& l, const srf_params& p, doubl
 void launch_adjoint(const Tree& t, const Lists& l, const srf_params& p, const double* wx, const double* wy,
                     const double* wz, int64_t ws, double* gx, double* gy, double* gz, int64_t gs, double* gm,
                     int64_t gms, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);
+// The same on the library's static workspace: no allocation (SRF_EINVAL if
+// the tree needs more than SRF_NOALLOC_WORKSPACE_BYTES).
+void launch_adjoint_noalloc(const Tree& t, const Lists& l, const srf_params& p, const double* wx, const double* wy,
+                            const double* wz, int64_t ws, double* gx, double* gy, double* gz, int64_t gs,
+                            double* gm, int64_t gms, hipStream_t stream);
+size_t adjoint_workspace_bytes(int64_t n, int64_t n_nodes);
 
 // Fill helpers (kernels, safe under stream capture).
 void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);

@@ -21,6 +21,8 @@
 // powers of k = 2/r_cut folded into the coefficients; r is the unsoftened
 // distance.
 #include <cmath>
+#include <mutex>
+#include <string>
 
 #include "common.h"
 
@@ -915,20 +917,34 @@ void launch_potential(const Tree& t, const Lists& l, const srf_params& p, double
     SRF_HIP(hipGetLastError());
 }
 
-void launch_adjoint(const Tree& t, const Lists& l, const srf_params& p, const double* wx, const double* wy,
-                    const double* wz, int64_t ws, double* gx, double* gy, double* gz, int64_t gs, double* gm,
-                    int64_t gms, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+// Bytes of device workspace the adjoint needs: the j-side rows
+// [n + n_cells][4], the i-side [3][n] and the cells' chain sums [4][n_cells]
+// (FP64), each part starting on a 256-byte boundary.
+static size_t adjoint_part_bytes(int64_t count) { return ((size_t)count * sizeof(double) + 255) & ~size_t(255); }
+
+size_t adjoint_workspace_bytes(int64_t n, int64_t nn) {
+    return adjoint_part_bytes(4 * (n + nn)) + adjoint_part_bytes(3 * n) + adjoint_part_bytes(4 * nn);
+}
+
+// The adjoint on a caller-provided workspace of adjoint_workspace_bytes()
+// (256-byte aligned).  Its j-side rows are cleared here; the rest is written
+// in full before it is read, so nothing of an earlier call leaks through.
+static void adjoint_on(const Tree& t, const Lists& l, const srf_params& p, const double* wx, const double* wy,
+                       const double* wz, int64_t ws, double* gx, double* gy, double* gz, int64_t gs, double* gm,
+                       int64_t gms, void* work, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
     const int64_t n = t.n, nn = t.n_nodes, ng = t.n_groups;
-    DevBuf<double> rows(4 * (n + nn), st), part(3 * n, st), node(4 * nn, st);
+    char* w = static_cast<char*>(work);
     AdjOut o;
-    o.gj = rows.get();          // [n + nn][4], 32-byte aligned at the block start
+    o.gj = reinterpret_cast<double*>(w);          // [n + nn][4], 32-byte rows
     o.gn = o.gj + 4 * n;
-    o.gix = part.get();
+    w += adjoint_part_bytes(4 * (n + nn));
+    o.gix = reinterpret_cast<double*>(w);
     o.giy = o.gix + n;
     o.giz = o.giy + n;
+    w += adjoint_part_bytes(3 * n);
     o.n = n;
     o.nn = nn;
-    double* sax = node.get();
+    double* sax = reinterpret_cast<double*>(w);
     double* say = sax + nn;
     double* saz = say + nn;
     double* sb = saz + nn;
@@ -953,6 +969,52 @@ void launch_adjoint(const Tree& t, const Lists& l, const srf_params& p, const do
                        t.leaf_of.get(), t.px.get(), t.py.get(), t.pz.get(), t.pm.get(), t.nX.get(), t.nY.get(),
                        t.nZ.get(), o, sax, say, saz, sb, gx, gy, gz, gs, gm, gms);
     SRF_HIP(hipGetLastError());
+}
+
+void launch_adjoint(const Tree& t, const Lists& l, const srf_params& p, const double* wx, const double* wy,
+                    const double* wz, int64_t ws, double* gx, double* gy, double* gz, int64_t gs, double* gm,
+                    int64_t gms, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+    DevBuf<char> work(adjoint_workspace_bytes(t.n, t.n_nodes), st);
+    adjoint_on(t, l, p, wx, wy, wz, ws, gx, gy, gz, gs, gm, gms, work.get(), st, ev0, ev1);
+}
+
+// ------------------------------------------------- allocation-free adjoint
+// The workspace of srf_short_range_adjoint_noalloc: a file-scope device
+// array, one copy per GPU, held until the process ends.  Host code never
+// passes the array's own name to a kernel (on the host it is only a stand-in
+// for the symbol); it uses the device address that hipGetSymbolAddress
+// returns, looked up once per device with that device current.
+static __device__ __align__(256) double scratch[SRF_NOALLOC_WORKSPACE_BYTES / sizeof(double)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+void* scratch_on_current_device() {
+    int dev = 0;
+    SRF_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) fail(SRF_EINVAL, "device index beyond the workspace table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        SRF_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) fail(SRF_EHIP, "hipGetSymbolAddress returned no address for the workspace");
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
+void launch_adjoint_noalloc(const Tree& t, const Lists& l, const srf_params& p, const double* wx, const double* wy,
+                            const double* wz, int64_t ws, double* gx, double* gy, double* gz, int64_t gs,
+                            double* gm, int64_t gms, hipStream_t st) {
+    const size_t need = adjoint_workspace_bytes(t.n, t.n_nodes);
+    if (need > (size_t)SRF_NOALLOC_WORKSPACE_BYTES)
+        fail(SRF_EINVAL, "the allocation-free adjoint needs " + std::to_string(need) +
+                             " bytes of workspace for this tree; its static workspace holds " +
+                             std::to_string((size_t)SRF_NOALLOC_WORKSPACE_BYTES));
+    adjoint_on(t, l, p, wx, wy, wz, ws, gx, gy, gz, gs, gm, gms, scratch_on_current_device(), st, nullptr, nullptr);
 }
 
 }  // namespace srf
