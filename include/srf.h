@@ -109,7 +109,8 @@ typedef struct srf_lists srf_lists;
  *   m:          masses at m[i*m_stride]; must be finite and > 0.
  *   out:        (host) receives the new handle.
  * The inputs are copied; they may be reused once `stream` passes this call.
- * Synchronises `stream` once per tree level (to size the next level).
+ * Synchronises `stream` once (to read the number of cells and groups and
+ * the device's check of the inputs).
  * Errors: SRF_EINVAL, SRF_EDOMAIN (checked on the device, reported here),
  * SRF_ENOMEM, SRF_EHIP.  On error *out is NULL. */
 int srf_tree_build(int64_t n, const double* x, const double* y, const double* z, int64_t pos_stride,

@@ -118,11 +118,7 @@ int srf_tree_build(int64_t n, const double* x, const double* y, const double* z,
         srf::DevBuf<int32_t> flag(1, st);
         srf::fill_i32(flag.get(), 0, 1, st);
         srf::build_sorted(t, x, y, z, pos_stride, m, m_stride, flag.get(), st);
-        int32_t hf = 0;
-        SRF_HIP(hipMemcpyAsync(&hf, flag.get(), sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        SRF_HIP(hipStreamSynchronize(st));
-        if (hf & 1) srf::fail(SRF_EDOMAIN, "non-finite particle position");
-        if (hf & 2) srf::fail(SRF_EDOMAIN, "particle mass not finite and > 0");
+        // reads the flag at its one synchronisation (SRF_EDOMAIN)
         srf::build_cells_and_groups(t, flag.get(), st);
     });
     if (rc != SRF_OK) {

@@ -142,7 +142,8 @@ void exclusive_scan_i32(int32_t* data, int64_t n, bool write_total, hipStream_t 
 // inside `flag` (bit 0: non-finite position, bit 1: bad mass).
 void build_sorted(Tree& t, const double* x, const double* y, const double* z, int64_t ps,
                   const double* m, int64_t ms, int32_t* d_flag, hipStream_t stream);
-// a3-a5
+// a3-a5; synchronises `stream` once, and fails with SRF_EDOMAIN if *d_flag
+// (set by build_sorted) is nonzero
 void build_cells_and_groups(Tree& t, int32_t* d_flag, hipStream_t stream);
 // a6
 void build_lists(const Tree& t, Lists& l, hipStream_t stream);

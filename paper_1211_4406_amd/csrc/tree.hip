@@ -1,237 +1,276 @@
-// Steps a3-a5: octree over the Morton order (built level by level), monopole
-// moments (bottom-up), renumbering into DFS preorder with subtree "skip"
-// links, particle groups and their bounding boxes.
+// Steps a3-a5 with one host synchronisation: the octree, its monopole
+// moments, the DFS preorder with subtree "skip" links, the particle groups
+// and their bounding boxes, all derived from the sorted Morton keys.
+//
+// Let delta(s) be the number of leading 3-bit digits that keys s-1 and s
+// share (-1 for s = 0).  The cell of level L holding particle s starts at s
+// iff delta(s) < L, and ends before the next index e with delta(e) < L.  It
+// holds at least W particles iff some run of W consecutive particles that
+// contains s lies inside it, i.e. iff delta >= L over that run's interior.
+// So the deepest level whose cell holding s has more than k particles is
+//   lambda_k(s) = max over runs [t, t + k] containing s of min delta(t+1 .. t+k)
+// (-1 if there is no such run), a max of mins over runs of at most 65
+// particles, taken per particle from an LDS tile.  From it:
+//   - s lies in the leaf of level leaf(s) = min(21, max(1, lambda_{n_leaf}(s) + 1))
+//     (a cell is split iff it holds more than n_leaf particles; the root
+//     always);
+//   - the cells starting at s are the levels delta(s)+1 .. leaf(s), a chain
+//     in which each is the first child of the one before: their preorder
+//     numbers are start(s) + L - delta(s) - 1, start the exclusive scan of
+//     the chain lengths, so the whole preorder follows from one scan;
+//   - s lies in the group candidate of level max(1, lambda_{n_group}(s) + 1)
+//     (lambda = 21: a level-21 cell with more than n_group particles, cut
+//     into chunks of n_group); whether a candidate starts a group follows
+//     from its left siblings, found by 64-lane scans of delta in LDS.
+// Each level's cells also get consecutive slots ordered by first particle
+// (per-block counts, scanned per level), so that a cell's children are one
+// contiguous run of the next level's slots; counts, moments and skip links
+// then follow bottom-up, one launch per level, sized from the level totals
+// read at the one synchronisation.
 //
 // Compiled with -ffp-contract=off: the group boxes feed the list decisions,
 // which must be the literal FP64 expressions.
-#include <algorithm>
-#include <vector>
+#include <string>
 
 #include "common.h"
 
 namespace srf {
 namespace {
 
-// Breadth-first cell arrays used while building (level-major order).
-struct Bfs {
-    int64_t cap = 0;
-    DevBuf<int32_t> level, first, count, parent, child_begin, child_cnt;
-    DevBuf<uint64_t> prefix;
-};
+constexpr int kLvThreads = 256;
+constexpr int kLvTile = 1024;                      // particles per block
+constexpr int kPer = kLvTile / kLvThreads;
+constexpr int kHalo = 64;                          // runs hold at most 65 particles
+constexpr int kLvSpan = kLvTile + 2 * kHalo;       // deltas of the range tables
+constexpr int kLvRuns = kLvTile + kHalo;           // run starts
+constexpr int kLog = 7;                            // range tables for lengths 1..64
+constexpr int kLeft = 512;                         // left reach of the sibling scans (7 siblings of <= 64, + 64)
+constexpr int kScanSpan = kLeft + kLvTile + kHalo; // deltas of the sibling scans
 
-void bfs_alloc(Bfs& b, int64_t cap, hipStream_t st) {
-    b.cap = cap;
-    b.level.alloc(cap, st);
-    b.first.alloc(cap, st);
-    b.count.alloc(cap, st);
-    b.parent.alloc(cap, st);
-    b.child_begin.alloc(cap, st);
-    b.child_cnt.alloc(cap, st);
-    b.prefix.alloc(cap, st);
+__device__ __forceinline__ int shared_digits(uint64_t a, uint64_t b) {
+    const uint64_t x = a ^ b;   // keys use the low 63 bits
+    return x ? (__clzll(x) - 1) / 3 : kMaxLevel;
 }
 
-template <class T>
-void grow_one(DevBuf<T>& buf, int64_t used, int64_t cap, hipStream_t st) {
-    DevBuf<T> nb(cap, st);
-    if (used > 0) SRF_HIP(hipMemcpyAsync(nb.get(), buf.get(), used * sizeof(T), hipMemcpyDeviceToDevice, st));
-    buf = std::move(nb);
-}
+__device__ __forceinline__ int floor_log2(int v) { return 31 - __clz(v); }
 
-void bfs_grow(Bfs& b, int64_t used, int64_t need, hipStream_t st) {
-    if (need <= b.cap) return;
-    int64_t cap = std::max<int64_t>(need, b.cap * 2);
-    grow_one(b.level, used, cap, st);
-    grow_one(b.first, used, cap, st);
-    grow_one(b.count, used, cap, st);
-    grow_one(b.parent, used, cap, st);
-    grow_one(b.child_begin, used, cap, st);
-    grow_one(b.child_cnt, used, cap, st);
-    grow_one(b.prefix, used, cap, st);
-    b.cap = cap;
-}
-
-__global__ void k_root(int64_t n, int32_t* level, int32_t* first, int32_t* count, int32_t* parent,
-                       uint64_t* prefix) {
-    level[0] = 0;
-    first[0] = 0;
-    count[0] = (int32_t)n;
-    parent[0] = -1;
-    prefix[0] = 0;
-}
-
-// First index in [lo, hi) whose level-(L+1) digit is >= o (digits are
-// non-decreasing inside a cell).
-__device__ __forceinline__ int32_t lower_digit(const uint64_t* __restrict__ keys, int32_t lo, int32_t hi, int shift,
-                                               uint32_t o) {
+// First index in [lo, s] whose key equals keys[s] (sorted keys).
+__device__ __forceinline__ int64_t first_equal(const uint64_t* __restrict__ keys, int64_t lo, int64_t s) {
+    const uint64_t k = keys[s];
+    int64_t hi = s;
     while (lo < hi) {
-        int32_t mid = lo + ((hi - lo) >> 1);
-        uint32_t dg = (uint32_t)((keys[mid] >> shift) & 7u);
-        if (dg < o) lo = mid + 1;
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if (keys[mid] < k) lo = mid + 1;
         else hi = mid;
     }
     return lo;
 }
 
-// Children of the cells of one level: octant boundaries and counts.  Eight
-// threads per cell (32 cells per block of 256): thread o finds boundary o
-// (the first index whose level-(L+1) digit is >= o; o = 0 is the cell's
-// first index), so each thread's chain of dependent loads is one binary
-// search; thread 0 then counts the non-empty octants.
-__global__ __launch_bounds__(256) void k_child_count(int64_t begin, int64_t m, int level, int32_t n_leaf,
-                                                     const int32_t* __restrict__ first,
-                                                     const int32_t* __restrict__ count,
-                                                     const uint64_t* __restrict__ keys, int32_t* __restrict__ bnd,
-                                                     int32_t* __restrict__ cnt) {
-    __shared__ int32_t sb[256 + 32];
-    const int64_t k = blockIdx.x * 32ll + (threadIdx.x >> 3);
-    const int o = threadIdx.x & 7;
-    const int slot = (threadIdx.x >> 3) * 9;
-    bool split = false;
-    if (k < m) {
-        const int64_t c = begin + k;
-        const int32_t f = first[c], nc = count[c];
-        split = (level == 0) || (level < kMaxLevel && nc > n_leaf);
-        if (split) {
-            const int shift = 3 * (kMaxLevel - (level + 1));
-            const int32_t bo = o == 0 ? f : lower_digit(keys, f, f + nc, shift, (uint32_t)o);
-            sb[slot + o] = bo;
-            bnd[k * 9 + o] = bo;
-            if (o == 0) {
-                sb[slot + 8] = f + nc;
-                bnd[k * 9 + 8] = f + nc;
-            }
-        }
+// Per particle: delta, leaf level, the chain length of the cells starting
+// there and the group-start mark; per block and level the number of cells
+// (blk[L * nblocks + block]).
+//
+// Group starts.  A candidate (level >= 1, at most n_group particles, parent
+// the root or holding more than n_group) starts a group under the root, and
+// under any other parent unless the greedy run of the candidate siblings
+// before it (octant order, closed by a sibling with more than n_group
+// particles or by an overflow) takes it in.  Candidates under a parent of
+// level >= 1 are handled one at a time by the whole wave: the candidate's end
+// and its left siblings' starts are each the nearest index, among the 64
+// after (before) a position, with delta below the candidate's level; a
+// sibling whose start is further away holds more than n_group particles and
+// closes the run.
+__global__ __launch_bounds__(kLvThreads) void k_levels(int64_t n, const uint64_t* __restrict__ keys, int n_leaf,
+                                                       int n_group, int64_t nblocks, int8_t* __restrict__ delta,
+                                                       int8_t* __restrict__ leaflv, int32_t* __restrict__ chain,
+                                                       int32_t* __restrict__ mark, int32_t* __restrict__ blk) {
+    __shared__ int8_t mn[kLog][kLvSpan];   // mn[k][j] = min delta over [j, j + 2^k)
+    __shared__ int8_t mx[kLog][kLvRuns];   // mx[k][j] = max run minimum over run starts [j, j + 2^k)
+    __shared__ int8_t dl[kScanSpan];       // delta of global index b0 - kLeft + j
+    __shared__ unsigned lh[kLevels];
+    const int64_t b0 = blockIdx.x * (int64_t)kLvTile;
+    const int tid = threadIdx.x, lane = tid & 63;
+    if (tid < kLevels) lh[tid] = 0;
+    for (int j = tid; j < kScanSpan; j += kLvThreads) {
+        const int64_t i = b0 - kLeft + j;
+        int d = -1;
+        if (i >= 1 && i < n) d = shared_digits(keys[i - 1], keys[i]);
+        dl[j] = (int8_t)d;
     }
     __syncthreads();
-    if (k < m && o == 0) {
-        int nz = 0;
-        if (split) {
+    // range table of minima over [b0 - kHalo, b0 + kLvTile + kHalo)
+    for (int j = tid; j < kLvSpan; j += kLvThreads) mn[0][j] = dl[j + kLeft - kHalo];
+    __syncthreads();
+    for (int k = 1; k < kLog; ++k) {
+        const int h = 1 << (k - 1);
+        for (int j = tid; j < kLvSpan; j += kLvThreads) {
+            // entries whose range runs past the span are never queried
+            const int a = mn[k - 1][j], b = j + h < kLvSpan ? mn[k - 1][j + h] : a;
+            mn[k][j] = (int8_t)(a < b ? a : b);
+        }
+        __syncthreads();
+    }
+    int lam[2][kPer];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) nz += (sb[slot + q + 1] > sb[slot + q]) ? 1 : 0;
-        }
-        cnt[k] = nz;
-    }
-}
-
-__global__ void k_child_write(int64_t begin, int64_t m, int64_t out_begin, int level, const int32_t* __restrict__ bnd,
-                              const int32_t* __restrict__ off, int32_t* __restrict__ lv, int32_t* __restrict__ first,
-                              int32_t* __restrict__ count, int32_t* __restrict__ parent,
-                              int32_t* __restrict__ child_begin, int32_t* __restrict__ child_cnt,
-                              uint64_t* __restrict__ prefix) {
-    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (k >= m) return;
-    int64_t c = begin + k;
-    int32_t nz = off[k + 1] - off[k];
-    int64_t out = out_begin + off[k];
-    child_begin[c] = (int32_t)out;
-    child_cnt[c] = nz;
-    if (nz == 0) return;
-    const int32_t* b = bnd + k * 9;
-    uint64_t pp = prefix[c];
-    for (int o = 0; o < 8; ++o) {
-        int32_t cc = b[o + 1] - b[o];
-        if (cc <= 0) continue;
-        lv[out] = level + 1;
-        first[out] = b[o];
-        count[out] = cc;
-        parent[out] = (int32_t)c;
-        prefix[out] = pp * 8u + (uint64_t)o;
-        ++out;
-    }
-}
-
-__global__ void k_leaf_fix(int64_t begin, int64_t m, int32_t* __restrict__ child_begin, int32_t* __restrict__ child_cnt) {
-    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (k >= m) return;
-    child_begin[begin + k] = -1;
-    child_cnt[begin + k] = 0;
-}
-
-// Bottom-up monopoles of one level: mass and mass-weighted position sums,
-// 4 lanes per cell.  A leaf's lane j takes its particles j, j + 4, ...
-// (consecutive lanes read consecutive particles), an inner cell's lane j
-// its children j, j + 4.  The 4 partial sums are then added by shuffles.
-constexpr int kMomLanes = 4;
-
-__global__ __launch_bounds__(256) void k_moments(int64_t begin, int64_t m, const int32_t* __restrict__ first,
-                                                 const int32_t* __restrict__ count,
-                                                 const int32_t* __restrict__ child_begin,
-                                                 const int32_t* __restrict__ child_cnt, const double* __restrict__ px,
-                                                 const double* __restrict__ py, const double* __restrict__ pz,
-                                                 const double* __restrict__ pm, double* __restrict__ M,
-                                                 double* __restrict__ SX, double* __restrict__ SY,
-                                                 double* __restrict__ SZ) {
-    const int64_t k = blockIdx.x * (int64_t)(256 / kMomLanes) + threadIdx.x / kMomLanes;
-    const int j = threadIdx.x & (kMomLanes - 1);
-    const bool on = k < m;
-    const int64_t c = begin + (on ? k : 0);
-    double sm = 0, sx = 0, sy = 0, sz = 0;
-    if (on) {
-        const int32_t nch = child_cnt[c];
-        if (nch == 0) {
-            const int32_t f = first[c], e = first[c] + count[c];
-            for (int32_t s = f + j; s < e; s += kMomLanes) {
-                const double mm = pm[s];
-                sm += mm;
-                sx += mm * px[s];
-                sy += mm * py[s];
-                sz += mm * pz[s];
+    for (int w = 0; w < 2; ++w) {
+        const int W = (w == 0 ? n_leaf : n_group) + 1;   // run length, 2..65
+        const int kq = floor_log2(W - 1);
+        // minimum of delta over the interior of the run starting at each t
+        for (int j = tid; j < kLvRuns; j += kLvThreads) {
+            const int64_t t = b0 - kHalo + j;
+            int v = -1;
+            if (t >= 0 && t + W - 1 <= n - 1) {
+                const int a = mn[kq][j + 1], b = mn[kq][j + W - (1 << kq)];
+                v = a < b ? a : b;
             }
-        } else {
-            const int32_t cb = child_begin[c];
-            for (int32_t q = cb + j; q < cb + nch; q += kMomLanes) {
-                sm += M[q];
-                sx += SX[q];
-                sy += SY[q];
-                sz += SZ[q];
-            }
+            mx[0][j] = (int8_t)v;
         }
+        __syncthreads();
+        for (int k = 1; k < kLog; ++k) {
+            const int h = 1 << (k - 1);
+            for (int j = tid; j < kLvRuns; j += kLvThreads) {
+                const int a = mx[k - 1][j], b = j + h < kLvRuns ? mx[k - 1][j + h] : a;
+                mx[k][j] = (int8_t)(a > b ? a : b);
+            }
+            __syncthreads();
+        }
+        // maximum over the runs [s - W + 1, s] that contain s
+        const int kr = floor_log2(W);
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int js = kHalo + tid + q * kLvThreads;
+            const int a = mx[kr][js - W + 1], b = mx[kr][js - (1 << kr) + 1];
+            lam[w][q] = a > b ? a : b;
+        }
+        __syncthreads();
     }
 #pragma unroll
-    for (int o = kMomLanes / 2; o >= 1; o >>= 1) {
-        sm += __shfl_xor(sm, o, kMomLanes);
-        sx += __shfl_xor(sx, o, kMomLanes);
-        sy += __shfl_xor(sy, o, kMomLanes);
-        sz += __shfl_xor(sz, o, kMomLanes);
+    for (int q = 0; q < kPer; ++q) {
+        const int64_t s = b0 + tid + q * kLvThreads;   // a wave holds 64 consecutive particles
+        const bool on = s < n;
+        const int js = kLeft + tid + q * kLvThreads;  // index of s in dl
+        const int d = dl[js];
+        int ll = lam[0][q] + 1;
+        ll = ll < 1 ? 1 : (ll > kMaxLevel ? kMaxLevel : ll);
+        const int lg = lam[1][q];
+        const int kap = lg + 1 > 1 ? lg + 1 : 1;
+        int m = 0;
+        bool walk = false;
+        if (on) {
+            delta[s] = (int8_t)d;
+            leaflv[s] = (int8_t)ll;
+            chain[s] = ll > d ? ll - d : 0;
+            for (int L = d + 1; L <= ll; ++L) atomicAdd(&lh[L], 1u);
+            if (lg >= kMaxLevel) {
+                m = ((s - first_equal(keys, 0, s)) % n_group) == 0;   // chunks of a level-21 cell
+            } else if (d < kap) {
+                if (kap == 1) m = 1;
+                else walk = true;
+            }
+        }
+        // candidates under a parent of level >= 1, one per wave iteration
+        uint64_t todo = __ballot(walk);
+        while (todo) {
+            const int src = __ffsll((unsigned long long)todo) - 1;
+            todo &= todo - 1;
+            const int cs = __shfl(js, src, 64);
+            const int ck = __shfl(kap, src, 64);
+            const int64_t cg = __shfl(s, src, 64);
+            // the candidate's end: the first delta below its level among the
+            // next 64 (it holds at most n_group, so the end is among them)
+            const int de = cg + 1 + lane < n ? dl[cs + 1 + lane] : -1;
+            const uint64_t eb = __ballot(de < ck);
+            const int64_t own = __ffsll((unsigned long long)eb);
+            // left siblings back to the parent's start or a closing sibling;
+            // they span at most 7 x 64 particles, inside the left reach
+            int64_t cnt[7];
+            int ns = 0;
+            int pos = cs;
+            while (ns < 7 && dl[pos] >= ck - 1) {   // pos is not the parent's first index
+                const int jb = pos - 1 - lane;
+                const int db = jb >= 0 ? dl[jb] : -1;
+                const uint64_t bb = __ballot(db < ck);
+                if (!bb) break;   // no start within 64: the sibling holds more than n_group
+                const int c = __ffsll((unsigned long long)bb);
+                if (c > n_group) break;
+                cnt[ns++] = c;
+                pos -= c;
+            }
+            int64_t run = 0;
+            bool open = false;
+            for (int k = ns - 1; k >= 0; --k) {
+                if (open && run + cnt[k] <= n_group) {
+                    run += cnt[k];
+                } else {
+                    run = cnt[k];
+                    open = true;
+                }
+            }
+            if (lane == src) m = !(open && run + own <= n_group);
+        }
+        if (on) mark[s] = m;
     }
-    if (on && j == 0) {
-        M[c] = sm;
-        SX[c] = sx;
-        SY[c] = sy;
-        SZ[c] = sz;
-    }
+    __syncthreads();
+    if (tid < kLevels) blk[(int64_t)tid * nblocks + blockIdx.x] = (int32_t)lh[tid];
 }
 
-// Preorder numbering: the cells starting at sorted index f form one chain
-// of consecutive levels (each the first child of the previous), so
-// pre(c) = start[f] + level(c) - minlevel(f), with start[] the exclusive
-// scan of the number of cells starting at each index.  Every chain ends in
-// the leaf that starts at f, so each leaf walks up its chain (while the
-// parent starts at the same index) and stores the chain's length and top
-// level: one plain store per index, no atomics.
-__global__ void k_pre_count(int64_t nn, const int32_t* __restrict__ first, const int32_t* __restrict__ level,
-                            const int32_t* __restrict__ parent, const int32_t* __restrict__ child_cnt,
-                            int32_t* __restrict__ cntf, int32_t* __restrict__ minlv) {
-    int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (c >= nn || child_cnt[c] != 0) return;
-    const int32_t f = first[c];
-    int32_t top = level[c];
-    int32_t p = parent[c];
-    while (p >= 0 && first[p] == f) {
-        top = level[p];
-        p = parent[p];
+// Exclusive scan of one level's per-block cell counts (block = level), in
+// place; the level's total goes to tot.
+__global__ __launch_bounds__(256) void k_level_scan(int64_t nblocks, int32_t* __restrict__ blk,
+                                                    int32_t* __restrict__ tot) {
+    constexpr int kItems = 4;
+    __shared__ int32_t wsum[4];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    int32_t* row = blk + (int64_t)blockIdx.x * nblocks;
+    int32_t carry = 0;
+    for (int64_t c0 = 0; c0 < nblocks; c0 += 256 * kItems) {
+        const int64_t j = c0 + (int64_t)tid * kItems;
+        int32_t v[kItems];
+        int32_t s = 0;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            v[k] = j + k < nblocks ? row[j + k] : 0;
+            s += v[k];
+        }
+        int32_t incl = s;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t u = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += u;
+        }
+        if (lane == 63) wsum[wid] = incl;
+        __syncthreads();
+        int32_t off = carry + incl - s, total = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            off += w < wid ? wsum[w] : 0;
+            total += wsum[w];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            if (j + k < nblocks) row[j + k] = off;
+            off += v[k];
+        }
+        carry += total;
     }
-    cntf[f] = level[c] - top + 1;
-    minlv[f] = top;
+    if (tid == 0) tot[blockIdx.x] = carry;
 }
 
-__global__ void k_pre_assign(int64_t nn, const int32_t* __restrict__ first, const int32_t* __restrict__ level,
-                             const int32_t* __restrict__ start, const int32_t* __restrict__ minlv,
-                             int32_t* __restrict__ bfs2pre) {
-    int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (c >= nn) return;
-    int32_t f = first[c];
-    bfs2pre[c] = start[f] + level[c] - minlv[f];
+struct Summary {
+    int64_t n_groups;
+    int32_t flag;
+    int32_t pad;
+    int64_t tot[kLevels];    // cells per level
+};
+
+__global__ void k_summary(int64_t n, const int32_t* __restrict__ gscan, const int32_t* __restrict__ flag,
+                          const int32_t* __restrict__ tot, Summary* __restrict__ out) {
+    if (threadIdx.x != 0) return;
+    out->n_groups = gscan[n];
+    out->flag = *flag;
+    out->pad = 0;
+    for (int L = 0; L < kLevels; ++L) out->tot[L] = tot[L];
 }
 
 __device__ __forceinline__ uint32_t compact3(uint64_t v) {
@@ -244,90 +283,176 @@ __device__ __forceinline__ uint32_t compact3(uint64_t v) {
     return (uint32_t)v;
 }
 
-__global__ void k_pre_scatter(int64_t nn, int64_t n, const int32_t* __restrict__ bfs2pre,
-                              const int32_t* __restrict__ level, const int32_t* __restrict__ first,
-                              const int32_t* __restrict__ count, const int32_t* __restrict__ parent,
-                              const int32_t* __restrict__ child_cnt, const uint64_t* __restrict__ prefix,
-                              const int32_t* __restrict__ start, const double* __restrict__ M,
-                              const double* __restrict__ SX, const double* __restrict__ SY,
-                              const double* __restrict__ SZ, NodeGeo* __restrict__ geo, NodeRange* __restrict__ rng,
-                              uint4* __restrict__ pack,
-                              uint64_t* __restrict__ opre, double* __restrict__ oM, double* __restrict__ oX,
-                              double* __restrict__ oY, double* __restrict__ oZ, int32_t* __restrict__ leaf_of) {
-    int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+struct LevelBase {
+    int32_t off[kLevels + 1];   // first slot of each level; off[kLevels] = number of cells
+};
+
+// The cells starting at each particle (same tiling as k_levels): their
+// level slot (level base + the block's offset + the rank among the block's
+// cells of that level, by first particle) and, in preorder, their geometry,
+// first index and key prefix; per slot the first particle, the preorder
+// number and the slot of the first child (-1 for a leaf).
+constexpr int kWords = kLvTile / 32;
+
+__global__ __launch_bounds__(kLvThreads) void k_cells(int64_t n, int64_t nblocks, const uint64_t* __restrict__ keys,
+                                                      const int8_t* __restrict__ delta,
+                                                      const int8_t* __restrict__ leaflv,
+                                                      const int32_t* __restrict__ start, LevelBase base,
+                                                      const int32_t* __restrict__ blk, NodeGeo* __restrict__ geo,
+                                                      int32_t* __restrict__ pfirst, uint64_t* __restrict__ prefix,
+                                                      int32_t* __restrict__ sfirst, int32_t* __restrict__ spre,
+                                                      int32_t* __restrict__ schild) {
+    __shared__ uint32_t msk[kLevels][kWords];
+    __shared__ int32_t wpre[kLevels][kWords];
+    const int tid = threadIdx.x;
+    const int64_t b0 = blockIdx.x * (int64_t)kLvTile;
+    for (int q = tid; q < kLevels * kWords; q += kLvThreads) (&msk[0][0])[q] = 0u;
+    __syncthreads();
+    int d[kPer], ll[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int p = tid + q * kLvThreads;
+        const int64_t s = b0 + p;
+        d[q] = 0;
+        ll[q] = 0;
+        if (s < n) {
+            d[q] = delta[s];
+            ll[q] = leaflv[s];
+            for (int L = d[q] + 1; L <= ll[q]; ++L) atomicOr(&msk[L][p >> 5], 1u << (p & 31));
+        }
+    }
+    __syncthreads();
+    if (tid < kLevels) {
+        int32_t acc = 0;
+        for (int w = 0; w < kWords; ++w) {
+            wpre[tid][w] = acc;
+            acc += __popc(msk[tid][w]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int p = tid + q * kLvThreads;
+        const int64_t s = b0 + p;
+        if (s >= n || ll[q] <= d[q]) continue;
+        const int32_t st = start[s];
+        const uint64_t k = keys[s];
+        const uint32_t below = (1u << (p & 31)) - 1u;
+        int32_t slot_next = -1;
+        for (int L = ll[q]; L >= d[q] + 1; --L) {   // deepest first: each cell's first child is the one before
+            const int32_t rank = wpre[L][p >> 5] + __popc(msk[L][p >> 5] & below);
+            const int32_t slot = base.off[L] + blk[(int64_t)L * nblocks + blockIdx.x] + rank;
+            const int32_t pre = st + (L - d[q] - 1);
+            sfirst[slot] = (int32_t)s;
+            spre[slot] = pre;
+            schild[slot] = slot_next;
+            slot_next = slot;
+            const uint64_t pf = L == 0 ? 0ull : k >> (3 * (kMaxLevel - L));
+            NodeGeo g;
+            g.ix = compact3(pf >> 2);
+            g.iy = compact3(pf >> 1);
+            g.iz = compact3(pf);
+            g.level_leaf = (uint32_t)L | (L == ll[q] ? 0x100u : 0u);
+            geo[pre] = g;
+            pfirst[pre] = (int32_t)s;
+            prefix[pre] = pf;
+        }
+    }
+}
+
+// One level, deepest first, 4 lanes per cell.  A leaf's particles run to
+// the first particle of the next cell in preorder; an inner cell's children
+// are the next level's slots from its first child on, while their first
+// particle lies before the first particle of the next slot of this level.
+// Sums and counts are kept per slot; count, skip link and monopole go to
+// the cell's preorder record, and the children get their parent.
+constexpr int kMomLanes = 4;
+
+__global__ __launch_bounds__(256) void k_moments(int32_t lo, int32_t hi, int32_t next_hi, int64_t n, int64_t nn,
+                                                 const int32_t* __restrict__ sfirst, const int32_t* __restrict__ spre,
+                                                 const int32_t* __restrict__ schild,
+                                                 const int32_t* __restrict__ pfirst,
+                                                 const int32_t* __restrict__ start, const double* __restrict__ px,
+                                                 const double* __restrict__ py, const double* __restrict__ pz,
+                                                 const double* __restrict__ pm, int32_t* __restrict__ scount,
+                                                 double* __restrict__ sM, double* __restrict__ sX,
+                                                 double* __restrict__ sY, double* __restrict__ sZ,
+                                                 NodeRange* __restrict__ rng, double* __restrict__ oM,
+                                                 double* __restrict__ oX, double* __restrict__ oY,
+                                                 double* __restrict__ oZ, int32_t* __restrict__ leaf_of) {
+    const int64_t i = lo + blockIdx.x * (int64_t)(256 / kMomLanes) + threadIdx.x / kMomLanes;
+    const int j = threadIdx.x & (kMomLanes - 1);
+    const bool on = i < hi;
+    const int64_t c = on ? i : lo;
+    const int32_t f = sfirst[c], pre = spre[c], ch = schild[c];
+    double sm = 0, sx = 0, sy = 0, sz = 0;
+    int64_t cnt = 0;
+    if (on) {
+        if (ch < 0) {
+            const int64_t e = pre + 1 < nn ? pfirst[pre + 1] : n;
+            for (int64_t s = f + j; s < e; s += kMomLanes) {
+                const double mm = pm[s];
+                sm += mm;
+                sx += mm * px[s];
+                sy += mm * py[s];
+                sz += mm * pz[s];
+                leaf_of[s] = pre;
+            }
+            cnt = j == 0 ? e - f : 0;
+        } else {
+            const int64_t lim = c + 1 < hi ? sfirst[c + 1] : n;   // first particle of the next cell of this level
+            for (int64_t q = ch + j; q < next_hi && sfirst[q] < lim; q += kMomLanes) {
+                sm += sM[q];
+                sx += sX[q];
+                sy += sY[q];
+                sz += sZ[q];
+                cnt += scount[q];
+                rng[spre[q]].parent = pre;
+            }
+        }
+    }
+#pragma unroll
+    for (int o = kMomLanes / 2; o >= 1; o >>= 1) {
+        sm += __shfl_xor(sm, o, kMomLanes);
+        sx += __shfl_xor(sx, o, kMomLanes);
+        sy += __shfl_xor(sy, o, kMomLanes);
+        sz += __shfl_xor(sz, o, kMomLanes);
+        cnt += __shfl_xor(cnt, o, kMomLanes);
+    }
+    if (on && j == 0) {
+        scount[c] = (int32_t)cnt;
+        sM[c] = sm;
+        sX[c] = sx;
+        sY[c] = sy;
+        sZ[c] = sz;
+        const int64_t e = f + cnt;
+        rng[pre].first = f;
+        rng[pre].count = (int32_t)cnt;
+        rng[pre].skip = e < n ? start[e] : (int32_t)nn;
+        if (pre == 0) rng[pre].parent = -1;
+        oM[pre] = sm;
+        oX[pre] = sx / sm;
+        oY[pre] = sy / sm;
+        oZ[pre] = sz / sm;
+    }
+}
+
+// The packed walk record of each cell (preorder).
+__global__ void k_pack(int64_t nn, const NodeGeo* __restrict__ geo, const NodeRange* __restrict__ rng,
+                       uint4* __restrict__ pack) {
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (c >= nn) return;
-    int32_t p = bfs2pre[c];
-    uint64_t pf = prefix[c];
-    int32_t lv = level[c];
-    bool leaf = child_cnt[c] == 0;
-    NodeGeo g;
-    g.ix = compact3(pf >> 2);
-    g.iy = compact3(pf >> 1);
-    g.iz = compact3(pf);
-    g.level_leaf = (uint32_t)lv | (leaf ? 0x100u : 0u);
-    geo[p] = g;
-    int32_t f = first[c], cnt = count[c];
-    NodeRange r;
-    r.first = f;
-    r.count = cnt;
-    r.skip = start[f + cnt];
-    r.parent = parent[c] >= 0 ? bfs2pre[parent[c]] : -1;
-    rng[p] = r;
+    const NodeGeo g = geo[c];
+    const NodeRange r = rng[c];
     const uint32_t sk = (uint32_t)r.skip;
+    const uint32_t lv = g.level_leaf & 0xffu;
+    const bool leaf = (g.level_leaf >> 8) & 1u;
     uint4 pk;
     pk.x = g.ix | ((sk & 0x7ffu) << 21);
     pk.y = g.iy | (((sk >> 11) & 0x7ffu) << 21);
     pk.z = g.iz | (((sk >> 22) & 0x3ffu) << 21);
-    pk.w = (uint32_t)lv | (leaf ? 0x20u : 0u) | ((uint32_t)(cnt < (int32_t)kPackCountMax ? cnt : (int32_t)kPackCountMax) << 6);
-    pack[p] = pk;
-    opre[p] = pf;
-    double mm = M[c];
-    oM[p] = mm;
-    oX[p] = SX[c] / mm;
-    oY[p] = SY[c] / mm;
-    oZ[p] = SZ[c] / mm;
-    if (leaf)
-        for (int32_t s = f; s < f + cnt; ++s) leaf_of[s] = p;
-    (void)n;
-}
-
-// Group starts.  A "group parent" is the root or a cell with more than
-// n_group particles.  Its candidate children (at most n_group particles)
-// start groups: each on its own under the root, merged greedily with the
-// following candidate siblings (in octant order) otherwise.  A level-21
-// cell with more than n_group particles is cut into chunks of n_group.
-__global__ void k_group_marks(int64_t nn, int32_t n_g, const NodeGeo* __restrict__ geo,
-                              const NodeRange* __restrict__ rng, int32_t* __restrict__ mark) {
-    int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (c >= nn) return;
-    NodeRange r = rng[c];
-    int lv = (int)(geo[c].level_leaf & 0xffu);
-    if (!(lv == 0 || r.count > n_g)) return;
-    bool leaf = (geo[c].level_leaf >> 8) & 1u;
-    if (leaf) {  // level 21, too many coincident keys
-        for (int32_t s = 0; s < r.count; s += n_g) mark[r.first + s] = 1;
-        return;
-    }
-    bool merge = lv >= 1;
-    bool open = false;
-    int32_t run = 0;
-    int32_t ch = (int32_t)c + 1;
-    while (ch < r.skip) {
-        NodeRange q = rng[ch];
-        if (q.count <= n_g) {
-            if (merge && open && run + q.count <= n_g) {
-                run += q.count;
-            } else {
-                mark[q.first] = 1;
-                open = true;
-                run = q.count;
-            }
-        } else {
-            open = false;
-            run = 0;
-        }
-        ch = q.skip;
-    }
+    pk.w = lv | (leaf ? 0x20u : 0u) | ((uint32_t)(r.count < (int32_t)kPackCountMax ? r.count : (int32_t)kPackCountMax) << 6);
+    pack[c] = pk;
 }
 
 __global__ void k_group_write(int64_t n, const int32_t* __restrict__ sc, int32_t* __restrict__ gfirst) {
@@ -389,81 +514,52 @@ __global__ __launch_bounds__(256) void k_group_bbox(int64_t ng, const int32_t* _
     }
 }
 
-int64_t read_i32(const int32_t* d, hipStream_t st) {
-    int32_t h = 0;
-    SRF_HIP(hipMemcpyAsync(&h, d, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    SRF_HIP(hipStreamSynchronize(st));
-    return h;
-}
-
 }  // namespace
 
 void build_cells_and_groups(Tree& t, int32_t* d_flag, hipStream_t st) {
-    (void)d_flag;
     const int64_t n = t.n;
     const int B = 256;
-    Bfs b;
-    bfs_alloc(b, std::max<int64_t>(1024, n / 4 + 64), st);
-    hipLaunchKernelGGL(k_root, dim3(1), dim3(1), 0, st, n, b.level.get(), b.first.get(), b.count.get(),
-                       b.parent.get(), b.prefix.get());
+    const int64_t nblocks = (n + kLvTile - 1) / kLvTile;
+    // per-particle levels, chain lengths and group starts; per-block cell counts
+    DevBuf<int8_t> delta(n, st), leaflv(n, st);
+    DevBuf<int32_t> start(n + 1, st), mark(n + 1, st), blk(kLevels * nblocks, st), tot(kLevels, st);
+    DevBuf<Summary> dsum(1, st);
+    fill_i32(start.get() + n, 0, 1, st);
+    fill_i32(mark.get() + n, 0, 1, st);
+    hipLaunchKernelGGL(k_levels, dim3((unsigned)nblocks), dim3(kLvThreads), 0, st, n, t.keys.get(), t.n_leaf,
+                       t.n_group, nblocks, delta.get(), leaflv.get(), start.get(), mark.get(), blk.get());
     SRF_HIP(hipGetLastError());
-    std::vector<int64_t> lvl_off{0, 1};
-    int64_t cur_begin = 0, cur_end = 1;
+    hipLaunchKernelGGL(k_level_scan, dim3(kLevels), dim3(256), 0, st, nblocks, blk.get(), tot.get());
+    SRF_HIP(hipGetLastError());
+    exclusive_scan_i32(start.get(), n, true, st);   // preorder number of each chain's first cell
+    exclusive_scan_i32(mark.get(), n, true, st);    // group number of each group start
+    hipLaunchKernelGGL(k_summary, dim3(1), dim3(64), 0, st, n, mark.get(), d_flag, tot.get(), dsum.get());
+    SRF_HIP(hipGetLastError());
+    // the one synchronisation: sizes and the device's check of the inputs
+    Summary hs;
+    SRF_HIP(hipMemcpyAsync(&hs, dsum.get(), sizeof(Summary), hipMemcpyDeviceToHost, st));
+    SRF_HIP(hipStreamSynchronize(st));
+    if (hs.flag & 1) fail(SRF_EDOMAIN, "non-finite particle position");
+    if (hs.flag & 2) fail(SRF_EDOMAIN, "particle mass not finite and > 0");
+    // (a level holds fewer than 2^31 cells: its per-block counts are exact
+    // int32 sums of counts below n; the total is checked here)
+    LevelBase base;
+    int64_t acc = 0;
     int max_level = 0;
-    for (int L = 0; L < kMaxLevel; ++L) {
-        const int64_t m = cur_end - cur_begin;
-        DevBuf<int32_t> bnd(m * 9, st), cnt(m + 1, st);
-        hipLaunchKernelGGL(k_child_count, dim3(grid_for(m, 32, 1 << 30)), dim3(256), 0, st, cur_begin, m, L,
-                           t.n_leaf, b.first.get(), b.count.get(), t.keys.get(), bnd.get(), cnt.get());
-        SRF_HIP(hipGetLastError());
-        exclusive_scan_i32(cnt.get(), m, true, st);
-        const int64_t c = read_i32(cnt.get() + m, st);
-        if (c == 0) {
-            hipLaunchKernelGGL(k_leaf_fix, dim3(grid_for(m, B, 1 << 30)), dim3(B), 0, st, cur_begin, m,
-                               b.child_begin.get(), b.child_cnt.get());
-            SRF_HIP(hipGetLastError());
-            break;
-        }
-        bfs_grow(b, cur_end, cur_end + c, st);
-        hipLaunchKernelGGL(k_child_write, dim3(grid_for(m, B, 1 << 30)), dim3(B), 0, st, cur_begin, m, cur_end, L,
-                           bnd.get(), cnt.get(), b.level.get(), b.first.get(), b.count.get(), b.parent.get(),
-                           b.child_begin.get(), b.child_cnt.get(), b.prefix.get());
-        SRF_HIP(hipGetLastError());
-        cur_begin = cur_end;
-        cur_end += c;
-        lvl_off.push_back(cur_end);
-        max_level = L + 1;
-        if (max_level == kMaxLevel) {
-            const int64_t mm = cur_end - cur_begin;
-            hipLaunchKernelGGL(k_leaf_fix, dim3(grid_for(mm, B, 1 << 30)), dim3(B), 0, st, cur_begin, mm,
-                               b.child_begin.get(), b.child_cnt.get());
-            SRF_HIP(hipGetLastError());
-        }
+    for (int L = 0; L < kLevels; ++L) {
+        base.off[L] = (int32_t)(acc < INT32_MAX ? acc : INT32_MAX);
+        acc += hs.tot[L];
+        if (hs.tot[L] > 0) max_level = L;
     }
-    const int64_t nn = cur_end;
+    if (acc > (int64_t)INT32_MAX - 1)
+        fail(SRF_EINVAL, "the tree would hold " + std::to_string(acc) + " cells, past 32-bit cell indices");
+    base.off[kLevels] = (int32_t)acc;
+    const int64_t nn = acc, ng = hs.n_groups;
     t.n_nodes = nn;
+    t.n_groups = ng;
     t.max_level = max_level;
 
-    // moments, deepest level first
-    DevBuf<double> M(nn, st), SX(nn, st), SY(nn, st), SZ(nn, st);
-    for (int L = (int)lvl_off.size() - 2; L >= 0; --L) {
-        const int64_t beg = lvl_off[L], m = lvl_off[L + 1] - lvl_off[L];
-        hipLaunchKernelGGL(k_moments, dim3(grid_for(m, 256 / kMomLanes, 1 << 30)), dim3(256), 0, st, beg, m,
-                           b.first.get(), b.count.get(), b.child_begin.get(), b.child_cnt.get(), t.px.get(),
-                           t.py.get(), t.pz.get(), t.pm.get(), M.get(), SX.get(), SY.get(), SZ.get());
-        SRF_HIP(hipGetLastError());
-    }
-
-    // preorder renumbering
-    DevBuf<int32_t> cntf(n + 1, st), minlv(n + 1, st), bfs2pre(nn, st);
-    fill_i32(cntf.get(), 0, n + 1, st);
-    hipLaunchKernelGGL(k_pre_count, dim3(grid_for(nn, B, 1 << 30)), dim3(B), 0, st, nn, b.first.get(), b.level.get(),
-                       b.parent.get(), b.child_cnt.get(), cntf.get(), minlv.get());
-    SRF_HIP(hipGetLastError());
-    exclusive_scan_i32(cntf.get(), n, true, st);  // cntf[n] = nn
-    hipLaunchKernelGGL(k_pre_assign, dim3(grid_for(nn, B, 1 << 30)), dim3(B), 0, st, nn, b.first.get(),
-                       b.level.get(), cntf.get(), minlv.get(), bfs2pre.get());
-    SRF_HIP(hipGetLastError());
+    // cells: slots and geometry, then counts, moments and links bottom-up
     t.geo.alloc(nn, st);
     t.range.alloc(nn, st);
     t.pack.alloc(nn, st);
@@ -473,22 +569,27 @@ void build_cells_and_groups(Tree& t, int32_t* d_flag, hipStream_t st) {
     t.nY.alloc(nn, st);
     t.nZ.alloc(nn, st);
     t.leaf_of.alloc(n, st);
-    hipLaunchKernelGGL(k_pre_scatter, dim3(grid_for(nn, B, 1 << 30)), dim3(B), 0, st, nn, n, bfs2pre.get(),
-                       b.level.get(), b.first.get(), b.count.get(), b.parent.get(), b.child_cnt.get(), b.prefix.get(),
-                       cntf.get(), M.get(), SX.get(), SY.get(), SZ.get(), t.geo.get(), t.range.get(), t.pack.get(),
-                       t.prefix.get(),
-                       t.nM.get(), t.nX.get(), t.nY.get(), t.nZ.get(), t.leaf_of.get());
+    DevBuf<int32_t> pfirst(nn, st), sfirst(nn, st), spre(nn, st), schild(nn, st), scount(nn, st);
+    DevBuf<double> sM(nn, st), sX(nn, st), sY(nn, st), sZ(nn, st);
+    hipLaunchKernelGGL(k_cells, dim3((unsigned)nblocks), dim3(kLvThreads), 0, st, n, nblocks, t.keys.get(),
+                       delta.get(), leaflv.get(), start.get(), base, blk.get(), t.geo.get(), pfirst.get(),
+                       t.prefix.get(), sfirst.get(), spre.get(), schild.get());
+    SRF_HIP(hipGetLastError());
+    for (int L = max_level; L >= 0; --L) {
+        const int32_t lo = base.off[L], hi = base.off[L + 1];
+        if (hi <= lo) continue;
+        const int32_t next_hi = L < kMaxLevel ? base.off[L + 2] : hi;
+        hipLaunchKernelGGL(k_moments, dim3(grid_for(hi - lo, 256 / kMomLanes, 1 << 30)), dim3(256), 0, st, lo, hi,
+                           next_hi, n, nn, sfirst.get(), spre.get(), schild.get(), pfirst.get(), start.get(),
+                           t.px.get(), t.py.get(), t.pz.get(), t.pm.get(), scount.get(), sM.get(), sX.get(), sY.get(),
+                           sZ.get(), t.range.get(), t.nM.get(), t.nX.get(), t.nY.get(), t.nZ.get(), t.leaf_of.get());
+        SRF_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_pack, dim3(grid_for(nn, B, 1 << 30)), dim3(B), 0, st, nn, t.geo.get(), t.range.get(),
+                       t.pack.get());
     SRF_HIP(hipGetLastError());
 
     // groups
-    DevBuf<int32_t> mark(n + 1, st);
-    fill_i32(mark.get(), 0, n + 1, st);
-    hipLaunchKernelGGL(k_group_marks, dim3(grid_for(nn, B, 1 << 30)), dim3(B), 0, st, nn, t.n_group, t.geo.get(),
-                       t.range.get(), mark.get());
-    SRF_HIP(hipGetLastError());
-    exclusive_scan_i32(mark.get(), n, true, st);
-    const int64_t ng = read_i32(mark.get() + n, st);
-    t.n_groups = ng;
     t.gfirst.alloc(ng, st);
     t.gcount.alloc(ng, st);
     t.glo.alloc(ng * 3, st);
