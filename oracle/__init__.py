@@ -299,11 +299,12 @@ class Lists:
     nidx: np.ndarray   # int64 node ids (preorder), ascending within a group
 
 
-def make_lists(tree: Tree, lo, hi, r_cut: float, theta: float, com=None) -> Lists:
+def make_lists(tree: Tree, lo, hi, r_cut: float, theta: float, com=None, boxes=None) -> Lists:
     """a6: per-group lists in canonical order (two passes: count, fill).
     With ``com`` ([nn, 3] centres of mass) the opening criterion measures
     the distance to each cell's centre of mass instead of its geometric
-    centre (the pruning stays box to box)."""
+    centre (the pruning stays box to box).  With ``boxes`` = (clo, chi)
+    ([nn, 3] each, a refitted tree) cells are measured by those boxes."""
     ng = lo.shape[0]
     lo = _f64(lo)
     hi = _f64(hi)
@@ -312,8 +313,11 @@ def make_lists(tree: Tree, lo, hi, r_cut: float, theta: float, com=None) -> List
         cx = cy = cz = None
     else:
         cx, cy, cz = (np.ascontiguousarray(com[:, k], dtype=np.float64) for k in range(3))
+    clo = chi = None
+    if boxes is not None:
+        clo, chi = (_f64(b) for b in boxes)
     args = (_ptr(tree.level), _ptr(tree.prefix), _ptr(tree.first), _ptr(tree.count), _ptr(tree.child),
-            _ptr(tree.leaf), _d(r_cut), _d(theta), _ptr(cx), _ptr(cy), _ptr(cz))
+            _ptr(tree.leaf), _d(r_cut), _d(theta), _ptr(cx), _ptr(cy), _ptr(cz), _ptr(clo), _ptr(chi))
     lib().or_lists_count(_i64(ng), _ptr(lo), _ptr(hi), *args, _ptr(np_), _ptr(nn_))
     poff = np.zeros(ng + 1, np.int64)
     noff = np.zeros(ng + 1, np.int64)
@@ -347,6 +351,36 @@ class OracleTree:
     @property
     def n_groups(self) -> int:
         return int(self.gfirst.size)
+
+    def refitted(self, x, y, z, m=None):
+        """The tree reused at new positions (input order) with the sort
+        order, cells and groups held: positions wrapped and taken in the old
+        sorted order, moments recomputed, each cell and group measured by
+        the box of its particles (moved to the image nearest the cell's
+        dyadic centre, or the group's first particle), and the lists built
+        on those boxes.  Returns a new OracleTree."""
+        import copy
+
+        r = copy.copy(self)
+        _, ux, uy, uz = morton_keys(x, y, z)
+        r.ux, r.uy, r.uz = ux[self.perm], uy[self.perm], uz[self.perm]
+        if m is not None:
+            r.m = _f64(m)[self.perm]
+        r.M, r.X = moments(self.tree, r.ux, r.uy, r.uz, r.m)
+        nn = self.tree.size
+        r.clo, r.chi = np.empty((nn, 3)), np.empty((nn, 3))
+        t = self.tree
+        lib().or_refit_cell_boxes(_i64(nn), _ptr(t.level), _ptr(t.prefix), _ptr(t.first), _ptr(t.count),
+                                  _ptr(t.child), _ptr(t.leaf), _ptr(r.ux), _ptr(r.uy), _ptr(r.uz), _ptr(r.clo),
+                                  _ptr(r.chi))
+        r.lo, r.hi = np.empty((self.n_groups, 3)), np.empty((self.n_groups, 3))
+        lib().or_refit_group_bbox(_i64(self.n_groups), _ptr(self.gfirst), _ptr(self.gcount), _ptr(r.ux), _ptr(r.uy),
+                                  _ptr(r.uz), _ptr(r.lo), _ptr(r.hi))
+        p = self.params
+        r.lists = make_lists(t, r.lo, r.hi, p.r_cut, p.theta, com=r.X if getattr(p, "mac", 0) == 1 else None,
+                             boxes=(r.clo, r.chi))
+        r._S = None
+        return r
 
     def interactions(self) -> int:
         """I = sum over groups of N_i * N_j (the paper's count, Table I)."""

@@ -672,11 +672,88 @@ static int accept_cell(const double cen[3], double side, const double cg[3], con
     return side * side < (theta * theta) * d2;
 }
 
+/* Refitted tree (tree reuse across the substeps of a step). */
+
+/* Box of every cell of a refitted tree: its particles' positions, each
+ * moved by the whole number of box lengths that brings it nearest the
+ * cell's dyadic centre, then min and max per axis; an inner cell takes the
+ * union of its children's boxes, each moved the same way as a whole (by the
+ * image of its centre).  Cells in preorder, so children follow parents. */
+void or_refit_cell_boxes(int64_t nn, const int32_t* level, const uint64_t* prefix, const int64_t* first,
+                         const int64_t* count, const int64_t* child, const uint8_t* leaf,
+                         const double* ux, const double* uy, const double* uz, double* lo, double* hi) {
+    const double* u[3] = {ux, uy, uz};
+    for (int64_t c = nn - 1; c >= 0; --c) {
+        double cref[3], side, l[3] = {INFINITY, INFINITY, INFINITY}, h[3] = {-INFINITY, -INFINITY, -INFINITY};
+        cell_geom(level[c], prefix[c], cref, &side);
+        if (leaf[c]) {
+            for (int64_t s = first[c]; s < first[c] + count[c]; ++s)
+                for (int a = 0; a < 3; ++a) {
+                    double v = u[a][s] - rint(u[a][s] - cref[a]);
+                    if (v < l[a]) l[a] = v;
+                    if (v > h[a]) h[a] = v;
+                }
+        } else {
+            for (int o = 0; o < 8; ++o) {
+                int64_t ch = child[c * 8 + o];
+                if (ch < 0) continue;
+                for (int a = 0; a < 3; ++a) {
+                    double sh = rint((lo[3 * ch + a] + hi[3 * ch + a]) * 0.5 - cref[a]);
+                    double vl = lo[3 * ch + a] - sh, vh = hi[3 * ch + a] - sh;
+                    if (vl < l[a]) l[a] = vl;
+                    if (vh > h[a]) h[a] = vh;
+                }
+            }
+        }
+        for (int a = 0; a < 3; ++a) { lo[3 * c + a] = l[a]; hi[3 * c + a] = h[a]; }
+    }
+}
+
+/* Box of every group of a refitted tree: positions moved to the image
+ * nearest the group's first particle, then min and max per axis. */
+void or_refit_group_bbox(int64_t ng, const int64_t* gfirst, const int64_t* gcount,
+                         const double* ux, const double* uy, const double* uz, double* lo, double* hi) {
+    const double* u[3] = {ux, uy, uz};
+    for (int64_t g = 0; g < ng; ++g)
+        for (int a = 0; a < 3; ++a) {
+            double ref = u[a][gfirst[g]], l = ref, h = ref;
+            for (int64_t s = gfirst[g]; s < gfirst[g] + gcount[g]; ++s) {
+                double v = u[a][s] - rint(u[a][s] - ref);
+                if (v < l) l = v;
+                if (v > h) h = v;
+            }
+            lo[3 * g + a] = l; hi[3 * g + a] = h;
+        }
+}
+
+/* A refitted tree (reused after its particles moved) measures each cell by
+ * the tight box [lo, hi] of its particles instead of its dyadic box: per
+ * axis t = |cen_c - cg| taken to the nearest image (t -= rint(t), since the
+ * boxes of a refitted tree may reach past the unit box), gap r = t - (half
+ * + h_g), e = max(0, r), d^2 = (e_x e_x + e_y e_y) + e_z e_z; prune iff
+ * d^2(half = the box's half sides) >= r_cut^2; accept iff s^2 < theta^2
+ * d^2(half = 0), s the larger of the cell's dyadic side and the box's
+ * longest side, cen_c the box's centre (or the centre of mass with that
+ * criterion).  Since the box holds the cell's particles, a cell holding a
+ * member of the group is then never accepted (d <= s sqrt(3)/2 for the
+ * geometric criterion), also where the box has shrunk to a point. */
+static double refit_gap2(const double cen[3], const double half[3], const double cg[3], const double hg[3]) {
+    double e[3];
+    for (int a = 0; a < 3; ++a) {
+        double t = cen[a] - cg[a];
+        t = fabs(t - rint(t));
+        double r = t - (half[a] + hg[a]);
+        e[a] = r > 0.0 ? r : 0.0;
+    }
+    return (e[0] * e[0] + e[1] * e[1]) + e[2] * e[2];
+}
+
 typedef struct {
     const int32_t* level; const uint64_t* prefix; const int64_t* first; const int64_t* count;
     const int64_t* child; const uint8_t* leaf;
     double rc, theta;
     const double *X, *Y, *Z;          /* centres of mass for the MAC, or NULL (geometric centre) */
+    const double *clo, *chi;          /* refitted cell boxes [nn*3], or NULL (dyadic cells) */
     double cg[3], hg[3];
     int64_t np, nn;
     int64_t* pidx; int64_t* nidx;     /* NULL in the counting pass */
@@ -684,11 +761,30 @@ typedef struct {
 
 static void list_rec(list_ctx* c, int64_t node) {
     double cen[3], side;
-    cell_geom(c->level[node], c->prefix[node], cen, &side);
-    if (prune_cell(cen, side, c->cg, c->hg, c->rc)) return;
-    double mac_cen[3] = {cen[0], cen[1], cen[2]};
-    if (c->X) { mac_cen[0] = c->X[node]; mac_cen[1] = c->Y[node]; mac_cen[2] = c->Z[node]; }
-    if (accept_cell(mac_cen, side, c->cg, c->hg, c->theta)) {
+    int accept;
+    if (c->clo) {
+        double half[3], zero[3] = {0.0, 0.0, 0.0}, hmax = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double l = c->clo[3 * node + a], h = c->chi[3 * node + a];
+            cen[a] = (l + h) * 0.5;
+            half[a] = (h - l) * 0.5;
+            if (half[a] > hmax) hmax = half[a];
+        }
+        side = hmax + hmax;
+        double dyadic = ldexp(1.0, -c->level[node]);
+        if (dyadic > side) side = dyadic;
+        if (refit_gap2(cen, half, c->cg, c->hg) >= c->rc * c->rc) return;
+        double mac_cen[3] = {cen[0], cen[1], cen[2]};
+        if (c->X) { mac_cen[0] = c->X[node]; mac_cen[1] = c->Y[node]; mac_cen[2] = c->Z[node]; }
+        accept = side * side < (c->theta * c->theta) * refit_gap2(mac_cen, zero, c->cg, c->hg);
+    } else {
+        cell_geom(c->level[node], c->prefix[node], cen, &side);
+        if (prune_cell(cen, side, c->cg, c->hg, c->rc)) return;
+        double mac_cen[3] = {cen[0], cen[1], cen[2]};
+        if (c->X) { mac_cen[0] = c->X[node]; mac_cen[1] = c->Y[node]; mac_cen[2] = c->Z[node]; }
+        accept = accept_cell(mac_cen, side, c->cg, c->hg, c->theta);
+    }
+    if (accept) {
         if (c->nidx) c->nidx[c->nn] = node;
         c->nn++;
         return;
@@ -713,17 +809,19 @@ static void group_frame(const double* lo, const double* hi, int64_t g, double cg
     }
 }
 
-/* Pass 1: particle and node entry counts per group. */
+/* Pass 1: particle and node entry counts per group (clo/chi: the boxes of
+ * a refitted tree, or NULL). */
 void or_lists_count(int64_t ng, const double* lo, const double* hi,
                     const int32_t* level, const uint64_t* prefix, const int64_t* first, const int64_t* count,
                     const int64_t* child, const uint8_t* leaf, double rc, double theta,
-                    const double* X, const double* Y, const double* Z, int64_t* np, int64_t* nn) {
+                    const double* X, const double* Y, const double* Z, const double* clo, const double* chi,
+                    int64_t* np, int64_t* nn) {
     #pragma omp parallel for schedule(dynamic, 8)
     for (int64_t g = 0; g < ng; ++g) {
         list_ctx c;
         memset(&c, 0, sizeof c);
         c.level = level; c.prefix = prefix; c.first = first; c.count = count; c.child = child; c.leaf = leaf;
-        c.rc = rc; c.theta = theta; c.X = X; c.Y = Y; c.Z = Z;
+        c.rc = rc; c.theta = theta; c.X = X; c.Y = Y; c.Z = Z; c.clo = clo; c.chi = chi;
         group_frame(lo, hi, g, c.cg, c.hg);
         list_rec(&c, 0);
         np[g] = c.np; nn[g] = c.nn;
@@ -735,14 +833,14 @@ void or_lists_count(int64_t ng, const double* lo, const double* hi,
 void or_lists_fill(int64_t ng, const double* lo, const double* hi,
                    const int32_t* level, const uint64_t* prefix, const int64_t* first, const int64_t* count,
                    const int64_t* child, const uint8_t* leaf, double rc, double theta,
-                   const double* X, const double* Y, const double* Z,
+                   const double* X, const double* Y, const double* Z, const double* clo, const double* chi,
                    const int64_t* poff, const int64_t* noff, int64_t* pidx, int64_t* nidx) {
     #pragma omp parallel for schedule(dynamic, 8)
     for (int64_t g = 0; g < ng; ++g) {
         list_ctx c;
         memset(&c, 0, sizeof c);
         c.level = level; c.prefix = prefix; c.first = first; c.count = count; c.child = child; c.leaf = leaf;
-        c.rc = rc; c.theta = theta; c.X = X; c.Y = Y; c.Z = Z;
+        c.rc = rc; c.theta = theta; c.X = X; c.Y = Y; c.Z = Z; c.clo = clo; c.chi = chi;
         group_frame(lo, hi, g, c.cg, c.hg);
         c.pidx = pidx + poff[g]; c.nidx = nidx + noff[g];
         list_rec(&c, 0);
@@ -1044,7 +1142,7 @@ void or_tree_force_bound(int64_t ng, const int64_t* gfirst, const int64_t* gcoun
         double cg[3], hg[3];
         group_frame(lo, hi, g, cg, hg);
         for (int64_t i = gfirst[g]; i < gfirst[g] + gcount[g]; ++i) {
-            double oi[3] = {ux[i] - cg[0], uy[i] - cg[1], uz[i] - cg[2]};
+            double oi[3] = {mimage(ux[i] - cg[0]), mimage(uy[i] - cg[1]), mimage(uz[i] - cg[2])};
             double acc = 0.0, nJ, nH;
             for (int64_t e = poff[g]; e < poff[g + 1]; ++e) {
                 int64_t j = pidx[e];
@@ -1100,7 +1198,7 @@ void or_tree_adjoint_bound(int64_t n, int64_t ng, const int64_t* gfirst, const i
             double cg[3], hg[3];
             group_frame(lo, hi, g, cg, hg);
             for (int64_t i = gfirst[g]; i < gfirst[g] + gcount[g]; ++i) {
-                double oi[3] = {ux[i] - cg[0], uy[i] - cg[1], uz[i] - cg[2]};
+                double oi[3] = {mimage(ux[i] - cg[0]), mimage(uy[i] - cg[1]), mimage(uz[i] - cg[2])};
                 double wn = norm3(wx[i], wy[i], wz[i]), nJ, nH;
                 for (int64_t e = poff[g]; e < poff[g + 1]; ++e) {
                     int64_t j = pidx[e];
