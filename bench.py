@@ -155,7 +155,8 @@ def cpu_baseline(ps, sample_groups: int, w):
     def adjoint(ng):
         t = time.perf_counter()
         oracle.lib().or_tree_adjoint(_i(ps.n), _i(ng), _p(gfs), _p(gcs), _p(L.poff), _p(L.pidx), _p(L.noff),
-                                     _p(L.nidx), _i(tree.size), _p(tree.first), _p(tree.count), _p(ux), _p(uy),
+                                     _p(L.nidx), _i(tree.size), _p(tree.first), _p(tree.count), _p(tree.level),
+                                     _p(tree.prefix), _p(ux), _p(uy),
                                      _p(uz), _p(m), _p(M), _p(X0), _p(X1), _p(X2), _p(wx), _p(wy), _p(wz),
                                      _d(p.G), _d(p.r_cut), _d(p.eps), _p(gx), _p(gy), _p(gz), _p(gm))
         return time.perf_counter() - t

@@ -136,7 +136,8 @@ def second_moments(tree: "Tree", ux, uy, uz, m, X):
     nn = tree.size
     S = np.empty((nn, 6))
     X0, X1, X2 = (np.ascontiguousarray(X[:, k]) for k in range(3))
-    lib().or_second_moments(_i64(nn), _ptr(tree.first), _ptr(tree.count), _ptr(_f64(ux)), _ptr(_f64(uy)),
+    lib().or_second_moments(_i64(nn), _ptr(tree.level), _ptr(tree.prefix), _ptr(tree.first), _ptr(tree.count),
+                            _ptr(_f64(ux)), _ptr(_f64(uy)),
                             _ptr(_f64(uz)), _ptr(_f64(m)), _ptr(X0), _ptr(X1), _ptr(X2), _ptr(S))
     return S
 
@@ -266,10 +267,12 @@ def build_tree(keys_sorted, n_leaf: int) -> Tree:
 
 
 def moments(tree: Tree, ux, uy, uz, m):
-    """a4: monopole mass and centre of mass of every cell (sorted-order inputs)."""
+    """a4: monopole mass and centre of mass of every cell (sorted-order
+    inputs), positions taken at their images nearest the cell's centre."""
     nn = tree.size
     M, X, Y, Z = (np.empty(nn) for _ in range(4))
-    lib().or_moments(_i64(nn), _ptr(tree.first), _ptr(tree.count), _ptr(_f64(ux)), _ptr(_f64(uy)),
+    lib().or_moments(_i64(nn), _ptr(tree.level), _ptr(tree.prefix), _ptr(tree.first), _ptr(tree.count),
+                     _ptr(_f64(ux)), _ptr(_f64(uy)),
                      _ptr(_f64(uz)), _ptr(_f64(m)), _ptr(M), _ptr(X), _ptr(Y), _ptr(Z))
     return M, np.stack([X, Y, Z], axis=1)
 
@@ -486,7 +489,7 @@ class OracleTree:
         lib().or_tree_adjoint(_i64(self.n), _i64(self.n_groups), _ptr(self.gfirst), _ptr(self.gcount),
                               _ptr(L.poff), _ptr(L.pidx), _ptr(L.noff), _ptr(L.nidx),
                               _i64(self.tree.size), _ptr(self.tree.first), _ptr(self.tree.count),
-                              _ptr(ux), _ptr(uy), _ptr(uz), _ptr(m), _ptr(M),
+                              _ptr(self.tree.level), _ptr(self.tree.prefix), _ptr(ux), _ptr(uy), _ptr(uz), _ptr(m), _ptr(M),
                               _ptr(X0), _ptr(X1), _ptr(X2), _ptr(wx), _ptr(wy), _ptr(wz),
                               _d(p.G), _d(p.r_cut), _d(p.eps), _ptr(gx), _ptr(gy), _ptr(gz), _ptr(gm))
         gxs = np.stack([gx, gy, gz], axis=1)
@@ -541,7 +544,7 @@ class OracleTree:
         lib().or_tree_adjoint_bound(_i64(self.n), _i64(self.n_groups), _ptr(self.gfirst), _ptr(self.gcount),
                                     _ptr(L.poff), _ptr(L.pidx), _ptr(L.noff), _ptr(L.nidx),
                                     _i64(self.tree.size), _ptr(self.tree.first), _ptr(self.tree.count),
-                                    _ptr(self.ux), _ptr(self.uy), _ptr(self.uz), _ptr(self.m), _ptr(self.M),
+                                    _ptr(self.tree.level), _ptr(self.tree.prefix), _ptr(self.ux), _ptr(self.uy), _ptr(self.uz), _ptr(self.m), _ptr(self.M),
                                     _ptr(X0), _ptr(X1), _ptr(X2), _ptr(wx), _ptr(wy), _ptr(wz), _ptr(self.lo),
                                     _ptr(self.hi), _d(p.G), _d(p.r_cut), _d(p.eps), _d(u_k), _d(u_c), _d(e_abs),
                                     _ptr(Ex), _ptr(Em))

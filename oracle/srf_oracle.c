@@ -181,6 +181,9 @@ void or_pair_jac(double dx, double dy, double dz, double rc, double eps, const d
 /* Minimum image of one coordinate difference (periodic unit box). */
 static double mimage(double d) { return d - rint(d); }
 
+/* The periodic image of coordinate v nearest the reference point ref. */
+static double near_image(double v, double ref) { return v - rint(v - ref); }
+
 /* ================================================================== */
 /* Brute force (the plain definition of the short-range sum)           */
 /* ================================================================== */
@@ -531,15 +534,26 @@ void or_tree_fill(int64_t n, const uint64_t* keys_sorted, int64_t n_leaf,
 
 /* Monopole moments, directly from the definition: M = sum m, X = sum m x / M
  * over the particles of the cell (Sec. 1 multipole expansion of a cell,
- * truncated at the monopole with the centre of mass as expansion point). */
-void or_moments(int64_t nn, const int64_t* first, const int64_t* count,
-                const double* ux, const double* uy, const double* uz, const double* m,
+ * truncated at the monopole with the centre of mass as expansion point).
+ * Each position is taken at its periodic image nearest the cell's dyadic
+ * centre: in a freshly built tree every particle lies inside its cell and
+ * this is the position itself; in a tree reused after its particles moved
+ * (refitted) a cell's particles may sit on both sides of a face of the unit
+ * box, and the centre of mass is that of the images which lie together. */
+static void cell_geom(int level, uint64_t prefix, double cen[3], double* side);
+
+void or_moments(int64_t nn, const int32_t* level, const uint64_t* prefix, const int64_t* first,
+                const int64_t* count, const double* ux, const double* uy, const double* uz, const double* m,
                 double* M, double* X, double* Y, double* Z) {
     #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t c = 0; c < nn; ++c) {
-        double sm = 0, sx = 0, sy = 0, sz = 0;
+        double cref[3], side, sm = 0, sx = 0, sy = 0, sz = 0;
+        cell_geom(level[c], prefix[c], cref, &side);
         for (int64_t s = first[c]; s < first[c] + count[c]; ++s) {
-            sm += m[s]; sx += m[s] * ux[s]; sy += m[s] * uy[s]; sz += m[s] * uz[s];
+            double vx = near_image(ux[s], cref[0]);
+            double vy = near_image(uy[s], cref[1]);
+            double vz = near_image(uz[s], cref[2]);
+            sm += m[s]; sx += m[s] * vx; sy += m[s] * vy; sz += m[s] * vz;
         }
         M[c] = sm; X[c] = sx / sm; Y[c] = sy / sm; Z[c] = sz / sm;
     }
@@ -953,15 +967,18 @@ void or_quad_term(double dx, double dy, double dz, const double* S, double rc, d
 
 /* Second moments about the centre of mass, directly from the definition:
  * S_c = sum_{k in c} m_k (x_k - X_c)(x_k - X_c)^T as (xx, yy, zz, xy, xz, yz)
- * (a cell never straddles the periodic boundary, so no image is taken). */
-void or_second_moments(int64_t nn, const int64_t* first, const int64_t* count,
-                       const double* ux, const double* uy, const double* uz, const double* m,
+ * with x_k at its image nearest the cell's dyadic centre, as in the centre of
+ * mass. */
+void or_second_moments(int64_t nn, const int32_t* level, const uint64_t* prefix, const int64_t* first,
+                       const int64_t* count, const double* ux, const double* uy, const double* uz, const double* m,
                        const double* X, const double* Y, const double* Z, double* S) {
     #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t c = 0; c < nn; ++c) {
-        double a[6] = {0, 0, 0, 0, 0, 0};
+        double cref[3], side, a[6] = {0, 0, 0, 0, 0, 0};
+        cell_geom(level[c], prefix[c], cref, &side);
         for (int64_t k = first[c]; k < first[c] + count[c]; ++k) {
-            double dx = ux[k] - X[c], dy = uy[k] - Y[c], dz = uz[k] - Z[c];
+            double dx = near_image(ux[k], cref[0]) - X[c], dy = near_image(uy[k], cref[1]) - Y[c];
+            double dz = near_image(uz[k], cref[2]) - Z[c];
             a[0] += m[k] * dx * dx; a[1] += m[k] * dy * dy; a[2] += m[k] * dz * dz;
             a[3] += m[k] * dx * dy; a[4] += m[k] * dx * dz; a[5] += m[k] * dy * dz;
         }
@@ -998,13 +1015,15 @@ void or_tree_quad(int64_t ng, const int64_t* gfirst, const int64_t* gcount, cons
  * fixed.  For each pair (i, source s of mass mu at y):
  *     dL/dx_i -= G mu J w_i,  dL/dy_s += G mu J w_i,  dL/dmu_s += G w_i . F(d).
  * Node sources then pass their gradients to member particles through
- * M_c = sum m_k and X_c = sum m_k x_k / M_c:
+ * M_c = sum m_k and X_c = sum m_k x_k / M_c (x_k at its image nearest the
+ * cell's dyadic centre, as in the moments):
  *     dL/dx_k += (m_k / M_c) dL/dX_c,
  *     dL/dm_k += dL/dM_c + (x_k - X_c) . dL/dX_c / M_c.
  * Scatter contributions are accumulated per thread and summed afterwards. */
 void or_tree_adjoint(int64_t n, int64_t ng, const int64_t* gfirst, const int64_t* gcount,
                      const int64_t* poff, const int64_t* pidx, const int64_t* noff, const int64_t* nidx,
-                     int64_t nnodes, const int64_t* nfirst, const int64_t* ncount,
+                     int64_t nnodes, const int64_t* nfirst, const int64_t* ncount, const int32_t* nlevel,
+                     const uint64_t* nprefix,
                      const double* ux, const double* uy, const double* uz, const double* m,
                      const double* NM, const double* NX, const double* NY, const double* NZ,
                      const double* wx, const double* wy, const double* wz,
@@ -1068,10 +1087,14 @@ void or_tree_adjoint(int64_t n, int64_t ng, const int64_t* gfirst, const int64_t
     for (int64_t c = 0; c < nnodes; ++c) {
         double gX[3] = {Q[4 * c], Q[4 * c + 1], Q[4 * c + 2]}, gM = Q[4 * c + 3];
         if (gX[0] == 0.0 && gX[1] == 0.0 && gX[2] == 0.0 && gM == 0.0) continue;
+        double cref[3], side;
+        cell_geom(nlevel[c], nprefix[c], cref, &side);
         for (int64_t k = nfirst[c]; k < nfirst[c] + ncount[c]; ++k) {
             double f = m[k] / NM[c];
+            double o[3] = {near_image(ux[k], cref[0]) - NX[c], near_image(uy[k], cref[1]) - NY[c],
+                           near_image(uz[k], cref[2]) - NZ[c]};
             P[4 * k] += f * gX[0]; P[4 * k + 1] += f * gX[1]; P[4 * k + 2] += f * gX[2];
-            P[4 * k + 3] += gM + ((ux[k] - NX[c]) * gX[0] + (uy[k] - NY[c]) * gX[1] + (uz[k] - NZ[c]) * gX[2]) / NM[c];
+            P[4 * k + 3] += gM + (o[0] * gX[0] + o[1] * gX[1] + o[2] * gX[2]) / NM[c];
         }
     }
     for (int64_t k = 0; k < n; ++k) {
@@ -1175,7 +1198,8 @@ void or_tree_force_bound(int64_t ng, const int64_t* gfirst, const int64_t* gcoun
  * Outputs in sorted order, times |G|. */
 void or_tree_adjoint_bound(int64_t n, int64_t ng, const int64_t* gfirst, const int64_t* gcount,
                            const int64_t* poff, const int64_t* pidx, const int64_t* noff, const int64_t* nidx,
-                           int64_t nnodes, const int64_t* nfirst, const int64_t* ncount,
+                           int64_t nnodes, const int64_t* nfirst, const int64_t* ncount, const int32_t* nlevel,
+                     const uint64_t* nprefix,
                            const double* ux, const double* uy, const double* uz, const double* m,
                            const double* NM, const double* NX, const double* NY, const double* NZ,
                            const double* wx, const double* wy, const double* wz, const double* lo, const double* hi,
@@ -1239,10 +1263,13 @@ void or_tree_adjoint_bound(int64_t n, int64_t ng, const int64_t* gfirst, const i
     for (int64_t c = 0; c < nnodes; ++c) {
         double EXc = Q[3 * c], EMc = Q[3 * c + 1], GXc = Q[3 * c + 2];
         if (EXc == 0.0 && EMc == 0.0 && GXc == 0.0) continue;
-        double uc = u_c * (2.0 * (double)ncount[c] + 2.0);
+        double uc = u_c * (2.0 * (double)ncount[c] + 2.0), cref[3], side;
+        cell_geom(nlevel[c], nprefix[c], cref, &side);
         for (int64_t k = nfirst[c]; k < nfirst[c] + ncount[c]; ++k) {
+            double o[3] = {near_image(ux[k], cref[0]) - NX[c], near_image(uy[k], cref[1]) - NY[c],
+                           near_image(uz[k], cref[2]) - NZ[c]};
             P[2 * k] += (m[k] / NM[c]) * (EXc + GXc * uc);
-            P[2 * k + 1] += EMc + norm3(ux[k] - NX[c], uy[k] - NY[c], uz[k] - NZ[c]) * EXc / NM[c]
+            P[2 * k + 1] += EMc + norm3(o[0], o[1], o[2]) * EXc / NM[c]
                           + (GXc / NM[c]) * (e_abs + uc);
         }
     }

@@ -145,3 +145,132 @@ def test_refit_without_motion_prunes_no_less():
     assert np.array_equal(rt.force(), rt.force())
     # at theta = 0 both are the exact sum within r_cut
     assert np.allclose(rt.force(), ot.force(), rtol=1e-12, atol=1e-12 * np.abs(ot.force()).max())
+
+
+@pytest.mark.parametrize("name", ["clustered", "uniform"])
+def test_refitted_centres_of_mass_follow_a_translation(name):
+    """Every particle moved by the same vector, some across a face of the
+    unit box: each cell's centre of mass (the root aside, which is never a
+    source) moves by exactly that vector, and the masses are unchanged --
+    also for cells whose particles now sit on both sides of the face."""
+    ps = _sets()[name]
+    ot = oracle.OracleTree(ps.x, ps.y, ps.z, ps.m, ps.params)
+    shift = np.array([-0.0123, 0.0071, 0.0])
+    new = np.mod(np.stack([ps.x, ps.y, ps.z], axis=1) + shift, 1.0)
+    rt = ot.refitted(new[:, 0], new[:, 1], new[:, 2])
+    t = ot.tree
+    sel = t.level >= 1
+    assert np.array_equal(rt.M, ot.M)
+    moved = rt.X[sel] - ot.X[sel]
+    assert np.max(np.abs(moved - shift)) <= 1e-12
+    # some cell does hold particles on both sides of the face x = 0
+    straddle = [c for c in np.nonzero(sel)[0] if np.ptp(new[ot.perm][t.first[c]:t.first[c] + t.count[c], 0]) > 0.5]
+    assert straddle
+
+
+@pytest.mark.parametrize("name", ["clustered", "uniform"])
+def test_refitted_force_error_after_a_translation(name):
+    """The refitted tree's same-list force at translated positions is as
+    close to the brute-force sum as the fresh tree's force at the original
+    positions: the monopole error does not grow where cells straddle a
+    face of the unit box."""
+    ps = _sets()[name]
+    p = synth.Params(ps.params.G, ps.params.r_cut, ps.params.eps, 1.0, 64, 16)
+    ot = oracle.OracleTree(ps.x, ps.y, ps.z, ps.m, p)
+    shift = np.array([-0.0123, 0.0071, 0.0])
+    new = np.mod(np.stack([ps.x, ps.y, ps.z], axis=1) + shift, 1.0)
+    rt = ot.refitted(new[:, 0], new[:, 1], new[:, 2])
+    bf0 = oracle.brute_force(ps.x, ps.y, ps.z, ps.m, 1.0, p.r_cut, p.eps, method="n2")
+    bf1 = oracle.brute_force(new[:, 0], new[:, 1], new[:, 2], ps.m, 1.0, p.r_cut, p.eps, method="n2")
+    e0 = np.linalg.norm(ot.force() - bf0, axis=1)
+    e1 = np.linalg.norm(rt.force() - bf1, axis=1)
+    scale = np.max(np.linalg.norm(bf0, axis=1))
+    assert rt.lists.nidx.size > 0
+    assert np.max(e1) <= 2.0 * np.max(e0) + 1e-12 * scale
+    assert np.sqrt(np.mean(e1 ** 2)) <= 1.5 * np.sqrt(np.mean(e0 ** 2)) + 1e-12 * scale
+
+
+def _fd(rt, w, s, axis, h):
+    u = [rt.ux.copy(), rt.uy.copy(), rt.uz.copy()]
+    up = [a.copy() for a in u]
+    um = [a.copy() for a in u]
+    up[axis][s] += h
+    um[axis][s] -= h
+    return float(np.sum(w[rt.perm] * (rt.force_sorted(*up) - rt.force_sorted(*um)))) / (2 * h)
+
+
+def _fd_mass(rt, w, s, rel):
+    h = rt.m[s] * rel
+    mp, mm = rt.m.copy(), rt.m.copy()
+    mp[s] += h
+    mm[s] -= h
+    return float(np.sum(w[rt.perm] * (rt.force_sorted(m=mp) - rt.force_sorted(m=mm)))) / (2 * h)
+
+
+def _slab():
+    """A slab of particles on both sides of the face x = 0 (|x| < 0.08),
+    moved by -0.0123 in x: most cells near the face then hold particles on
+    both sides of it, and many are accepted with their centre of mass
+    within r_cut of the group."""
+    rng = np.random.default_rng(5)
+    n = 4000
+    x = np.concatenate([rng.random(n // 2) * 0.08, 0.92 + rng.random(n // 2) * 0.08])
+    y, z = 0.3 + 0.4 * rng.random(n), 0.3 + 0.4 * rng.random(n)
+    p = synth.Params(1.0, 0.06, 3e-4, 1.0, 64, 16)
+    ot = oracle.OracleTree(x, y, z, np.full(n, 1.0 / n), p)
+    new = np.mod(np.stack([x, y, z], axis=1) + np.array([-0.0123, 0.0071, 0.0]), 1.0)
+    return ot, ot.refitted(new[:, 0], new[:, 1], new[:, 2])
+
+
+def test_refitted_adjoint_matches_finite_differences_across_a_face():
+    """The gradient of L = sum w . a on a refitted tree, structure held
+    fixed, against central differences of its own forward, for particles of
+    accepted cells whose particles sit on both sides of a face of the unit
+    box (the mass derivative goes through x_k - X_c at its nearest image)."""
+    ot, rt = _slab()
+    t = ot.tree
+    acc = np.unique(rt.lists.nidx)
+    straddle = [c for c in acc if np.ptp(rt.ux[t.first[c]:t.first[c] + t.count[c]]) > 0.5]
+    assert len(straddle) > 20
+    w = synth.loss_weights(rt.n, 9)
+    gx, gm = rt.adjoint(w)
+    rng = np.random.default_rng(3)
+    ex, em = [], []
+    for c in rng.choice(straddle, 12, replace=False):
+        for s in rng.choice(np.arange(t.first[c], t.first[c] + t.count[c]), 2, replace=False):
+            k = rt.perm[s]
+            for a in range(3):
+                ex.append(abs(_fd(rt, w, s, a, 1e-7) - gx[k, a]) / np.abs(gx[k]).max())
+            em.append(abs(_fd_mass(rt, w, s, 1e-6) - gm[k]) / max(abs(gm[k]), 1e-6 * np.abs(gm).max()))
+    assert max(ex) < 1e-4 and max(em) < 1e-4, (max(ex), max(em))
+
+
+def test_refitted_force_across_a_face_is_translation_covariant():
+    """On the slab across the face x = 0: the tree refitted to the moved
+    positions and the same tree refitted to the unmoved ones have the same
+    lists and the same forces to rounding (moving every particle by one
+    vector moves every box and centre of mass by it, also where a cell's
+    particles now sit on both sides of the face), and the force stays as
+    close to the brute-force sum as the fresh tree's."""
+    ot, rt = _slab()
+    p = ot.params
+    x0 = np.empty((ot.n, 3))
+    x1 = np.empty((ot.n, 3))
+    x0[ot.perm] = np.stack([ot.ux, ot.uy, ot.uz], axis=1)
+    x1[rt.perm] = np.stack([rt.ux, rt.uy, rt.uz], axis=1)
+    r0 = ot.refitted(x0[:, 0], x0[:, 1], x0[:, 2])
+    for a, b in [(r0.lists.poff, rt.lists.poff), (r0.lists.pidx, rt.lists.pidx), (r0.lists.noff, rt.lists.noff),
+                 (r0.lists.nidx, rt.lists.nidx)]:
+        assert np.array_equal(a, b)
+    m = np.empty(ot.n)
+    m[ot.perm] = ot.m
+    bf0 = oracle.brute_force(x0[:, 0], x0[:, 1], x0[:, 2], m, 1.0, p.r_cut, p.eps, method="n2")
+    bf1 = oracle.brute_force(x1[:, 0], x1[:, 1], x1[:, 2], m, 1.0, p.r_cut, p.eps, method="n2")
+    scale = np.max(np.linalg.norm(bf0, axis=1))
+    assert np.max(np.linalg.norm(rt.force() - r0.force(), axis=1)) <= 1e-12 * scale
+    # so is the quadrupole term (second moments about the centre of mass)
+    dq = rt.force_quadrupole() - r0.force_quadrupole()
+    assert np.max(np.linalg.norm(dq, axis=1)) <= 1e-12 * scale
+    e0 = np.linalg.norm(ot.force() - bf0, axis=1)
+    e1 = np.linalg.norm(rt.force() - bf1, axis=1)
+    assert np.sqrt(np.mean(e1 ** 2)) <= 1.5 * np.sqrt(np.mean(e0 ** 2))
