@@ -323,8 +323,10 @@ def main():
                        steps="TSC assignment, 3-D FFT, Green's function, inverse FFT, 4-point differences, "
                              "TSC interpolation (FP64)")
         del tree
-        # one step of the multiple-stepsize integrator (1 PM + 2 PP cycles,
-        # each PP cycle with its own tree and lists) on a copy of the state
+        # one step of the multiple-stepsize integrator (1 PM + 2 PP cycles;
+        # the second PP cycle refits the first one's tree, each builds its
+        # lists) on a copy of the state, and the same step rebuilding the
+        # tree in both cycles
         xs, vs = x.clone(), torch.zeros_like(x)
         integ = srf.TreePMIntegrator(p, n_mesh)
         integ.step(xs, vs, m, 1e-4)
@@ -334,6 +336,14 @@ def main():
             integ.step(xs, vs, m, 1e-4)
         torch.cuda.synchronize()
         pm_info["treepm_step_ms"] = (time.perf_counter() - t1) / 3 * 1e3
+        integ = srf.TreePMIntegrator(p, n_mesh, reuse_tree=False)
+        integ.step(xs, vs, m, 1e-4)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(3):
+            integ.step(xs, vs, m, 1e-4)
+        torch.cuda.synchronize()
+        pm_info["treepm_step_ms_rebuild"] = (time.perf_counter() - t1) / 3 * 1e3
         del xs, vs, integ
 
     dominant = "adjoint" if ka >= kf else "force"

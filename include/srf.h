@@ -19,7 +19,8 @@
  * Calls are made in this order: srf_tree_build -> srf_make_lists ->
  * srf_short_range_force and/or srf_short_range_adjoint (and, over the same
  * tree and lists, srf_short_range_potential, or srf_short_range_quadrupole
- * after srf_short_range_force on the same output).  srf_pm_force needs only
+ * after srf_short_range_force on the same output); srf_tree_refit moves a
+ * tree's particles, after which srf_make_lists is called again.  srf_pm_force needs only
  * the tree; srf_kick and srf_drift need no handle.
  *
  * Memory and streams.  Unless a comment says "host", every pointer is a
@@ -116,6 +117,30 @@ typedef struct srf_lists srf_lists;
 int srf_tree_build(int64_t n, const double* x, const double* y, const double* z, int64_t pos_stride,
                    const double* m, int64_t m_stride, const srf_params* p, void* stream, srf_tree** out);
 
+/* Tree reuse within a step (Sec. 3.1: a simulation step is one PM cycle and
+ * two PP cycles; the second PP cycle may reuse the first one's tree).  The
+ * particles' new positions (and, if m is not NULL, masses), in the input
+ * order and number of srf_tree_build, replace the tree's; the sort order,
+ * cells and groups are kept.  Positions are wrapped into [0,1)^3, and each
+ * cell and group is then measured by the box of its particles instead of
+ * its dyadic cube: a leaf takes its particles at their periodic images
+ * nearest its dyadic centre, an inner cell the union of its children's
+ * boxes, each moved by the whole number of box lengths that brings the
+ * child box's centre nearest the cell's centre; a group's box holds its
+ * particles' images nearest its first particle.  The monopoles are
+ * recomputed from the same images (a cell whose particles lie across a
+ * face of the unit box keeps them together).  srf_make_lists prunes and
+ * opens on these boxes: every pair within r_cut is still found however far
+ * the particles moved, but the lists grow as the boxes do, so rebuild when
+ * they have moved far.  Refitting again starts from the same structure.
+ * Lists built before this call are refused after it (SRF_EMISMATCH).
+ *   x, y, z, pos_stride, m, m_stride: as srf_tree_build.
+ * Synchronises `stream` once (the device's check of the inputs).
+ * Errors: SRF_EINVAL, SRF_EDOMAIN (the tree is then unchanged), SRF_ENOMEM,
+ * SRF_EHIP (the tree must then be freed). */
+int srf_tree_refit(srf_tree* t, const double* x, const double* y, const double* z, int64_t pos_stride,
+                   const double* m, int64_t m_stride, void* stream);
+
 /* Step a6: per-group interaction lists.  Defined by Sec. 2 (Barnes'
  * modified algorithm: one list of cells and particles per group, built by
  * one traversal for the whole group), Fig. 2 (the short-range force needs
@@ -125,7 +150,10 @@ int srf_tree_build(int64_t n, const double* x, const double* y, const double* z,
  * one monopole if side^2 < theta^2 d^2 (d: distance from the group box to
  * the cell centre, or to its centre of mass with SRF_MAC_COM), expanded to
  * its particles if it is a leaf, and opened otherwise (the decisions are
- * made in FP64 without fused multiply-add).
+ * made in FP64 without fused multiply-add).  For a refitted tree
+ * (srf_tree_refit) each cell is its particles' box instead: the distances
+ * are taken per axis to the nearest periodic image of the box centre, and
+ * the side is the larger of the dyadic side and the box's longest side.
  * p must carry the n_group and n_leaf the tree was built with.  The lists
  * belong to this tree: after it is freed they are refused (SRF_EMISMATCH)
  * by every call, even with a new tree at the same address.
@@ -273,6 +301,10 @@ int srf_tree_export(const srf_tree* t, uint64_t* keys_sorted, int64_t* perm,
 
 /* Monopoles per cell (preorder): mass and centre of mass. */
 int srf_moments_export(const srf_tree* t, double* M, double* X, double* Y, double* Z);
+
+/* Boxes of the cells of a refitted tree (preorder, x,y,z per cell):
+ * lo, hi [n_nodes*3].  SRF_EINVAL for a tree that was not refitted. */
+int srf_cell_boxes_export(const srf_tree* t, double* lo, double* hi);
 
 /* Wrapped positions and masses in sorted order [n]. */
 int srf_sorted_export(const srf_tree* t, double* x, double* y, double* z, double* m);

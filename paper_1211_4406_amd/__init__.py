@@ -23,7 +23,8 @@ import numpy as np
 import torch
 
 __all__ = [
-    "Params", "Tree", "Lists", "SrfError", "FP32_REL", "FP64", "MAC_CENTRE", "MAC_COM", "lib", "lib_path", "tree_build", "make_lists",
+    "Params", "Tree", "Lists", "SrfError", "FP32_REL", "FP64", "MAC_CENTRE", "MAC_COM", "lib", "lib_path", "tree_build",
+    "tree_refit", "make_lists",
     "short_range_force", "short_range_adjoint", "short_range_adjoint_noalloc", "short_range_potential", "short_range_quadrupole", "ShortRange", "short_range", "pm_force", "kick", "drift",
     "TreePMIntegrator", "set_kernel_timing", "last_kernel_ms",
 ]
@@ -92,6 +93,7 @@ def lib():
     L = C.CDLL(_LIB_PATH)
     vp, i64, i32, pp = C.c_void_p, C.c_int64, C.c_int32, C.POINTER(_CParams)
     L.srf_tree_build.argtypes = [i64, vp, vp, vp, i64, vp, i64, pp, vp, C.POINTER(vp)]
+    L.srf_tree_refit.argtypes = [vp, vp, vp, vp, i64, vp, i64, vp]
     L.srf_make_lists.argtypes = [vp, pp, vp, C.POINTER(vp)]
     L.srf_short_range_force.argtypes = [vp, vp, pp, vp, vp, vp, i64, vp]
     L.srf_short_range_adjoint.argtypes = [vp, vp, pp, vp, vp, vp, i64, vp, vp, vp, i64, vp, i64, vp]
@@ -110,6 +112,7 @@ def lib():
     L.srf_tree_export.argtypes = [vp] + [vp] * 10
     L.srf_moments_export.argtypes = [vp] + [vp] * 4
     L.srf_sorted_export.argtypes = [vp] + [vp] * 4
+    L.srf_cell_boxes_export.argtypes = [vp, vp, vp]
     L.srf_lists_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
     L.srf_lists_export.argtypes = [vp] * 5
     L.srf_short_range_potential.argtypes = [vp, vp, pp, vp, i64, vp]
@@ -195,6 +198,13 @@ class Tree:
         _check(lib().srf_moments_export(self._h, _hptr(M), _hptr(X), _hptr(Y), _hptr(Z)))
         return M, np.stack([X, Y, Z], axis=1)
 
+    def cell_boxes(self):
+        """Boxes (lo, hi) [n_nodes, 3] of the cells of a refitted tree."""
+        nn = self.info()["n_nodes"]
+        lo, hi = np.empty((nn, 3)), np.empty((nn, 3))
+        _check(lib().srf_cell_boxes_export(self._h, _hptr(lo), _hptr(hi)))
+        return lo, hi
+
     def sorted_particles(self):
         x, y, z, m = (np.empty(self.n) for _ in range(4))
         _check(lib().srf_sorted_export(self._h, _hptr(x), _hptr(y), _hptr(z), _hptr(m)))
@@ -246,6 +256,22 @@ def tree_build(x: torch.Tensor, m: torch.Tensor, params: Params) -> Tree:
     _check(lib().srf_tree_build(C.c_int64(x.shape[0]), *cols, C.c_int64(ps), _dptr(m), C.c_int64(m.stride(0)),
                                 C.byref(cp), _stream(), C.byref(h)))
     return Tree(h, params, int(x.shape[0]))
+
+
+def tree_refit(tree: Tree, x: torch.Tensor, m: torch.Tensor | None = None) -> Tree:
+    """Reuse ``tree`` at new positions x [N,3] (and masses m [N], or the
+    tree's if None): sort order, cells and groups kept, moments and boxes
+    recomputed.  Lists of the old positions are refused afterwards."""
+    x, cols, ps = _cols(x)
+    if x.shape[0] != tree.n:
+        raise ValueError("x must hold the tree's n particles")
+    mp, ms = None, 1
+    if m is not None:
+        if m.dtype != torch.float64 or not m.is_cuda or m.dim() != 1 or m.shape[0] != tree.n:
+            raise ValueError("masses must be a float64 CUDA tensor of shape [N]")
+        mp, ms = _dptr(m), m.stride(0)
+    _check(lib().srf_tree_refit(tree.handle, *cols, C.c_int64(ps), mp, C.c_int64(ms), _stream()))
+    return tree
 
 
 def make_lists(tree: Tree, params: Params) -> Lists:
@@ -365,20 +391,28 @@ class TreePMIntegrator:
 
         kick(PM, dt/2); 2 x [kick(PP, dt/4); drift(dt/2); PP at new x; kick(PP, dt/4)]; PM at new x; kick(PM, dt/2)
 
-    which is symmetric (time-reversible) and evaluates PM once and PP twice
-    per step; the PM of the new positions reuses the tree of the last PP
-    evaluation, and the accelerations of the step's end start the next.
+    which evaluates PM once and PP twice per step; the PM of the new
+    positions uses the tree of the last PP evaluation, and the accelerations
+    of the step's end start the next.  With ``reuse_tree`` the second PP
+    cycle refits the first one's tree to the drifted positions instead of
+    building a new one (lists are always rebuilt); the step is then
+    time-symmetric only up to the tree's truncation error (exactly so at
+    theta = 0, where the lists hold every pair within r_cut either way).
     x, v are [N,3] float64 device tensors updated in place; m is [N]."""
 
-    def __init__(self, params: Params, n_mesh: int, pm_r_cut: float | None = None):
+    def __init__(self, params: Params, n_mesh: int, pm_r_cut: float | None = None, reuse_tree: bool = True):
         self.params = params
         self.n_mesh = int(n_mesh)
         self.pm_r_cut = params.r_cut if pm_r_cut is None else pm_r_cut
+        self.reuse_tree = bool(reuse_tree)
         self.a_pp = None
         self.a_pm = None
 
-    def _pp(self, x, m):
-        tree = tree_build(x, m, self.params)
+    def _pp(self, x, m, tree=None):
+        if tree is None:
+            tree = tree_build(x, m, self.params)
+        else:
+            tree_refit(tree, x)
         lists = make_lists(tree, self.params)
         return tree, short_range_force(tree, lists, self.params, device=x.device)
 
@@ -391,7 +425,7 @@ class TreePMIntegrator:
         for _ in range(2):
             kick(v, self.a_pp, 0.25 * dt)
             drift(x, v, 0.5 * dt)
-            tree, self.a_pp = self._pp(x, m)
+            tree, self.a_pp = self._pp(x, m, tree if self.reuse_tree else None)
             kick(v, self.a_pp, 0.25 * dt)
         self.a_pm = pm_force(tree, self.params.G, self.pm_r_cut, self.n_mesh, device=x.device)
         kick(v, self.a_pm, 0.5 * dt)

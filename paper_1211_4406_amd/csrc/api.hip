@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "common.h"
@@ -127,6 +128,37 @@ int srf_tree_build(int64_t n, const double* x, const double* y, const double* z,
     }
     *out = h;
     return SRF_OK;
+}
+
+int srf_tree_refit(srf_tree* t, const double* x, const double* y, const double* z, int64_t pos_stride,
+                   const double* m, int64_t m_stride, void* stream) {
+    return guarded([&] {
+        if (!t) srf::fail(SRF_EINVAL, "tree is NULL");
+        if (!x || !y || !z) srf::fail(SRF_EINVAL, "NULL position pointer");
+        if (pos_stride < 1 || (m && m_stride < 1)) srf::fail(SRF_EINVAL, "strides must be >= 1");
+        srf::Tree& T = t->t;
+        hipStream_t st = (hipStream_t)stream;
+        const int64_t n = T.n;
+        // gather into new buffers: the tree is untouched until the inputs pass
+        srf::DevBuf<double> nx(n, st), ny(n, st), nz(n, st), nm;
+        if (m) nm.alloc(n, st);
+        srf::DevBuf<int32_t> flag(1, st);
+        srf::fill_i32(flag.get(), 0, 1, st);
+        srf::gather_refit(T, x, y, z, pos_stride, m, m_stride, flag.get(), nx.get(), ny.get(), nz.get(),
+                          m ? nm.get() : nullptr, st);
+        int32_t hflag = 0;
+        SRF_HIP(hipMemcpyAsync(&hflag, flag.get(), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        SRF_HIP(hipStreamSynchronize(st));
+        if (hflag & 1) srf::fail(SRF_EDOMAIN, "non-finite particle position");
+        if (hflag & 2) srf::fail(SRF_EDOMAIN, "particle mass not finite and > 0");
+        T.px = std::move(nx);
+        T.py = std::move(ny);
+        T.pz = std::move(nz);
+        if (m) T.pm = std::move(nm);
+        T.id = ++g_tree_generation;   // lists of the old positions are refused from here on
+        T.refit = true;
+        srf::refit_cells_and_groups(T, st);
+    });
 }
 
 int srf_make_lists(const srf_tree* t, const srf_params* p, void* stream, srf_lists** out) {
@@ -325,6 +357,16 @@ int srf_moments_export(const srf_tree* t, double* M, double* X, double* Y, doubl
         copy_out(X, T.nX.get(), T.n_nodes, T.stream);
         copy_out(Y, T.nY.get(), T.n_nodes, T.stream);
         copy_out(Z, T.nZ.get(), T.n_nodes, T.stream);
+    });
+}
+
+int srf_cell_boxes_export(const srf_tree* t, double* lo, double* hi) {
+    return guarded([&] {
+        if (!t) srf::fail(SRF_EINVAL, "tree is NULL");
+        const srf::Tree& T = t->t;
+        if (!T.refit) srf::fail(SRF_EINVAL, "the tree has not been refitted: its cells are their dyadic boxes");
+        copy_out(lo, T.clo.get(), T.n_nodes * 3, T.stream);
+        copy_out(hi, T.chi.get(), T.n_nodes * 3, T.stream);
     });
 }
 

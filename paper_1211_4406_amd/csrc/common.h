@@ -87,6 +87,8 @@ struct Tree {
     int64_t n_groups = 0;
     int32_t max_level = 0;
     int32_t n_group = 0, n_leaf = 0;
+    bool refit = false;        // cells measured by the boxes of their particles (tree_refit)
+    int32_t level_off[kLevels + 1] = {};   // first slot of each level, and the total
     hipStream_t stream = nullptr;
     // sorted particles
     DevBuf<uint64_t> keys;     // sorted keys
@@ -99,6 +101,11 @@ struct Tree {
     DevBuf<uint4> pack;        // packed records (see kPackCountMax)
     DevBuf<uint64_t> prefix;
     DevBuf<double> nM, nX, nY, nZ;   // monopoles
+    // the cells again as level slots (each level's cells ordered by first
+    // particle; a cell's children are one run of the next level's slots):
+    // first particle, preorder id and first child slot (-1 for a leaf)
+    DevBuf<int32_t> sfirst, spre, schild;
+    DevBuf<double> clo, chi;   // [nn*3] boxes of the cells of a refitted tree
     // groups, in order of first
     DevBuf<int32_t> gfirst, gcount;
     DevBuf<double> glo, ghi;   // [ng*3]
@@ -118,6 +125,12 @@ struct Lists {
     DevBuf<int64_t> off;       // [ng+1] entry offsets per group
     DevBuf<int32_t> ent;       // entries: s >= 0 particle (sorted index), -(c+1) cell c
 };
+
+// Nearest periodic image of a coordinate difference (unit box).  Targets are
+// taken as offsets from their group's centre through it too: in a fresh
+// tree a group lies inside one level-1 cell and the offset is unchanged; in
+// a refitted tree its box may reach past the unit box.
+__device__ __forceinline__ double image(double d) { return d - rint(d); }
 
 // Workgroups are handed to the 8 XCDs (each with its own L2) round-robin in
 // launch order.  This maps launch index b of nb to a logical block index so
@@ -145,6 +158,14 @@ void build_sorted(Tree& t, const double* x, const double* y, const double* z, in
 // a3-a5; synchronises `stream` once, and fails with SRF_EDOMAIN if *d_flag
 // (set by build_sorted) is nonzero
 void build_cells_and_groups(Tree& t, int32_t* d_flag, hipStream_t stream);
+// Tree reuse: positions and masses (m may be NULL: masses kept) gathered in
+// the tree's sorted order into px..pm, wrapped, with the same checks as
+// build_sorted (bits of *d_flag)
+void gather_refit(const Tree& t, const double* x, const double* y, const double* z, int64_t ps, const double* m,
+                  int64_t ms, int32_t* d_flag, double* px, double* py, double* pz, double* pm, hipStream_t stream);
+// moments and cell and group boxes of the tree's current particles, the
+// structure held (asynchronous)
+void refit_cells_and_groups(Tree& t, hipStream_t stream);
 // a6
 void build_lists(const Tree& t, Lists& l, hipStream_t stream);
 // a7-a8

@@ -16,7 +16,17 @@
 //   prune  iff d2(half = side/2) >= r_cut * r_cut
 //   accept iff side * side < (theta * theta) * d2(half = 0)
 // with cen_c the cell's geometric centre, or for the acceptance test of the
-// centre-of-mass criterion its centre of mass.
+// centre-of-mass criterion its centre of mass.  A refitted tree measures
+// each cell by the box [lo, hi] of its particles instead:
+//   cen_c = (lo + hi) * 0.5, half = (hi - lo) * 0.5 per axis,
+//   per axis t = cen_c - cen_g, t = |t - rint(t)|, e = max(0, t - (half + h_g))
+//   d2 as above; prune iff d2 >= r_cut * r_cut,
+//   accept iff s * s < (theta * theta) * d2(half = 0, cen_c or the centre of mass),
+// s the larger of the cell's dyadic side and the box's longest side
+// (2 max(half)), so that a cell holding a member of the group is never
+// accepted, however small its box.
+#include <type_traits>
+
 #include "common.h"
 
 namespace srf {
@@ -84,6 +94,39 @@ __device__ __forceinline__ int classify(const Cell& k, const double* mc, const F
     return k.leaf ? 2 : 3;
 }
 
+__device__ __forceinline__ double refit_axis_gap(double cen, double cg, double half) {
+    double t = cen - cg;
+    t = fabs(t - rint(t));
+    double r = t - half;
+    return r > 0.0 ? r : 0.0;
+}
+
+// The same classification for a cell of a refitted tree with box [bl, bh].
+__device__ __forceinline__ int classify_refit(const Cell& k, const double* bl, const double* bh, const double* mc,
+                                              bool com, const Frame& f, double rc2, double th2) {
+    double cen[3], half[3], hmax = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cen[a] = (bl[a] + bh[a]) * 0.5;
+        half[a] = (bh[a] - bl[a]) * 0.5;
+        hmax = half[a] > hmax ? half[a] : hmax;
+    }
+    double side = hmax + hmax;
+    side = k.side > side ? k.side : side;
+    double ex = refit_axis_gap(cen[0], f.cg[0], half[0] + f.hg[0]);
+    double ey = refit_axis_gap(cen[1], f.cg[1], half[1] + f.hg[1]);
+    double ez = refit_axis_gap(cen[2], f.cg[2], half[2] + f.hg[2]);
+    double D2 = (ex * ex + ey * ey) + ez * ez;
+    if (D2 >= rc2) return 0;
+    const double* m = com ? mc : cen;
+    ex = refit_axis_gap(m[0], f.cg[0], 0.0 + f.hg[0]);
+    ey = refit_axis_gap(m[1], f.cg[1], 0.0 + f.hg[1]);
+    ez = refit_axis_gap(m[2], f.cg[2], 0.0 + f.hg[2]);
+    double d2 = (ex * ex + ey * ey) + ez * ez;
+    if (side * side < th2 * d2) return 1;
+    return k.leaf ? 2 : 3;
+}
+
 // Items of one group pass through a 16-slot LDS buffer of the thread and go
 // to memory as aligned 64-byte chunks (the partial chunks at the two ends of
 // a group's items are written item by item), so that the item array is
@@ -131,13 +174,13 @@ struct ItemWriter {
 constexpr int64_t kSlot = 2048;
 constexpr int kListThreads = 64;   // one wave per block (128 and 256 measured slower)
 
-template <int G, bool WRITE, bool COM>
+template <int G, bool WRITE, bool COM, bool REFIT>
 __global__ __launch_bounds__(kListThreads) void k_lists(int64_t ng, const double* __restrict__ glo,
                                                const double* __restrict__ ghi, const int32_t* __restrict__ gcount,
                                                const uint4* __restrict__ pack, const NodeRange* __restrict__ rng,
                                                const double* __restrict__ nX, const double* __restrict__ nY,
-                                               const double* __restrict__ nZ,
-                                               int64_t nn, double rc2, double th2, int64_t* __restrict__ cnt,
+                                               const double* __restrict__ nZ, const double* __restrict__ clo,
+                                               const double* __restrict__ chi, int64_t nn, double rc2, double th2, int64_t* __restrict__ cnt,
                                                int64_t* __restrict__ icnt, unsigned long long* __restrict__ totals,
                                                const int64_t* __restrict__ ioff, int32_t* __restrict__ items) {
     static_assert(G * kLevels <= 64, "level masks must fit one word");
@@ -173,10 +216,19 @@ __global__ __launch_bounds__(kListThreads) void k_lists(int64_t ng, const double
                 mcen[1] = nY[i];
                 mcen[2] = nZ[i];
             }
+            double bl[3] = {0, 0, 0}, bh[3] = {0, 0, 0};
+            if (REFIT) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    bl[a] = clo[i * 3 + a];
+                    bh[a] = chi[i * 3 + a];
+                }
+            }
 #pragma unroll
             for (int q = 0; q < G; ++q) {
                 if (!((act >> q) & 1ull)) continue;
-                const int cls = classify(k, mcen, f[q], rc2, th2);
+                const int cls = REFIT ? classify_refit(k, bl, bh, mcen, COM, f[q], rc2, th2)
+                                      : classify(k, mcen, f[q], rc2, th2);
                 if (cls == 3) {
                     open |= 1ull << q;
                 } else if (cls == 1) {
@@ -325,16 +377,27 @@ void build_lists(const Tree& t, Lists& l, hipStream_t st) {
     const int B = kListThreads;
     constexpr int G = kGroupsPerThread;
     const int64_t nthreads = (ng + G - 1) / G;
-    if (l.mac == SRF_MAC_COM)
-        hipLaunchKernelGGL((k_lists<G, false, true>), dim3(grid_for(nthreads, B, 1 << 30)), dim3(B), 0, st, ng,
-                           t.glo.get(), t.ghi.get(), t.gcount.get(), t.pack.get(), t.range.get(), t.nX.get(),
-                           t.nY.get(), t.nZ.get(), t.n_nodes, rc2, th2, l.off.get(), icnt.get(), totals.get(),
-                           (const int64_t*)nullptr, slots.get());
-    else
-        hipLaunchKernelGGL((k_lists<G, false, false>), dim3(grid_for(nthreads, B, 1 << 30)), dim3(B), 0, st, ng,
-                           t.glo.get(), t.ghi.get(), t.gcount.get(), t.pack.get(), t.range.get(), t.nX.get(),
-                           t.nY.get(), t.nZ.get(), t.n_nodes, rc2, th2, l.off.get(), icnt.get(), totals.get(),
-                           (const int64_t*)nullptr, slots.get());
+    const dim3 grid(grid_for(nthreads, B, 1 << 30)), block(B);
+    const bool com = l.mac == SRF_MAC_COM;
+    // the walk for this tree: geometric or refitted cells, either criterion
+    auto walk = [&](auto kernel, int64_t* cnt, int64_t* ic, unsigned long long* tot, const int64_t* ioff,
+                    int32_t* out) {
+        hipLaunchKernelGGL(kernel, grid, block, 0, st, ng, t.glo.get(), t.ghi.get(), t.gcount.get(), t.pack.get(),
+                           t.range.get(), t.nX.get(), t.nY.get(), t.nZ.get(), t.clo.get(), t.chi.get(), t.n_nodes,
+                           rc2, th2, cnt, ic, tot, ioff, out);
+    };
+    auto walk_all = [&](auto write, int64_t* cnt, int64_t* ic, unsigned long long* tot, const int64_t* ioff,
+                        int32_t* out) {
+        constexpr bool W = decltype(write)::value;
+        if (t.refit) {
+            if (com) walk(k_lists<G, W, true, true>, cnt, ic, tot, ioff, out);
+            else walk(k_lists<G, W, false, true>, cnt, ic, tot, ioff, out);
+        } else {
+            if (com) walk(k_lists<G, W, true, false>, cnt, ic, tot, ioff, out);
+            else walk(k_lists<G, W, false, false>, cnt, ic, tot, ioff, out);
+        }
+    };
+    walk_all(std::false_type{}, l.off.get(), icnt.get(), totals.get(), (const int64_t*)nullptr, slots.get());
     SRF_HIP(hipGetLastError());
     exclusive_scan_i64(l.off.get(), ng, true, st);
     unsigned long long h[4];
@@ -361,16 +424,8 @@ void build_lists(const Tree& t, Lists& l, hipStream_t st) {
     SRF_HIP(hipMemcpyAsync(&n_items, icnt.get() + ng, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     SRF_HIP(hipStreamSynchronize(st));
     DevBuf<int32_t> items(n_items > 0 ? n_items : 1, st);
-    if (l.mac == SRF_MAC_COM)
-        hipLaunchKernelGGL((k_lists<G, true, true>), dim3(grid_for(nthreads, B, 1 << 30)), dim3(B), 0, st, ng,
-                           t.glo.get(), t.ghi.get(), t.gcount.get(), t.pack.get(), t.range.get(), t.nX.get(),
-                           t.nY.get(), t.nZ.get(), t.n_nodes, rc2, th2, (int64_t*)nullptr, (int64_t*)nullptr,
-                           (unsigned long long*)nullptr, (const int64_t*)icnt.get(), items.get());
-    else
-        hipLaunchKernelGGL((k_lists<G, true, false>), dim3(grid_for(nthreads, B, 1 << 30)), dim3(B), 0, st, ng,
-                           t.glo.get(), t.ghi.get(), t.gcount.get(), t.pack.get(), t.range.get(), t.nX.get(),
-                           t.nY.get(), t.nZ.get(), t.n_nodes, rc2, th2, (int64_t*)nullptr, (int64_t*)nullptr,
-                           (unsigned long long*)nullptr, (const int64_t*)icnt.get(), items.get());
+    walk_all(std::true_type{}, (int64_t*)nullptr, (int64_t*)nullptr, (unsigned long long*)nullptr,
+             (const int64_t*)icnt.get(), items.get());
     SRF_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_expand, dim3((unsigned)ng), dim3(64), 0, st, ng, (int64_t)0, (const int64_t*)nullptr,
                        icnt.get(), items.get(), t.range.get(), l.off.get(), l.ent.get());

@@ -331,7 +331,7 @@ __device__ __forceinline__ void force_group(const GroupArgs& ga, const Src& src,
     const double hy = (ga.ghi[g * 3 + 1] - ga.glo[g * 3 + 1]) * 0.5;
     const double hz = (ga.ghi[g * 3 + 2] - ga.glo[g * 3 + 2]) * 0.5;
     const int32_t me = first + il;
-    const T xi = (T)(src.px[me] - cx), yi = (T)(src.py[me] - cy), zi = (T)(src.pz[me] - cz);
+    const T xi = (T)image(src.px[me] - cx), yi = (T)image(src.py[me] - cy), zi = (T)image(src.pz[me] - cz);
     double sx = 0, sy = 0, sz = 0;
     const int64_t e0 = ga.off[g], e1 = ga.off[g + 1];
     for (int64_t tb = e0; tb < e1; tb += kTile) {
@@ -474,7 +474,7 @@ __device__ __forceinline__ void potential_group(const GroupArgs& ga, const Src& 
     const double hy = (ga.ghi[g * 3 + 1] - ga.glo[g * 3 + 1]) * 0.5;
     const double hz = (ga.ghi[g * 3 + 2] - ga.glo[g * 3 + 2]) * 0.5;
     const int32_t me = first + il;
-    const T xi = (T)(src.px[me] - cx), yi = (T)(src.py[me] - cy), zi = (T)(src.pz[me] - cz);
+    const T xi = (T)image(src.px[me] - cx), yi = (T)image(src.py[me] - cy), zi = (T)image(src.pz[me] - cz);
     double sum = 0.0;
     const int64_t e0 = ga.off[g], e1 = ga.off[g + 1];
     for (int64_t tb = e0; tb < e1; tb += kTile) {
@@ -713,9 +713,9 @@ __device__ __forceinline__ void adjoint_group(const GroupArgs& ga, const Src& sr
     for (int ib = 0; ib < NB; ++ib) {
         const int i = ib * kRow + ra;
         const int32_t me = first + (i < cnt ? i : 0);
-        tg.x[ib] = (T)(src.px[me] - cx);
-        tg.y[ib] = (T)(src.py[me] - cy);
-        tg.z[ib] = (T)(src.pz[me] - cz);
+        tg.x[ib] = (T)image(src.px[me] - cx);
+        tg.y[ib] = (T)image(src.py[me] - cy);
+        tg.z[ib] = (T)image(src.pz[me] - cz);
         const int64_t wi = (int64_t)ga.perm[me] * ws;
         const bool on = i < cnt;
         tg.wx[ib] = on ? (T)wx[wi] : T(0);
@@ -792,6 +792,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
 //   dL/dx_k += m_k SA(c0),   dL/dm_k += T(c0) + (x_k - X_c0) . SA(c0),
 // which equals sum_c [dL/dM_c + (x_k - X_c) . A_c] with every difference of
 // positions formed before it is multiplied (no cancellation of large terms).
+// Differences are taken to the nearest periodic image: a refitted cell's
+// particles, and its centre of mass, may lie across a face of the unit box
+// (the root, whose differences could reach half the box, is never a source).
 __global__ void k_node_chain(int64_t nn, const NodeRange* __restrict__ rng, const double* __restrict__ M,
                              const double* __restrict__ X, const double* __restrict__ Y, const double* __restrict__ Z,
                              const double4* __restrict__ gn, double* __restrict__ sax, double* __restrict__ say,
@@ -808,7 +811,7 @@ __global__ void k_node_chain(int64_t nn, const NodeRange* __restrict__ rng, cons
         ax += a0;
         ay += a1;
         az += a2;
-        b += q.w + ((x0 - X[p]) * a0 + (y0 - Y[p]) * a1 + (z0 - Z[p]) * a2);
+        b += q.w + (image(x0 - X[p]) * a0 + image(y0 - Y[p]) * a1 + image(z0 - Z[p]) * a2);
         p = rng[p].parent;
     }
     sax[c] = ax;
@@ -835,7 +838,8 @@ __global__ void k_adj_final(int64_t n, double G, const int32_t* __restrict__ per
     gx[i * gs] = G * (o.gix[s] + gj.x + m * a0);
     gy[i * gs] = G * (o.giy[s] + gj.y + m * a1);
     gz[i * gs] = G * (o.giz[s] + gj.z + m * a2);
-    gm[i * gms] = G * (gj.w + b + ((px[s] - nX[lf]) * a0 + (py[s] - nY[lf]) * a1 + (pz[s] - nZ[lf]) * a2));
+    gm[i * gms] = G * (gj.w + b + (image(px[s] - nX[lf]) * a0 + image(py[s] - nY[lf]) * a1 +
+                                   image(pz[s] - nZ[lf]) * a2));
 }
 
 GroupArgs group_args(const Tree& t, const Lists& l) {

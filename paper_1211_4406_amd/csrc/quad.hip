@@ -135,8 +135,9 @@ __global__ void k_mark_cells(int64_t n_entries, const int32_t* __restrict__ ent,
 // the marked cells.  One wave takes 64 consecutive cells: a cell of at most
 // kSmallCell particles is summed by its own lane; each larger one is summed
 // by the whole wave (lanes stride over its particles, partial sums combined
-// in a fixed order).  Deterministic either way.  A cell never straddles the
-// periodic boundary, so no image is taken.
+// in a fixed order).  Deterministic either way.  Offsets x_k - X_c are taken
+// to the nearest periodic image (a refitted cell may straddle a face of the
+// unit box; the root, never a source, is not computed).
 constexpr int32_t kSmallCell = 64;
 
 __device__ __forceinline__ void add_second(double (&a)[6], double m, double dx, double dy, double dz) {
@@ -169,7 +170,7 @@ __global__ __launch_bounds__(64) void k_second_moments(int64_t nn, const NodeRan
     // small cells: one lane each
     if (on && rg.count <= kSmallCell) {
         double a[6] = {0, 0, 0, 0, 0, 0};
-        for (int32_t k = rg.first; k < rg.first + rg.count; ++k) add_second(a, pm[k], px[k] - X, py[k] - Y, pz[k] - Z);
+        for (int32_t k = rg.first; k < rg.first + rg.count; ++k) add_second(a, pm[k], image(px[k] - X), image(py[k] - Y), image(pz[k] - Z));
 #pragma unroll
         for (int q = 0; q < 6; ++q) S[c * 6 + q] = a[q];
     }
@@ -181,7 +182,7 @@ __global__ __launch_bounds__(64) void k_second_moments(int64_t nn, const NodeRan
         const int32_t f = __shfl(rg.first, l, 64), n = __shfl(rg.count, l, 64);
         const double bx = __shfl(X, l, 64), by = __shfl(Y, l, 64), bz = __shfl(Z, l, 64);
         double a[6] = {0, 0, 0, 0, 0, 0};
-        for (int32_t k = f + lane; k < f + n; k += 64) add_second(a, pm[k], px[k] - bx, py[k] - by, pz[k] - bz);
+        for (int32_t k = f + lane; k < f + n; k += 64) add_second(a, pm[k], image(px[k] - bx), image(py[k] - by), image(pz[k] - bz));
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
 #pragma unroll
@@ -264,7 +265,7 @@ __global__ __launch_bounds__(64) void k_quadrupole(const int32_t* __restrict__ g
     const double hy = (ghi[g * 3 + 1] - glo[g * 3 + 1]) * 0.5;
     const double hz = (ghi[g * 3 + 2] - glo[g * 3 + 2]) * 0.5;
     const int32_t me = first + (lane < cnt ? lane : 0);
-    const T xi = (T)(px[me] - cx), yi = (T)(py[me] - cy), zi = (T)(pz[me] - cz);
+    const T xi = (T)image(px[me] - cx), yi = (T)image(py[me] - cy), zi = (T)image(pz[me] - cz);
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const QCoef<T> cq = q_pinned(c);
     double sx = 0, sy = 0, sz = 0;

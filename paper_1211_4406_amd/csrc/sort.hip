@@ -262,7 +262,37 @@ __global__ void k_gather(int64_t n, const int32_t* __restrict__ perm, const doub
     pm[s] = m[i * ms];
 }
 
+// The same gather for a tree reused at new positions, with the input checks
+// of k_keys; without masses (m == nullptr) only the positions are gathered.
+__global__ void k_gather_checked(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ x,
+                                 const double* __restrict__ y, const double* __restrict__ z, int64_t ps,
+                                 const double* __restrict__ m, int64_t ms, double* __restrict__ px,
+                                 double* __restrict__ py, double* __restrict__ pz, double* __restrict__ pm,
+                                 int32_t* __restrict__ flag) {
+    int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    int64_t i = perm[s];
+    const double a = x[i * ps], b = y[i * ps], c = z[i * ps];
+    int bad = (isfinite(a) && isfinite(b) && isfinite(c)) ? 0 : 1;
+    px[s] = wrap01(a);
+    py[s] = wrap01(b);
+    pz[s] = wrap01(c);
+    if (m) {
+        const double mm = m[i * ms];
+        if (!(isfinite(mm) && mm > 0.0)) bad |= 2;
+        pm[s] = mm;
+    }
+    if (bad) atomicOr(flag, bad);
+}
+
 }  // namespace
+
+void gather_refit(const Tree& t, const double* x, const double* y, const double* z, int64_t ps, const double* m,
+                  int64_t ms, int32_t* d_flag, double* px, double* py, double* pz, double* pm, hipStream_t st) {
+    hipLaunchKernelGGL(k_gather_checked, dim3(grid_for(t.n, 256, 1 << 30)), dim3(256), 0, st, t.n, t.perm.get(), x,
+                       y, z, ps, m, ms, px, py, pz, pm, d_flag);
+    SRF_HIP(hipGetLastError());
+}
 
 void build_sorted(Tree& t, const double* x, const double* y, const double* z, int64_t ps, const double* m,
                   int64_t ms, int32_t* d_flag, hipStream_t st) {

@@ -437,6 +437,105 @@ __global__ __launch_bounds__(256) void k_moments(int32_t lo, int32_t hi, int32_t
     }
 }
 
+// A refitted tree (the structure held, the particles moved), one level,
+// deepest first, 4 lanes per cell.  A leaf takes its particles at their
+// periodic images nearest its dyadic centre; an inner cell takes its
+// children's sums and boxes, each child moved as a whole by the whole
+// number of box lengths that brings its box centre nearest the cell's
+// centre.  The box is the min and max of those images per axis; the sums
+// give the monopole.  Slot sums and boxes (sbox: lo xyz, hi xyz per slot)
+// feed the next level up; monopoles and boxes go to the preorder records.
+__global__ __launch_bounds__(256) void k_refit_level(int32_t lo, int32_t hi, int32_t next_hi, int64_t n,
+                                                     const int32_t* __restrict__ sfirst,
+                                                     const int32_t* __restrict__ spre,
+                                                     const int32_t* __restrict__ schild,
+                                                     const NodeGeo* __restrict__ geo,
+                                                     const NodeRange* __restrict__ rng, const double* __restrict__ px,
+                                                     const double* __restrict__ py, const double* __restrict__ pz,
+                                                     const double* __restrict__ pm, double* __restrict__ sM,
+                                                     double* __restrict__ sX, double* __restrict__ sY,
+                                                     double* __restrict__ sZ, double* __restrict__ sbox,
+                                                     double* __restrict__ oM, double* __restrict__ oX,
+                                                     double* __restrict__ oY, double* __restrict__ oZ,
+                                                     double* __restrict__ clo, double* __restrict__ chi) {
+    const int64_t i = lo + blockIdx.x * (int64_t)(256 / kMomLanes) + threadIdx.x / kMomLanes;
+    const int j = threadIdx.x & (kMomLanes - 1);
+    const bool on = i < hi;
+    const int64_t c = on ? i : lo;
+    const int32_t f = sfirst[c], pre = spre[c], ch = schild[c];
+    const NodeGeo g = geo[pre];
+    const int lv = (int)(g.level_leaf & 0xffu);
+    const double cref[3] = {ldexp((double)g.ix + 0.5, -lv), ldexp((double)g.iy + 0.5, -lv),
+                            ldexp((double)g.iz + 0.5, -lv)};
+    double sm = 0, sv[3] = {0, 0, 0}, bl[3], bh[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        bl[a] = INFINITY;
+        bh[a] = -INFINITY;
+    }
+    if (on) {
+        if (ch < 0) {
+            const int64_t e = f + (int64_t)rng[pre].count;
+            for (int64_t s = f + j; s < e; s += kMomLanes) {
+                const double mm = pm[s];
+                const double u[3] = {px[s], py[s], pz[s]};
+                sm += mm;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const double v = u[a] - rint(u[a] - cref[a]);
+                    sv[a] += mm * v;
+                    bl[a] = v < bl[a] ? v : bl[a];
+                    bh[a] = v > bh[a] ? v : bh[a];
+                }
+            }
+        } else {
+            const int64_t lim = c + 1 < hi ? sfirst[c + 1] : n;
+            for (int64_t q = ch + j; q < next_hi && sfirst[q] < lim; q += kMomLanes) {
+                const double mq = sM[q];
+                const double sq[3] = {sX[q], sY[q], sZ[q]};
+                sm += mq;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const double l = sbox[q * 6 + a], h = sbox[q * 6 + 3 + a];
+                    const double sh = rint((l + h) * 0.5 - cref[a]);
+                    const double vl = l - sh, vh = h - sh;
+                    bl[a] = vl < bl[a] ? vl : bl[a];
+                    bh[a] = vh > bh[a] ? vh : bh[a];
+                    sv[a] += sq[a] - sh * mq;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int o = kMomLanes / 2; o >= 1; o >>= 1) {
+        sm += __shfl_xor(sm, o, kMomLanes);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            sv[a] += __shfl_xor(sv[a], o, kMomLanes);
+            const double l = __shfl_xor(bl[a], o, kMomLanes), h = __shfl_xor(bh[a], o, kMomLanes);
+            bl[a] = l < bl[a] ? l : bl[a];
+            bh[a] = h > bh[a] ? h : bh[a];
+        }
+    }
+    if (on && j == 0) {
+        sM[c] = sm;
+        sX[c] = sv[0];
+        sY[c] = sv[1];
+        sZ[c] = sv[2];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            sbox[c * 6 + a] = bl[a];
+            sbox[c * 6 + 3 + a] = bh[a];
+            clo[(int64_t)pre * 3 + a] = bl[a];
+            chi[(int64_t)pre * 3 + a] = bh[a];
+        }
+        oM[pre] = sm;
+        oX[pre] = sv[0] / sm;
+        oY[pre] = sv[1] / sm;
+        oZ[pre] = sv[2] / sm;
+    }
+}
+
 // The packed walk record of each cell (preorder).
 __global__ void k_pack(int64_t nn, const NodeGeo* __restrict__ geo, const NodeRange* __restrict__ rng,
                        uint4* __restrict__ pack) {
@@ -469,9 +568,12 @@ __global__ void k_group_count(int64_t ng, int64_t n, const int32_t* __restrict__
 }
 
 // Tight boxes: 16 lanes per group, lane j taking the group's particles
-// j, j + 16, ... (min and max are exact in any order).
+// j, j + 16, ... (min and max are exact in any order).  In a refitted tree
+// (REFIT) each position is first moved to its periodic image nearest the
+// group's first particle.
 constexpr int kBoxLanes = 16;
 
+template <bool REFIT>
 __global__ __launch_bounds__(256) void k_group_bbox(int64_t ng, const int32_t* __restrict__ gfirst,
                                                     const int32_t* __restrict__ gcount, const double* __restrict__ px,
                                                     const double* __restrict__ py, const double* __restrict__ pz,
@@ -486,10 +588,12 @@ __global__ __launch_bounds__(256) void k_group_bbox(int64_t ng, const int32_t* _
     }
     if (g < ng) {
         const int32_t f = gfirst[g], cnt = gcount[g];
+        const double r[3] = {px[f], py[f], pz[f]};
         for (int32_t q = j; q < cnt; q += kBoxLanes) {
-            const double v[3] = {px[f + q], py[f + q], pz[f + q]};
+            double v[3] = {px[f + q], py[f + q], pz[f + q]};
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
+                if (REFIT) v[k] = v[k] - rint(v[k] - r[k]);
                 a[k] = v[k] < a[k] ? v[k] : a[k];
                 b[k] = v[k] > b[k] ? v[k] : b[k];
             }
@@ -569,18 +673,25 @@ void build_cells_and_groups(Tree& t, int32_t* d_flag, hipStream_t st) {
     t.nY.alloc(nn, st);
     t.nZ.alloc(nn, st);
     t.leaf_of.alloc(n, st);
-    DevBuf<int32_t> pfirst(nn, st), sfirst(nn, st), spre(nn, st), schild(nn, st), scount(nn, st);
+    t.sfirst.alloc(nn, st);
+    t.spre.alloc(nn, st);
+    t.schild.alloc(nn, st);
+    for (int L = 0; L <= kLevels; ++L) t.level_off[L] = base.off[L];
+    int32_t* sfirst = t.sfirst.get();
+    int32_t* spre = t.spre.get();
+    int32_t* schild = t.schild.get();
+    DevBuf<int32_t> pfirst(nn, st), scount(nn, st);
     DevBuf<double> sM(nn, st), sX(nn, st), sY(nn, st), sZ(nn, st);
     hipLaunchKernelGGL(k_cells, dim3((unsigned)nblocks), dim3(kLvThreads), 0, st, n, nblocks, t.keys.get(),
                        delta.get(), leaflv.get(), start.get(), base, blk.get(), t.geo.get(), pfirst.get(),
-                       t.prefix.get(), sfirst.get(), spre.get(), schild.get());
+                       t.prefix.get(), sfirst, spre, schild);
     SRF_HIP(hipGetLastError());
     for (int L = max_level; L >= 0; --L) {
         const int32_t lo = base.off[L], hi = base.off[L + 1];
         if (hi <= lo) continue;
         const int32_t next_hi = L < kMaxLevel ? base.off[L + 2] : hi;
         hipLaunchKernelGGL(k_moments, dim3(grid_for(hi - lo, 256 / kMomLanes, 1 << 30)), dim3(256), 0, st, lo, hi,
-                           next_hi, n, nn, sfirst.get(), spre.get(), schild.get(), pfirst.get(), start.get(),
+                           next_hi, n, nn, sfirst, spre, schild, pfirst.get(), start.get(),
                            t.px.get(), t.py.get(), t.pz.get(), t.pm.get(), scount.get(), sM.get(), sX.get(), sY.get(),
                            sZ.get(), t.range.get(), t.nM.get(), t.nX.get(), t.nY.get(), t.nZ.get(), t.leaf_of.get());
         SRF_HIP(hipGetLastError());
@@ -599,9 +710,35 @@ void build_cells_and_groups(Tree& t, int32_t* d_flag, hipStream_t st) {
     hipLaunchKernelGGL(k_group_count, dim3(grid_for(ng, B, 1 << 30)), dim3(B), 0, st, ng, n, t.gfirst.get(),
                        t.gcount.get());
     SRF_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_group_bbox, dim3(grid_for(ng, 256 / kBoxLanes, 1 << 30)), dim3(256), 0, st, ng, t.gfirst.get(),
+    hipLaunchKernelGGL(k_group_bbox<false>, dim3(grid_for(ng, 256 / kBoxLanes, 1 << 30)), dim3(256), 0, st, ng,
+                       t.gfirst.get(),
                        t.gcount.get(), t.px.get(), t.py.get(), t.pz.get(), t.glo.get(), t.ghi.get());
     SRF_HIP(hipGetLastError());
+}
+
+void refit_cells_and_groups(Tree& t, hipStream_t st) {
+    const int64_t n = t.n, nn = t.n_nodes, ng = t.n_groups;
+    if (!t.clo.get()) {
+        t.clo.alloc(nn * 3, st);
+        t.chi.alloc(nn * 3, st);
+    }
+    DevBuf<double> sM(nn, st), sX(nn, st), sY(nn, st), sZ(nn, st), sbox(nn * 6, st);
+    for (int L = t.max_level; L >= 0; --L) {
+        const int32_t lo = t.level_off[L], hi = t.level_off[L + 1];
+        if (hi <= lo) continue;
+        const int32_t next_hi = L < kMaxLevel ? t.level_off[L + 2] : hi;
+        hipLaunchKernelGGL(k_refit_level, dim3(grid_for(hi - lo, 256 / kMomLanes, 1 << 30)), dim3(256), 0, st, lo,
+                           hi, next_hi, n, t.sfirst.get(), t.spre.get(), t.schild.get(), t.geo.get(), t.range.get(),
+                           t.px.get(), t.py.get(), t.pz.get(), t.pm.get(), sM.get(), sX.get(), sY.get(), sZ.get(),
+                           sbox.get(), t.nM.get(), t.nX.get(), t.nY.get(), t.nZ.get(), t.clo.get(), t.chi.get());
+        SRF_HIP(hipGetLastError());
+    }
+    if (ng > 0) {
+        hipLaunchKernelGGL(k_group_bbox<true>, dim3(grid_for(ng, 256 / kBoxLanes, 1 << 30)), dim3(256), 0, st, ng,
+                           t.gfirst.get(), t.gcount.get(), t.px.get(), t.py.get(), t.pz.get(), t.glo.get(),
+                           t.ghi.get());
+        SRF_HIP(hipGetLastError());
+    }
 }
 
 }  // namespace srf

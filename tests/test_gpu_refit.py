@@ -1,0 +1,218 @@
+"""GPU parity of the refitted tree (tree reuse within a step) against the
+oracle's refitted tree (``OracleTree.refitted``).
+
+A tree is built at one set of positions and refitted through the C ABI to
+moved positions (a random drift with some particles pushed across the
+periodic faces, and a slab of particles straddling the face x = 0 moved
+across it).  Bit-exact: the sort order and cells kept from the build, the
+wrapped positions, every cell box and group box, and the lists (both
+opening criteria; with the centre-of-mass criterion the oracle decides on
+the GPU's centres of mass).  Element-wise bounds (tests/_parity.py): the
+moments, the FP32 and FP64 forces and the gradient.  theta = 0 gives the
+brute-force sum at the new positions.  Lists of the old positions are
+refused after a refit, a refit with a non-finite position leaves the tree
+as it was, and the integrator that reuses its tree follows the oracle
+trajectory at theta = 0."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1211_4406_amd as srf
+import synth
+from _parity import U32, U64, check, constant, max_list
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _drift(ps, scale, seed):
+    rng = np.random.default_rng(seed)
+    pos = ps.positions()
+    new = pos + scale * (2 * rng.random(pos.shape) - 1)
+    k = rng.choice(ps.n, ps.n // 50, replace=False)
+    new[k, 0] = np.where(pos[k, 0] < 0.5, pos[k, 0] - 0.7 * scale, pos[k, 0] + 0.7 * scale)
+    # unwrapped on purpose: the library wraps
+    return new
+
+
+def _slab():
+    rng = np.random.default_rng(5)
+    n = 4000
+    x = np.concatenate([rng.random(n // 2) * 0.08, 0.92 + rng.random(n // 2) * 0.08])
+    y, z = 0.3 + 0.4 * rng.random(n), 0.3 + 0.4 * rng.random(n)
+    ps = synth.ParticleSet(x, y, z, np.full(n, 1.0 / n), synth.Params(1.0, 0.06, 3e-4, 1.0, 64, 16))
+    return ps, ps.positions() + np.array([-0.0123, 0.0071, 0.0])
+
+
+def _cases():
+    c = synth.small_clustered(20000, 101, r_cut=0.1, eps=2e-4, theta=0.5, per_halo=1000)
+    u = synth.small_uniform(4096, 7, r_cut=0.1, eps=1e-3, theta=0.5)
+    s, s_new = _slab()
+    return {
+        "clustered-20000": (c, _drift(c, 3e-3, 1)),
+        "uniform-4096": (u, _drift(u, 8e-3, 2)),
+        "slab-4000": (s, s_new),
+    }
+
+
+def _refit(ps, new, params, precision):
+    p = srf.Params.of(params, precision)
+    x0 = torch.tensor(ps.positions(), dtype=torch.float64, device="cuda")
+    m = torch.tensor(ps.m, dtype=torch.float64, device="cuda")
+    tree = srf.tree_build(x0, m, p)
+    x1 = torch.tensor(new, dtype=torch.float64, device="cuda")
+    srf.tree_refit(tree, x1)
+    lists = srf.make_lists(tree, p)
+    return p, tree, lists, x1, m
+
+
+def _oracle(ps, new, params):
+    ot = oracle.OracleTree(ps.x, ps.y, ps.z, ps.m, params)
+    return ot, ot.refitted(new[:, 0], new[:, 1], new[:, 2])
+
+
+@pytest.mark.parametrize("name", ["clustered-20000", "uniform-4096", "slab-4000"])
+@pytest.mark.parametrize("theta", [0.5, 1.0])
+def test_refit_structure_boxes_lists_and_force(name, theta):
+    ps, new = _cases()[name]
+    params = synth.Params(1.0, ps.params.r_cut, ps.params.eps, theta, 64, 16)
+    say(f"[gpu] refit {name} theta={theta} n={ps.n}")
+    ot, rt = _oracle(ps, new, params)
+    p, tree, lists, _, _ = _refit(ps, new, params, srf.FP32_REL)
+    ex = tree.export()
+    assert np.array_equal(ex["perm"], ot.perm) and np.array_equal(ex["keys"], ot.keys)
+    for k, v in (("level", ot.tree.level), ("prefix", ot.tree.prefix), ("first", ot.tree.first),
+                 ("count", ot.tree.count), ("gfirst", ot.gfirst), ("gcount", ot.gcount)):
+        assert np.array_equal(ex[k], v), k
+    xs, ms = tree.sorted_particles()
+    assert np.array_equal(xs, np.stack([rt.ux, rt.uy, rt.uz], axis=1)), "wrapped positions"
+    assert np.array_equal(ms, rt.m)
+    assert np.array_equal(ex["lo"], rt.lo) and np.array_equal(ex["hi"], rt.hi), "group boxes"
+    clo, chi = tree.cell_boxes()
+    assert np.array_equal(clo, rt.clo) and np.array_equal(chi, rt.chi), "cell boxes"
+    M, X = tree.moments()
+    below = ot.tree.level >= 1   # the root is never a source
+    assert np.max(np.abs(M - rt.M) / rt.M / ot.tree.count) < 1e-15
+    d = np.abs(X - rt.X)[below]
+    assert np.all(d <= 1e-15 + 2.3e-16 * ot.tree.count[below, None]), float(d.max())
+    L = lists.export()
+    for k in ("poff", "pidx", "noff", "nidx"):
+        assert np.array_equal(L[k], getattr(rt.lists, k)), k
+    assert lists.info()["interactions"] == rt.interactions()
+    say(f"    {rt.lists.pidx.size} particle and {rt.lists.nidx.size} cell entries "
+        f"(fresh tree at the old positions: {ot.lists.pidx.size}, {ot.lists.nidx.size})")
+    ref = rt.force()
+    a32 = srf.short_range_force(tree, lists, p).cpu().numpy()
+    check(a32, ref, rt.force_bound(U32), constant("force", False, max_list(rt)), "fp32 force")
+    p64 = srf.Params.of(params, srf.FP64)
+    a64 = srf.short_range_force(tree, lists, p64).cpu().numpy()
+    check(a64, ref, rt.force_bound(U64), constant("force", True, max_list(rt)), "fp64 force")
+
+
+@pytest.mark.parametrize("name", ["clustered-20000", "slab-4000"])
+def test_refit_lists_with_the_centre_of_mass_criterion(name):
+    ps, new = _cases()[name]
+    params = synth.Params(1.0, ps.params.r_cut, ps.params.eps, 0.7, 64, 16)
+    ot, rt = _oracle(ps, new, params)
+    p = srf.Params.of(params, srf.FP32_REL)
+    p = srf.Params(p.G, p.r_cut, p.eps, p.theta, p.n_group, p.n_leaf, p.precision, 0, srf.MAC_COM)
+    _, tree, lists, _, _ = _refit(ps, new, p, srf.FP32_REL)
+    M, X = tree.moments()
+    clo, chi = tree.cell_boxes()
+    ref = oracle.make_lists(ot.tree, rt.lo, rt.hi, params.r_cut, params.theta, com=X, boxes=(clo, chi))
+    L = lists.export()
+    for k in ("poff", "pidx", "noff", "nidx"):
+        assert np.array_equal(L[k], getattr(ref, k)), k
+    say(f"[gpu] refit COM criterion {name}: {ref.nidx.size} cell entries")
+    assert ref.nidx.size > 0
+
+
+@pytest.mark.parametrize("name", ["clustered-20000", "slab-4000"])
+def test_refit_adjoint(name):
+    ps, new = _cases()[name]
+    params = synth.Params(1.0, ps.params.r_cut, ps.params.eps, 0.7, 64, 16)
+    ot, rt = _oracle(ps, new, params)
+    w = synth.loss_weights(ps.n, 13)
+    rx, rm = rt.adjoint(w)
+    wt = torch.tensor(w, dtype=torch.float64, device="cuda")
+    for precision, fp64 in ((srf.FP32_REL, False), (srf.FP64, True)):
+        p, tree, lists, _, _ = _refit(ps, new, params, precision)
+        gx, gm = srf.short_range_adjoint(tree, lists, p, wt)
+        Ex, Em = rt.adjoint_bound(w, U64 if fp64 else U32)
+        C = constant("adjoint", fp64, max_list(rt))
+        tag = "fp64" if fp64 else "fp32"
+        check(gx.cpu().numpy(), rx, Ex, C, f"refit {name} {tag} dL/dx")
+        check(gm.cpu().numpy(), rm, Em, C, f"refit {name} {tag} dL/dm")
+
+
+@pytest.mark.parametrize("name", ["uniform-4096", "slab-4000"])
+def test_refit_theta_zero_is_the_brute_force_sum(name):
+    ps, new = _cases()[name]
+    params = synth.Params(1.0, ps.params.r_cut, ps.params.eps, 0.0, 64, 16)
+    ot, rt = _oracle(ps, new, params)
+    p, tree, lists, _, _ = _refit(ps, new, params, srf.FP64)
+    assert lists.info()["n_node_entries"] == 0
+    a = srf.short_range_force(tree, lists, p).cpu().numpy()
+    w = np.mod(new, 1.0)
+    bf = oracle.brute_force(w[:, 0], w[:, 1], w[:, 2], ps.m, 1.0, params.r_cut, params.eps, method="n2")
+    check(a, bf, rt.force_bound(U64), constant("force", True, max_list(rt)), "theta=0 refit vs brute force")
+
+
+def test_refit_quadrupole():
+    ps, new = _cases()["slab-4000"]
+    params = synth.Params(1.0, ps.params.r_cut, ps.params.eps, 1.0, 64, 16)
+    ot, rt = _oracle(ps, new, params)
+    p, tree, lists, _, _ = _refit(ps, new, params, srf.FP64)
+    a = srf.short_range_force(tree, lists, p, quadrupole=True).cpu().numpy()
+    ref = rt.force_quadrupole()
+    mono = rt.force()
+    # the quadrupole term itself agrees to FP64 rounding of the second
+    # moments; the monopole part within its bound
+    dq = np.linalg.norm((a - mono) - (ref - mono), axis=1)
+    scale = np.linalg.norm(ref - mono, axis=1).max()
+    say(f"[gpu] refit quadrupole: max |dq| / max |q| = {dq.max() / scale:.3e}")
+    check(a, ref, rt.force_bound(U64) + 1e-12 * scale, constant("force", True, max_list(rt)), "refit quadrupole")
+
+
+def test_refit_refuses_stale_lists_and_keeps_the_tree_on_bad_input():
+    ps, new = _cases()["uniform-4096"]
+    params = srf.Params.of(ps.params, srf.FP64)
+    x0 = torch.tensor(ps.positions(), dtype=torch.float64, device="cuda")
+    m = torch.tensor(ps.m, dtype=torch.float64, device="cuda")
+    tree = srf.tree_build(x0, m, params)
+    with pytest.raises(srf.SrfError) as e:
+        tree.cell_boxes()
+    assert e.value.status == -1
+    lists = srf.make_lists(tree, params)
+    srf.tree_refit(tree, torch.tensor(new, dtype=torch.float64, device="cuda"))
+    with pytest.raises(srf.SrfError) as e:
+        srf.short_range_force(tree, lists, params)
+    assert e.value.status == -5
+    lists = srf.make_lists(tree, params)
+    a = srf.short_range_force(tree, lists, params).cpu().numpy()
+    bad = torch.tensor(new, dtype=torch.float64, device="cuda")
+    bad[17, 1] = float("nan")
+    with pytest.raises(srf.SrfError) as e:
+        srf.tree_refit(tree, bad)
+    assert e.value.status == -2
+    badm = m.clone()
+    badm[3] = -1.0
+    with pytest.raises(srf.SrfError) as e:
+        srf.tree_refit(tree, torch.tensor(new, dtype=torch.float64, device="cuda"), badm)
+    assert e.value.status == -2
+    # the failed refits left the tree (and its lists) as they were
+    b = srf.short_range_force(tree, lists, params).cpu().numpy()
+    assert np.array_equal(a, b)
+    # a refit to the same positions with new masses changes only the masses
+    m2 = m * 2.0
+    srf.tree_refit(tree, torch.tensor(new, dtype=torch.float64, device="cuda"), m2)
+    lists = srf.make_lists(tree, params)
+    c = srf.short_range_force(tree, lists, params).cpu().numpy()
+    assert np.allclose(c, 2.0 * a, rtol=1e-13, atol=1e-13 * np.abs(a).max())
