@@ -385,6 +385,17 @@ class OracleTree:
         r._S = None
         return r
 
+    def refit_qboxes(self):
+        """(qlo, qhi, bounded) of a refitted tree: each cell's box rounded
+        outward to multiples of 2^-(level+10), as the list decisions use it;
+        bounded is False where a bound lies beyond 32767 such steps from the
+        cell's centre (the cell is then never pruned or accepted)."""
+        nn = self.tree.size
+        qlo, qhi, ok = np.empty((nn, 3)), np.empty((nn, 3)), np.empty(nn, np.uint8)
+        lib().or_refit_qboxes(_i64(nn), _ptr(self.tree.level), _ptr(self.tree.prefix), _ptr(self.clo),
+                              _ptr(self.chi), _ptr(qlo), _ptr(qhi), _ptr(ok))
+        return qlo, qhi, ok.astype(bool)
+
     def interactions(self) -> int:
         """I = sum over groups of N_i * N_j (the paper's count, Table I)."""
         nj = np.diff(self.lists.poff) + np.diff(self.lists.noff)

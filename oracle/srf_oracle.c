@@ -741,7 +741,8 @@ void or_refit_group_bbox(int64_t ng, const int64_t* gfirst, const int64_t* gcoun
 }
 
 /* A refitted tree (reused after its particles moved) measures each cell by
- * the tight box [lo, hi] of its particles instead of its dyadic box: per
+ * the box [lo, hi] of its particles (rounded outward, refit_qbox) instead of
+ * its dyadic box: per
  * axis t = |cen_c - cg| taken to the nearest image (t -= rint(t), since the
  * boxes of a refitted tree may reach past the unit box), gap r = t - (half
  * + h_g), e = max(0, r), d^2 = (e_x e_x + e_y e_y) + e_z e_z; prune iff
@@ -762,6 +763,38 @@ static double refit_gap2(const double cen[3], const double half[3], const double
     return (e[0] * e[0] + e[1] * e[1]) + e[2] * e[2];
 }
 
+/* The box a refitted cell is measured by in the list decisions: its
+ * particles' box [lo, hi] with every bound rounded outward to a multiple of
+ * q = 2^-(level + 10) (1/1024 of the cell's side), so that the bounds are
+ * stored exactly as 16-bit multiples of q from the cell's dyadic centre.  A
+ * bound more than 32767 q from the centre cannot be stored: the cell is then
+ * unbounded -- never pruned, never accepted -- and the function returns 0. */
+static int refit_qbox(int level, uint64_t prefix, const double lo[3], const double hi[3], double ql[3],
+                      double qh[3]) {
+    int64_t ic[3];
+    cell_ints(level, prefix, &ic[0], &ic[1], &ic[2]);
+    int e = level + 10;
+    for (int a = 0; a < 3; ++a) {
+        int64_t kc = ic[a] * 1024 + 512;                 /* the centre in units of q */
+        double kl = floor(ldexp(lo[a], e)), kh = ceil(ldexp(hi[a], e));
+        if (kl - (double)kc < -32767.0 || kh - (double)kc > 32767.0) return 0;
+        ql[a] = ldexp(kl, -e);
+        qh[a] = ldexp(kh, -e);
+    }
+    return 1;
+}
+
+/* refit_qbox for every cell (for the tests): bounded[c] = 0 marks an
+ * unbounded cell, whose qlo/qhi are then left at its box. */
+void or_refit_qboxes(int64_t nn, const int32_t* level, const uint64_t* prefix, const double* lo, const double* hi,
+                     double* qlo, double* qhi, uint8_t* bounded) {
+    for (int64_t c = 0; c < nn; ++c) {
+        bounded[c] = (uint8_t)refit_qbox(level[c], prefix[c], lo + 3 * c, hi + 3 * c, qlo + 3 * c, qhi + 3 * c);
+        if (!bounded[c])
+            for (int a = 0; a < 3; ++a) { qlo[3 * c + a] = lo[3 * c + a]; qhi[3 * c + a] = hi[3 * c + a]; }
+    }
+}
+
 typedef struct {
     const int32_t* level; const uint64_t* prefix; const int64_t* first; const int64_t* count;
     const int64_t* child; const uint8_t* leaf;
@@ -777,20 +810,23 @@ static void list_rec(list_ctx* c, int64_t node) {
     double cen[3], side;
     int accept;
     if (c->clo) {
-        double half[3], zero[3] = {0.0, 0.0, 0.0}, hmax = 0.0;
-        for (int a = 0; a < 3; ++a) {
-            double l = c->clo[3 * node + a], h = c->chi[3 * node + a];
-            cen[a] = (l + h) * 0.5;
-            half[a] = (h - l) * 0.5;
-            if (half[a] > hmax) hmax = half[a];
+        double half[3], zero[3] = {0.0, 0.0, 0.0}, hmax = 0.0, ql[3], qh[3];
+        if (refit_qbox(c->level[node], c->prefix[node], c->clo + 3 * node, c->chi + 3 * node, ql, qh)) {
+            for (int a = 0; a < 3; ++a) {
+                cen[a] = (ql[a] + qh[a]) * 0.5;
+                half[a] = (qh[a] - ql[a]) * 0.5;
+                if (half[a] > hmax) hmax = half[a];
+            }
+            side = hmax + hmax;
+            double dyadic = ldexp(1.0, -c->level[node]);
+            if (dyadic > side) side = dyadic;
+            if (refit_gap2(cen, half, c->cg, c->hg) >= c->rc * c->rc) return;
+            double mac_cen[3] = {cen[0], cen[1], cen[2]};
+            if (c->X) { mac_cen[0] = c->X[node]; mac_cen[1] = c->Y[node]; mac_cen[2] = c->Z[node]; }
+            accept = side * side < (c->theta * c->theta) * refit_gap2(mac_cen, zero, c->cg, c->hg);
+        } else {
+            accept = 0;
         }
-        side = hmax + hmax;
-        double dyadic = ldexp(1.0, -c->level[node]);
-        if (dyadic > side) side = dyadic;
-        if (refit_gap2(cen, half, c->cg, c->hg) >= c->rc * c->rc) return;
-        double mac_cen[3] = {cen[0], cen[1], cen[2]};
-        if (c->X) { mac_cen[0] = c->X[node]; mac_cen[1] = c->Y[node]; mac_cen[2] = c->Z[node]; }
-        accept = side * side < (c->theta * c->theta) * refit_gap2(mac_cen, zero, c->cg, c->hg);
     } else {
         cell_geom(c->level[node], c->prefix[node], cen, &side);
         if (prune_cell(cen, side, c->cg, c->hg, c->rc)) return;

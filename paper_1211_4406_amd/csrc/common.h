@@ -79,6 +79,18 @@ struct __align__(16) NodeRange {
 //   z = iz | ((skip >> 22) & 0x3ff) << 21,
 //   w = level | leaf << 5 | min(count, kPackCountMax) << 6.
 constexpr uint32_t kPackCountMax = 0x3ffffffu;
+// A cell of a refitted tree for the list traversal, 32 bytes: the packed
+// record and its box rounded outward to multiples of q = 2^-(level + 10),
+// per axis a the 16-bit offsets (in q) of its lower and upper bound from
+// the cell's dyadic centre, b[a] = lo | hi << 16; b[3] bit 0 is set when the
+// box fits those offsets (else the cell is unbounded: never pruned or
+// accepted).
+struct __align__(32) RefitCell {
+    uint4 pk;
+    int32_t b[4];
+};
+constexpr int kRefitShift = 10;         // q = side / 2^kRefitShift
+constexpr int64_t kRefitMaxOff = 32767; // largest offset stored, in q
 
 struct Tree {
     uint64_t id = 0;           // generation number, unique per process (lists refer to it)
@@ -106,6 +118,7 @@ struct Tree {
     // first particle, preorder id and first child slot (-1 for a leaf)
     DevBuf<int32_t> sfirst, spre, schild;
     DevBuf<double> clo, chi;   // [nn*3] boxes of the cells of a refitted tree
+    DevBuf<RefitCell> rpack;   // their walk records
     // groups, in order of first
     DevBuf<int32_t> gfirst, gcount;
     DevBuf<double> glo, ghi;   // [ng*3]

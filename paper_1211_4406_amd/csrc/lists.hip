@@ -17,7 +17,9 @@
 //   accept iff side * side < (theta * theta) * d2(half = 0)
 // with cen_c the cell's geometric centre, or for the acceptance test of the
 // centre-of-mass criterion its centre of mass.  A refitted tree measures
-// each cell by the box [lo, hi] of its particles instead:
+// each cell by the box [lo, hi] of its particles instead, every bound
+// rounded outward to a multiple of 2^-(level + 10) (a cell whose bounds do
+// not fit 16-bit offsets from its centre is never pruned or accepted):
 //   cen_c = (lo + hi) * 0.5, half = (hi - lo) * 0.5 per axis,
 //   per axis t = cen_c - cen_g, t = |t - rint(t)|, e = max(0, t - (half + h_g))
 //   d2 as above; prune iff d2 >= r_cut * r_cut,
@@ -101,6 +103,20 @@ __device__ __forceinline__ double refit_axis_gap(double cen, double cg, double h
     return r > 0.0 ? r : 0.0;
 }
 
+// The rounded box of a refitted cell: bound K q with K the stored offset
+// plus the centre's multiple ic * 1024 + 512 (exact in FP64).
+__device__ __forceinline__ void refit_box(const RefitCell& r, const Cell& k, double* bl, double* bh) {
+    const uint32_t ic[3] = {r.pk.x & 0x1fffffu, r.pk.y & 0x1fffffu, r.pk.z & 0x1fffffu};
+    const int e = k.level + kRefitShift;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int64_t kc = (int64_t)ic[a] * (1 << kRefitShift) + (1 << (kRefitShift - 1));
+        const int32_t lo = (int32_t)(int16_t)(r.b[a] & 0xffff), hi = r.b[a] >> 16;
+        bl[a] = ldexp((double)(kc + lo), -e);
+        bh[a] = ldexp((double)(kc + hi), -e);
+    }
+}
+
 // The same classification for a cell of a refitted tree with box [bl, bh].
 __device__ __forceinline__ int classify_refit(const Cell& k, const double* bl, const double* bh, const double* mc,
                                               bool com, const Frame& f, double rc2, double th2) {
@@ -179,8 +195,8 @@ __global__ __launch_bounds__(kListThreads) void k_lists(int64_t ng, const double
                                                const double* __restrict__ ghi, const int32_t* __restrict__ gcount,
                                                const uint4* __restrict__ pack, const NodeRange* __restrict__ rng,
                                                const double* __restrict__ nX, const double* __restrict__ nY,
-                                               const double* __restrict__ nZ, const double* __restrict__ clo,
-                                               const double* __restrict__ chi, int64_t nn, double rc2, double th2, int64_t* __restrict__ cnt,
+                                               const double* __restrict__ nZ,
+                                               const RefitCell* __restrict__ rpack, int64_t nn, double rc2, double th2, int64_t* __restrict__ cnt,
                                                int64_t* __restrict__ icnt, unsigned long long* __restrict__ totals,
                                                const int64_t* __restrict__ ioff, int32_t* __restrict__ items) {
     static_assert(G * kLevels <= 64, "level masks must fit one word");
@@ -206,7 +222,9 @@ __global__ __launch_bounds__(kListThreads) void k_lists(int64_t ng, const double
     uint64_t masks = valid;  // level 0
     int64_t i = valid ? 0 : nn;
     while (i < nn) {
-        const Cell k = decode(pack[i]);
+        RefitCell rc;
+        if (REFIT) rc = rpack[i];
+        const Cell k = decode(REFIT ? rc.pk : pack[i]);
         const uint64_t act = (masks >> (k.level * G)) & full;
         uint64_t open = 0;
         if (act) {
@@ -217,17 +235,16 @@ __global__ __launch_bounds__(kListThreads) void k_lists(int64_t ng, const double
                 mcen[2] = nZ[i];
             }
             double bl[3] = {0, 0, 0}, bh[3] = {0, 0, 0};
+            bool bounded = true;
             if (REFIT) {
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    bl[a] = clo[i * 3 + a];
-                    bh[a] = chi[i * 3 + a];
-                }
+                bounded = rc.b[3] & 1;
+                refit_box(rc, k, bl, bh);
             }
 #pragma unroll
             for (int q = 0; q < G; ++q) {
                 if (!((act >> q) & 1ull)) continue;
-                const int cls = REFIT ? classify_refit(k, bl, bh, mcen, COM, f[q], rc2, th2)
+                const int cls = REFIT ? (bounded ? classify_refit(k, bl, bh, mcen, COM, f[q], rc2, th2)
+                                                 : (k.leaf ? 2 : 3))
                                       : classify(k, mcen, f[q], rc2, th2);
                 if (cls == 3) {
                     open |= 1ull << q;
@@ -383,7 +400,7 @@ void build_lists(const Tree& t, Lists& l, hipStream_t st) {
     auto walk = [&](auto kernel, int64_t* cnt, int64_t* ic, unsigned long long* tot, const int64_t* ioff,
                     int32_t* out) {
         hipLaunchKernelGGL(kernel, grid, block, 0, st, ng, t.glo.get(), t.ghi.get(), t.gcount.get(), t.pack.get(),
-                           t.range.get(), t.nX.get(), t.nY.get(), t.nZ.get(), t.clo.get(), t.chi.get(), t.n_nodes,
+                           t.range.get(), t.nX.get(), t.nY.get(), t.nZ.get(), t.rpack.get(), t.n_nodes,
                            rc2, th2, cnt, ic, tot, ioff, out);
     };
     auto walk_all = [&](auto write, int64_t* cnt, int64_t* ic, unsigned long long* tot, const int64_t* ioff,

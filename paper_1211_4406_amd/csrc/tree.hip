@@ -554,6 +554,33 @@ __global__ void k_pack(int64_t nn, const NodeGeo* __restrict__ geo, const NodeRa
     pack[c] = pk;
 }
 
+// The walk record of each cell of a refitted tree (preorder): the packed
+// record, and the box rounded outward to multiples of q = 2^-(level + 10),
+// K = floor(lo / q) and ceil(hi / q) (exact), stored as offsets from the
+// centre's multiple ic * 1024 + 512 when both fit 16 bits.
+__global__ void k_refit_pack(int64_t nn, const NodeGeo* __restrict__ geo, const uint4* __restrict__ pack,
+                             const double* __restrict__ clo, const double* __restrict__ chi,
+                             RefitCell* __restrict__ out) {
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= nn) return;
+    const NodeGeo g = geo[c];
+    const int e = (int)(g.level_leaf & 0xffu) + kRefitShift;
+    const uint32_t ic[3] = {g.ix, g.iy, g.iz};
+    RefitCell r;
+    r.pk = pack[c];
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int64_t kc = (int64_t)ic[a] * (1 << kRefitShift) + (1 << (kRefitShift - 1));
+        const int64_t kl = (int64_t)floor(ldexp(clo[c * 3 + a], e)) - kc;
+        const int64_t kh = (int64_t)ceil(ldexp(chi[c * 3 + a], e)) - kc;
+        ok = ok && kl >= -kRefitMaxOff && kh <= kRefitMaxOff;
+        r.b[a] = (int32_t)(((uint32_t)(uint16_t)(int16_t)kl) | ((uint32_t)(uint16_t)(int16_t)kh << 16));
+    }
+    r.b[3] = ok ? 1 : 0;
+    out[c] = r;
+}
+
 __global__ void k_group_write(int64_t n, const int32_t* __restrict__ sc, int32_t* __restrict__ gfirst) {
     int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= n) return;
@@ -733,6 +760,10 @@ void refit_cells_and_groups(Tree& t, hipStream_t st) {
                            sbox.get(), t.nM.get(), t.nX.get(), t.nY.get(), t.nZ.get(), t.clo.get(), t.chi.get());
         SRF_HIP(hipGetLastError());
     }
+    if (!t.rpack.get()) t.rpack.alloc(nn, st);
+    hipLaunchKernelGGL(k_refit_pack, dim3(grid_for(nn, 256, 1 << 30)), dim3(256), 0, st, nn, t.geo.get(),
+                       t.pack.get(), t.clo.get(), t.chi.get(), t.rpack.get());
+    SRF_HIP(hipGetLastError());
     if (ng > 0) {
         hipLaunchKernelGGL(k_group_bbox<true>, dim3(grid_for(ng, 256 / kBoxLanes, 1 << 30)), dim3(256), 0, st, ng,
                            t.gfirst.get(), t.gcount.get(), t.px.get(), t.py.get(), t.pz.get(), t.glo.get(),

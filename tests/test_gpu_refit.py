@@ -48,7 +48,7 @@ def _slab():
     x = np.concatenate([rng.random(n // 2) * 0.08, 0.92 + rng.random(n // 2) * 0.08])
     y, z = 0.3 + 0.4 * rng.random(n), 0.3 + 0.4 * rng.random(n)
     ps = synth.ParticleSet(x, y, z, np.full(n, 1.0 / n), synth.Params(1.0, 0.06, 3e-4, 1.0, 64, 16))
-    return ps, ps.positions() + np.array([-0.0123, 0.0071, 0.0])
+    return ps, ps.positions() + np.array([-13.0, 7.0, 0.0]) / 1024
 
 
 def _cases():
@@ -216,3 +216,23 @@ def test_refit_refuses_stale_lists_and_keeps_the_tree_on_bad_input():
     lists = srf.make_lists(tree, params)
     c = srf.short_range_force(tree, lists, params).cpu().numpy()
     assert np.allclose(c, 2.0 * a, rtol=1e-13, atol=1e-13 * np.abs(a).max())
+
+
+def test_refit_with_an_unbounded_cell():
+    """One particle of a deep leaf moved by 0.3 in x: that leaf's box no
+    longer fits its 16-bit offsets, so it is never pruned or accepted; the
+    lists still equal the oracle's and the force its bound."""
+    ps = synth.small_clustered(4096, 41, r_cut=0.06, eps=3e-4, theta=0.7, per_halo=2048, a_range=(5e-4, 2e-3))
+    ot = oracle.OracleTree(ps.x, ps.y, ps.z, ps.m, ps.params)
+    t = ot.tree
+    c0 = np.flatnonzero(t.leaf.astype(bool) & (t.level >= 7) & (t.count >= 2))[0]
+    new = ps.positions()
+    new[ot.perm[t.first[c0]], 0] += 0.3
+    rt = ot.refitted(new[:, 0], new[:, 1], new[:, 2])
+    assert not rt.refit_qboxes()[2][c0]
+    p, tree, lists, _, _ = _refit(ps, new, ps.params, srf.FP32_REL)
+    L = lists.export()
+    for k in ("poff", "pidx", "noff", "nidx"):
+        assert np.array_equal(L[k], getattr(rt.lists, k)), k
+    a = srf.short_range_force(tree, lists, p).cpu().numpy()
+    check(a, rt.force(), rt.force_bound(U32), constant("force", False, max_list(rt)), "unbounded-cell force")

@@ -86,6 +86,68 @@ def test_refitted_boxes_hold_their_particles(name):
 
 
 @pytest.mark.parametrize("name", ["clustered", "uniform"])
+def test_rounded_boxes_hold_the_particles(name):
+    """The boxes the list decisions use: each cell's box rounded outward to
+    multiples of q = 2^-(level+10), within one q of it, holding an image of
+    every particle of the cell.  A cell of level <= 6 is always bounded (no
+    image lies more than half the box from the cell's centre)."""
+    ps = _sets()[name]
+    ot = oracle.OracleTree(ps.x, ps.y, ps.z, ps.m, ps.params)
+    new = _drifted(ps, 4e-3, 4)
+    rt = ot.refitted(new[:, 0], new[:, 1], new[:, 2])
+    qlo, qhi, ok = rt.refit_qboxes()
+    t = ot.tree
+    assert np.all(ok[t.level <= 6])
+    u = np.stack([rt.ux, rt.uy, rt.uz], axis=1)
+    for c in np.flatnonzero(ok):
+        e = int(t.level[c]) + 10
+        q = 2.0 ** -e
+        for b in (qlo[c], qhi[c]):
+            assert np.all(np.ldexp(b, e) == np.rint(np.ldexp(b, e)))
+        assert np.all(qlo[c] <= rt.clo[c]) and np.all(qlo[c] > rt.clo[c] - q)
+        assert np.all(qhi[c] >= rt.chi[c]) and np.all(qhi[c] < rt.chi[c] + q)
+        v = u[t.first[c]:t.first[c] + t.count[c]]
+        imgs = v[None] + np.array([-1.0, 0.0, 1.0])[:, None, None]
+        assert np.all(((imgs >= qlo[c]) & (imgs <= qhi[c])).any(axis=0)), c
+
+
+def test_a_particle_moved_far_leaves_its_deep_cell_unbounded_and_covered():
+    """One particle of a deep leaf (level >= 7) moved by 0.3 in x: its leaf's
+    box no longer fits 32767 steps of its centre, so the cell is unbounded
+    (never pruned, never accepted), and every pair within r_cut is still
+    covered exactly once for every group."""
+    ps = synth.small_clustered(4096, 41, r_cut=0.06, eps=3e-4, theta=0.7, per_halo=2048, a_range=(5e-4, 2e-3))
+    ot = oracle.OracleTree(ps.x, ps.y, ps.z, ps.m, ps.params)
+    t = ot.tree
+    deep = np.flatnonzero(t.leaf.astype(bool) & (t.level >= 7) & (t.count >= 2))
+    assert deep.size
+    c0 = deep[0]
+    k = ot.perm[t.first[c0]]
+    new = np.stack([ps.x, ps.y, ps.z], axis=1)
+    new[k, 0] = np.mod(new[k, 0] + 0.3, 1.0)
+    rt = ot.refitted(new[:, 0], new[:, 1], new[:, 2])
+    qlo, qhi, ok = rt.refit_qboxes()
+    assert not ok[c0] and ok[t.level <= 6].all()
+    u = np.stack([rt.ux, rt.uy, rt.uz], axis=1)
+    L = rt.lists
+    listed = 0
+    for g in range(rt.n_groups):
+        cov = np.zeros(ps.n, np.int64)
+        np.add.at(cov, L.pidx[L.poff[g]:L.poff[g + 1]], 1)
+        for c in L.nidx[L.noff[g]:L.noff[g + 1]]:
+            assert ok[c]
+            cov[t.first[c]:t.first[c] + t.count[c]] += 1
+        assert cov.max() <= 1
+        mem = u[rt.gfirst[g]:rt.gfirst[g] + rt.gcount[g]]
+        d = u[None, :, :] - mem[:, None, :]
+        d -= np.rint(d)
+        near = np.any(np.sum(d * d, axis=2) < ps.params.r_cut ** 2, axis=0)
+        assert np.all(cov[near] == 1), g
+        listed += int(t.first[c0] in L.pidx[L.poff[g]:L.poff[g + 1]])
+    assert listed > 0
+
+
+@pytest.mark.parametrize("name", ["clustered", "uniform"])
 @pytest.mark.parametrize("theta", [0.0, 0.5, 1.0])
 def test_refitted_list_coverage(name, theta):
     ps = _sets()[name]
@@ -95,6 +157,7 @@ def test_refitted_list_coverage(name, theta):
     rt = ot.refitted(new[:, 0], new[:, 1], new[:, 2])
     u = np.stack([rt.ux, rt.uy, rt.uz], axis=1)
     L, t = rt.lists, rt.tree
+    qlo, qhi, ok = rt.refit_qboxes()
     for g in np.random.default_rng(0).choice(rt.n_groups, min(40, rt.n_groups), replace=False):
         cov = np.zeros(ps.n, np.int64)
         pl = L.pidx[L.poff[g]:L.poff[g + 1]]
@@ -110,14 +173,15 @@ def test_refitted_list_coverage(name, theta):
         near = np.any(np.sum(d * d, axis=2) < p.r_cut ** 2, axis=0)
         assert np.all(cov[near] == 1)
         assert np.all(np.isin(np.arange(rt.gfirst[g], rt.gfirst[g] + rt.gcount[g]), pl))
-        # accepted cells: the larger of the dyadic side and the longest box
-        # side below theta times the distance from the group box to the
-        # cell box's centre
+        # accepted cells: the larger of the dyadic side and the longest side
+        # of the (outward-rounded) box below theta times the distance from
+        # the group box to the box's centre
         cg = 0.5 * (rt.lo[g] + rt.hi[g])
         hg = 0.5 * (rt.hi[g] - rt.lo[g])
         for c in nl:
-            side = max(np.max(rt.chi[c] - rt.clo[c]), 2.0 ** -int(t.level[c]))
-            dd = 0.5 * (rt.clo[c] + rt.chi[c]) - cg
+            assert ok[c]
+            side = max(np.max(qhi[c] - qlo[c]), 2.0 ** -int(t.level[c]))
+            dd = 0.5 * (qlo[c] + qhi[c]) - cg
             dd = np.abs(dd - np.rint(dd))
             gap = np.maximum(dd - hg, 0)
             assert side < theta * np.sqrt(np.sum(gap * gap)) * (1 + 1e-12)
@@ -209,7 +273,8 @@ def _fd_mass(rt, w, s, rel):
 
 def _slab():
     """A slab of particles on both sides of the face x = 0 (|x| < 0.08),
-    moved by -0.0123 in x: most cells near the face then hold particles on
+    moved by -13/1024 in x (and 7/1024 in y; multiples of the rounding step
+    of every refitted box): most cells near the face then hold particles on
     both sides of it, and many are accepted with their centre of mass
     within r_cut of the group."""
     rng = np.random.default_rng(5)
@@ -218,7 +283,7 @@ def _slab():
     y, z = 0.3 + 0.4 * rng.random(n), 0.3 + 0.4 * rng.random(n)
     p = synth.Params(1.0, 0.06, 3e-4, 1.0, 64, 16)
     ot = oracle.OracleTree(x, y, z, np.full(n, 1.0 / n), p)
-    new = np.mod(np.stack([x, y, z], axis=1) + np.array([-0.0123, 0.0071, 0.0]), 1.0)
+    new = np.mod(np.stack([x, y, z], axis=1) + np.array([-13.0, 7.0, 0.0]) / 1024, 1.0)
     return ot, ot.refitted(new[:, 0], new[:, 1], new[:, 2])
 
 
