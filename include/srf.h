@@ -82,9 +82,11 @@ typedef struct {
     int32_t n_group;     /* maximum particles per group                             */
     int32_t n_leaf;      /* a cell with more particles is split (down to level 21)  */
     int32_t precision;   /* enum srf_precision (force and adjoint kernels)          */
-    int32_t compensated; /* 1: compensated (Kahan) FP32 partial sums over each list
-                            tile of the SRF_FP32_REL force kernel; 0: plain FP32.
-                            No effect on the FP64 kernel or on the adjoint.       */
+    int32_t compensated; /* 1: compensated (Kahan) FP32 partial sums over each chunk
+                            of 32 list entries of the SRF_FP32_REL force kernel
+                            (the chunks are added in FP64 either way); 0: plain
+                            FP32.  No effect on the FP64 kernel or on the
+                            adjoint.                                              */
     int32_t mac;         /* enum srf_mac: the point the opening criterion measures
                             to (srf_make_lists; must match the lists after)       */
 } srf_params;

@@ -288,21 +288,38 @@ __device__ __forceinline__ int stage_tile(const int32_t* __restrict__ ent, int l
 // Pairs of this lane's stream with the entries [a, b) of a staged tile
 // (entries a + st, a + st + S, ...).  The unrolled loop takes U entries
 // per stream (8 for the shorter far pairs, 4 for near pairs) while all
-// streams have U left, so its trip count is the same for every lane.
+// streams have U left, so its trip count is the same for every lane.  The
+// FP32 partial sums are added to the FP64 totals every kFlush entries:
+// the rounding error of an FP32 running sum grows with its length, and on
+// near-uniform sets, where a particle's force is a small residual of its
+// neighbours' pulls, partials over a whole tile (256 entries) dominated the
+// error; chunks of 32 cost no measurable time.
+constexpr int kFlush = 32;
 template <class T, class V4, int S, bool NEAR, bool COMP, bool RS>
 __device__ __forceinline__ void force_segment(const V4* tile, int a, int b, int st, T xi, T yi, T zi,
-                                              const Coef<T>& c, Acc<T, COMP>& acc) {
+                                              const Coef<T>& c, double& sx, double& sy, double& sz) {
     constexpr int U = NEAR ? 4 : 8;
+    constexpr int FL = kFlush / U;
     const V4* tp = tile + a + st;
     int kk = a;
-    for (; kk + U * S <= b; kk += U * S, tp += U * S) {
-        V4 pp[U];
+    while (kk + U * S <= b) {
+        Acc<T, COMP> acc;
+        for (int it = 0; it < FL && kk + U * S <= b; ++it, kk += U * S, tp += U * S) {
+            V4 pp[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) pp[u] = tp[u * S];
+            for (int u = 0; u < U; ++u) pp[u] = tp[u * S];
 #pragma unroll
-        for (int u = 0; u < U; ++u) pair_force<T, V4, NEAR, COMP, RS>(pp[u], xi, yi, zi, c, acc);
+            for (int u = 0; u < U; ++u) pair_force<T, V4, NEAR, COMP, RS>(pp[u], xi, yi, zi, c, acc);
+        }
+        sx += COMP ? (double)acc.x - (double)acc.cx : (double)acc.x;
+        sy += COMP ? (double)acc.y - (double)acc.cy : (double)acc.y;
+        sz += COMP ? (double)acc.z - (double)acc.cz : (double)acc.z;
     }
+    Acc<T, COMP> acc;
     for (int k = kk + st; k < b; k += S, tp += S) pair_force<T, V4, NEAR, COMP, RS>(tp[0], xi, yi, zi, c, acc);
+    sx += COMP ? (double)acc.x - (double)acc.cx : (double)acc.x;
+    sy += COMP ? (double)acc.y - (double)acc.cy : (double)acc.y;
+    sz += COMP ? (double)acc.z - (double)acc.cz : (double)acc.z;
 }
 
 struct GroupArgs {
@@ -339,14 +356,10 @@ __device__ __forceinline__ void force_group(const GroupArgs& ga, const Src& src,
         __syncthreads();
         const int nnear = stage_tile<T, V4>(ga.ent + tb, len, src, cx, cy, cz, hx, hy, hz, c0.far2, tile, nullptr);
         __syncthreads();
-        Acc<T, COMP> acc;
         if (active) {
-            force_segment<T, V4, S, true, COMP, RS>(tile, 0, nnear, st, xi, yi, zi, c, acc);
-            force_segment<T, V4, S, false, COMP, RS>(tile, nnear, len, st, xi, yi, zi, c, acc);
+            force_segment<T, V4, S, true, COMP, RS>(tile, 0, nnear, st, xi, yi, zi, c, sx, sy, sz);
+            force_segment<T, V4, S, false, COMP, RS>(tile, nnear, len, st, xi, yi, zi, c, sx, sy, sz);
         }
-        sx += COMP ? (double)acc.x - (double)acc.cx : (double)acc.x;
-        sy += COMP ? (double)acc.y - (double)acc.cy : (double)acc.y;
-        sz += COMP ? (double)acc.z - (double)acc.cz : (double)acc.z;
     }
     red[lane * 3 + 0] = sx;
     red[lane * 3 + 1] = sy;
@@ -483,13 +496,28 @@ __device__ __forceinline__ void potential_group(const GroupArgs& ga, const Src& 
         const int nnear = stage_tile<T, V4>(ga.ent + tb, len, src, cx, cy, cz, hx, hy, hz, c0.far2, tile, ids,
                                             n_part);
         __syncthreads();
-        T acc = 0;
         if (active) {
-            for (int k = st; k < nnear; k += S) acc += pair_pot<T, V4, true, RS>(tile[k], xi, yi, zi, c, ids[k] == me);
-            for (int k = nnear + st; k < len; k += S)
+            // FP32 partials over at most kFlush entries of this lane, added in FP64
+            int n = 0;
+            T acc = 0;
+            for (int k = st; k < nnear; k += S) {
+                acc += pair_pot<T, V4, true, RS>(tile[k], xi, yi, zi, c, ids[k] == me);
+                if (++n == kFlush) {
+                    sum += (double)acc;
+                    acc = 0;
+                    n = 0;
+                }
+            }
+            for (int k = nnear + st; k < len; k += S) {
                 acc += pair_pot<T, V4, false, RS>(tile[k], xi, yi, zi, c, false);
+                if (++n == kFlush) {
+                    sum += (double)acc;
+                    acc = 0;
+                    n = 0;
+                }
+            }
+            sum += (double)acc;
         }
-        sum += (double)acc;
     }
     red[lane] = active ? sum : 0.0;
     __syncthreads();

@@ -14,7 +14,7 @@ counts how many times that magnitude can be spent:
     C = K + P + L_ref * u64 / u
 
   K     the longest sum the kernel forms in working precision before it is
-        added in FP64 (force: one lane's partial over a 256-entry tile;
+        added in FP64 (force: one lane's partial over a 32-entry chunk of a tile;
         adjoint: one lane's i-side partial over the 64 entries of its row in
         a tile, longer than the j-side's 4-term register sum and 16-lane
         row sum),
@@ -32,7 +32,7 @@ import numpy as np
 U32 = 2.0 ** -24
 U64 = 2.0 ** -53
 P_PAIR = 64
-K_FORCE = 256
+K_FORCE = 32
 K_ADJOINT = 64
 
 

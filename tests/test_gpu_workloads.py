@@ -1,6 +1,6 @@
 """GPU accuracy on the five full-size workloads, and the workload-4 gradient.
 
-Workloads 1, 2 and 5 at theta = 0.5 and workload 3 at theta = 0.3, 0.5 and
+Workloads 1, 2, 4 and 5 at theta = 0.5 and workload 3 at theta = 0.3, 0.5 and
 0.7: the FP32 group-relative force and the all-FP64 kernel against the
 same-list FP64 oracle (on sampled groups), and the tree error of the FP32
 force against the brute-force cutoff sum (on sampled particles).  Workload
@@ -44,6 +44,31 @@ def run_gpu(ps, precision):
     return tree, lists, a.cpu().numpy()
 
 
+def kernel_ms(tree, lists, p, reps=3):
+    """Median force-kernel time (HIP events around the launch)."""
+    srf.set_kernel_timing(True)
+    ts = []
+    for _ in range(reps):
+        srf.short_range_force(tree, lists, p)
+        ts.append(srf.last_kernel_ms("force"))
+    srf.set_kernel_timing(False)
+    return float(np.median(ts))
+
+
+def variant_tree_error(ps, sel, bf, mac=srf.MAC_CENTRE, quadrupole=False):
+    """Tree error of the FP32 force of an accuracy variant (centre-of-mass
+    criterion, quadrupole cells) against the brute-force sum on `sel`."""
+    p = srf.Params.of(ps.params, srf.FP32_REL)
+    p = srf.Params(p.G, p.r_cut, p.eps, p.theta, p.n_group, p.n_leaf, p.precision, 0, mac)
+    x = torch.tensor(ps.positions(), dtype=torch.float64, device="cuda")
+    m = torch.tensor(ps.m, dtype=torch.float64, device="cuda")
+    tree = srf.tree_build(x, m, p)
+    lists = srf.make_lists(tree, p)
+    a = srf.short_range_force(tree, lists, p, quadrupole=quadrupole).cpu().numpy()
+    _, st = oracle.relative_errors(a[sel], bf)
+    return dict(median=st["median"], p99=st["p99"], l2=st["l2"], interactions=lists.info()["interactions"])
+
+
 def sampled_same_list(ot, a_gpu, n_groups, seed, fp64):
     """Relative-error statistics on sampled groups; every sampled particle is
     held to its element-wise bound (the constant needed is returned too)."""
@@ -60,7 +85,7 @@ def sampled_same_list(ot, a_gpu, n_groups, seed, fp64):
     return st
 
 
-def forward_accuracy(k, theta):
+def forward_accuracy(k, theta, variants=False):
     t0 = time.time()
     ps = synth.make_config(k, theta)
     say(f"[gpu] workload {k} ({ps.name}, theta={ps.params.theta}), n={ps.n}")
@@ -74,6 +99,12 @@ def forward_accuracy(k, theta):
     ng_sample = ot.n_groups if ps.n <= 4096 else 400
     s32 = sampled_same_list(ot, a32, ng_sample, 10 + k, False)
     s64 = sampled_same_list(ot, a64, ng_sample, 10 + k, True)
+    # the compensated (Kahan) FP32 option on the same tree and lists
+    pc = srf.Params.of(ps.params, srf.FP32_REL, compensated=1)
+    ac = srf.short_range_force(tree, lists, pc).cpu().numpy()
+    sc = sampled_same_list(ot, ac, ng_sample, 10 + k, False)
+    sc["kernel_ms"] = kernel_ms(tree, lists, pc)
+    s32["kernel_ms"] = kernel_ms(tree, lists, srf.Params.of(ps.params, srf.FP32_REL))
     # tree error (monopole cells of the opening criterion) against the exact
     # brute-force cutoff sum, on sampled particles
     rng = np.random.default_rng(20 + k)
@@ -87,17 +118,23 @@ def forward_accuracy(k, theta):
                momentum_residual=mom,
                n_groups=info["n_groups"], mean_Ni=ps.n / info["n_groups"],
                mean_Nj=(info["n_particle_entries"] + info["n_node_entries"]) / info["n_groups"],
-               fp32_vs_same_list=s32, fp64_vs_same_list=s64,
+               fp32_vs_same_list=s32, fp32_compensated_vs_same_list=sc, fp64_vs_same_list=s64,
                tree_vs_brute_force=dict(median=st_tree["median"], p99=st_tree["p99"], rms=st_tree["rms"],
-                                        max=st_tree["max"], l2=st_tree["l2"], sample=int(sel.size)),
-               seconds=round(time.time() - t0, 1))
+                                        max=st_tree["max"], l2=st_tree["l2"], sample=int(sel.size)))
+    if variants:
+        del tree, lists
+        rec["tree_vs_brute_force_com_mac"] = variant_tree_error(ps, sel, bf, mac=srf.MAC_COM)
+        rec["tree_vs_brute_force_quadrupole"] = variant_tree_error(ps, sel, bf, quadrupole=True)
+        rec["tree_vs_brute_force_com_mac_quadrupole"] = variant_tree_error(ps, sel, bf, mac=srf.MAC_COM,
+                                                                           quadrupole=True)
+    rec["seconds"] = round(time.time() - t0, 1)
     say("WORKLOAD " + json.dumps(rec))
-    assert s32["rms"] <= 1e-5
+    assert s32["rms"] <= 1e-5 and sc["rms"] <= 1e-5
     assert s64["rms"] <= 1e-12
     return rec
 
 
-@pytest.mark.parametrize("k", [1, 2, 5])
+@pytest.mark.parametrize("k", [1, 2, 4, 5])
 def test_workload_forward_accuracy(k):
     rec = forward_accuracy(k, None)
     # the uniform set is small enough that theta = 0.5 opens every cell near
@@ -110,7 +147,7 @@ def test_workload3_theta_sweep():
     """Near-uniform set: the net short-range force is a small residual of
     cancelling neighbours, so the monopole error relative to it grows quickly
     with theta; parity holds at every theta and the error is monotone."""
-    recs = [forward_accuracy(3, th) for th in (0.3, 0.5, 0.7)]
+    recs = [forward_accuracy(3, th, variants=(th == 0.5)) for th in (0.3, 0.5, 0.7)]
     med = [r["tree_vs_brute_force"]["median"] for r in recs]
     l2 = [r["tree_vs_brute_force"]["l2"] for r in recs]
     inter = [r["interactions"] for r in recs]
