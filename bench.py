@@ -89,6 +89,8 @@ def parse():
                     help="skip the separate timings of the quadrupole term and the potential")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (for HBM counter calibration)")
+    ap.add_argument("--valu-calibration", action="store_true",
+                    help="only measure the vector ALU's cycles per wave64 instruction (libsrf_calib.so)")
     return ap.parse_args()
 
 
@@ -104,6 +106,48 @@ def copy_calibration(mib: int):
     b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8}), flush=True)
+
+
+VALU_KINDS = ("v_fma_f32, all operands in VGPRs", "v_fma_f32 with one SGPR operand", "v_rsq_f32", "v_sqrt_f32",
+              "v_fma_f64, all operands in VGPRs", "v_fma_f32, one dependent chain per lane",
+              "v_add_f32 with DPP quad_perm", "v_add_f32 with DPP row_half_mirror", "v_add_f32 with DPP row_mirror")
+
+
+def valu_calibration():
+    """Cycles one SIMD spends per wave64 instruction of each kind, at 1, 2, 4
+    and 8 waves per SIMD on every compute unit (8 independent chains per
+    lane unless stated), from the shader clock each wave reads around its
+    loop; the pair kernels' instruction counts are priced with these."""
+    import ctypes as C
+
+    import torch
+
+    from paper_1211_4406_amd import build as _build
+
+    if not os.path.exists(_build.CALIB_LIB):
+        print(f"{_build.CALIB_LIB} is missing: run python paper_1211_4406_amd/build.py", file=sys.stderr)
+        sys.exit(1)
+    lib = C.CDLL(_build.CALIB_LIB)
+    lib.srf_calib_valu.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    out = []
+    for kind, name in enumerate(VALU_KINDS):
+        for w in (1, 2, 4, 8):
+            iters = 4096 if kind in (2, 3, 4) else 16384
+            cpi, ms = C.c_double(), C.c_double()
+            lib.srf_calib_valu(kind, n_cu, w, iters // 8, C.byref(cpi), C.byref(ms))   # warm-up
+            rc = lib.srf_calib_valu(kind, n_cu, w, iters, C.byref(cpi), C.byref(ms))
+            if rc != 0:
+                print(f"srf_calib_valu failed ({rc})", file=sys.stderr)
+                sys.exit(1)
+            per_wave = (8 if kind == 5 else 32) * iters
+            n_inst = per_wave * 4 * w * n_cu
+            rec = dict(kind=name, waves_per_simd=w, cycles_per_instruction=cpi.value, ms=ms.value,
+                       wave64_instructions_per_s=n_inst / (ms.value * 1e-3),
+                       implied_clock_ghz=cpi.value * n_inst / (4 * n_cu) / (ms.value * 1e-3) / 1e9)
+            out.append(rec)
+            print("VALU " + json.dumps(rec), flush=True)
+    return out
 
 
 def cpu_baseline(ps, sample_groups: int, w):
@@ -188,6 +232,9 @@ def cpu_baseline(ps, sample_groups: int, w):
 
 def main():
     args = parse()
+    if args.valu_calibration:
+        valu_calibration()
+        return
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return

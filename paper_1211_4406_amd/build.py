@@ -2,7 +2,9 @@
 
     python paper_1211_4406_amd/build.py
 
-(run as a script: importing the package loads the library it builds).
+(run as a script: importing the package loads the library it builds).  It also
+builds libsrf_calib.so, the vector-ALU issue-rate calibration that
+`bench.py --valu-calibration` runs.
 
 Every translation unit is compiled for gfx950 only, with packed FP32
 instructions disabled.  The cell/group and list units are compiled without
@@ -21,6 +23,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsrf.so")
+# the vector-ALU issue-rate calibration (a measurement tool, its own library)
+CALIB_SRC = os.path.join(HERE, "calib", "valu_issue.hip")
+CALIB_LIB = os.path.join(HERE, "libsrf_calib.so")
 
 SOURCES = {
     "runtime.hip": [],
@@ -69,8 +74,13 @@ def build(save_temps: bool = False, verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
     os.replace(tmp, LIB)
+    tmp = CALIB_LIB + ".tmp"
+    r = subprocess.run([hipcc(), *COMMON, "-shared", "-o", tmp, CALIB_SRC], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("calibration library failed:\n" + r.stdout + r.stderr)
+    os.replace(tmp, CALIB_LIB)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", CALIB_LIB)
     return LIB
 
 
