@@ -581,7 +581,7 @@ __device__ __forceinline__ void jac_coefs(T r2, T r, T rinv, const Coef<T>& c, T
         const T R = fma_(fma_(fma_(r, c.R3, c.R2), r, c.R1), r, c.R0);
         const T a = s3 * ((t * t) * (t * t));
         phi = a * (t * R);
-        psi = fma_(c.m3 * u, phi, -(a * fma_(r2, c.E2, fma_(r, c.E1, c.E0))));
+        psi = fma_(c.m3 * u, phi, -(a * fma_(fma_(r, c.E2, c.E1), r, c.E0)));
     }
 }
 
@@ -602,11 +602,14 @@ struct AdjOut {
 //     target (summed over the rows once per tile, in FP64, into the FP64
 //     total the target's own lane keeps),
 //   - V = J w_i and phi (d . w_i) are summed in registers over the NB
-//     blocks, then over the 16 lanes of the row with DPP moves; the row's
-//     first lane stores the four totals in the tile's j-side slot of the
-//     entry, and once per tile the slots are scaled by the source masses and
-//     added to the sources' gradients with FP64 atomics (four lanes per
-//     source, one 32-byte row each).
+//     blocks, then over the 16 lanes of the row by a transposed reduction
+//     (two exchange steps that halve the number of values a lane holds,
+//     then two quad steps: 6 selects and 5 DPP adds instead of 16 DPP adds,
+//     which cost 1.5 times a plain instruction); four lanes of the row store
+//     the four totals in the tile's j-side slot of the entry, and once per
+//     tile the slots are scaled by the source masses and added to the
+//     sources' gradients with FP64 atomics (four lanes per source, one
+//     32-byte row each).
 // Targets past N_i carry zero weight, so they add nothing to either side.
 constexpr int kRow = 16;   // lanes per row: targets per block
 constexpr int kRows = 4;   // rows: entries per block
@@ -629,6 +632,12 @@ __device__ __forceinline__ float dpp_f(float v, int ctrl) {
 // form uses that shuffle directly.
 __device__ __forceinline__ float row16_step(float v, int k) { return v + dpp_f(v, k); }
 __device__ __forceinline__ double row16_step(double v, int k) { return v + __shfl_xor(v, 1 << k, 64); }
+// keep + the partner's send, the partner being the row mirror (k = 3: lane
+// 15 - i) or the half-row mirror (k = 2: lane i ^ 7)
+__device__ __forceinline__ float row_pair(float keep, float send, int k) { return keep + dpp_f(send, k); }
+__device__ __forceinline__ double row_pair(double keep, double send, int k) {
+    return keep + __shfl_xor(send, k == 3 ? 15 : 7, 64);
+}
 
 // Targets of one lane: block ib holds target 16 ib + a.
 template <class T, int NB>
@@ -648,6 +657,7 @@ template <class T, class V4, int NB, bool NEAR, bool RS>
 __device__ __forceinline__ void adjoint_entries(int a, int b, const V4* tile, const int32_t* ids, V4* jbuf,
                                                 int lane, Targets<T, NB>& tg, const Coef<T>& c) {
     const int ra = lane & (kRow - 1), rb = lane >> 4;
+    const bool hi8 = ra & 8, hi4 = ra & 4;
     for (int eb = a; eb < b; eb += kRows) {
         const int e = eb + rb;
         V4 p = tile[e];
@@ -657,8 +667,10 @@ __device__ __forceinline__ void adjoint_entries(int a, int b, const V4* tile, co
 #pragma unroll
         for (int ib = 0; ib < NB; ++ib) {
             const T dx = p.x - tg.x[ib], dy = p.y - tg.y[ib], dz = p.z - tg.z[ib];
-            const T r2 = fma_(dz, dz, fma_(dy, dy, dx * dx));
-            const T s2 = r2 + c.eps2;
+            // the far path with r from s needs no unsoftened r^2: s^2 directly
+            const bool direct = !NEAR && RS;
+            const T r2 = direct ? T(0) : fma_(dz, dz, fma_(dy, dy, dx * dx));
+            const T s2 = direct ? fma_(dz, dz, fma_(dy, dy, fma_(dx, dx, c.eps2))) : r2 + c.eps2;
             const T rinv = (NEAR && v == tg.id[ib]) ? T(0) : rsqrt_(s2);
             const T r = NEAR ? sqrt_(r2) : far_r<T, RS>(r2, s2, rinv, c);
             T phi, psi;
@@ -683,25 +695,27 @@ __device__ __forceinline__ void adjoint_entries(int a, int b, const V4* tile, co
                 jm = fma_(phi, dw, jm);
             }
         }
-        // row sums, the four chains interleaved step by step; the empty asm
-        // keeps the last DPP add fused (otherwise it is split into a move
-        // and an add inside the store's branch)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            jx = row16_step(jx, k);
-            jy = row16_step(jy, k);
-            jz = row16_step(jz, k);
-            jm = row16_step(jm, k);
+        // row sums of the four values, transposed: the row mirror pairs each
+        // lane of the low half with one of the high half, which keeps (jx, jy)
+        // resp. (jz, jm) and adds its partner's; the half-row mirror then
+        // pairs lanes 4 apart in the same way, leaving one value per lane
+        // (lanes 0-3: jx, 4-7: jy, 8-11: jz, 12-15: jm), and two quad steps
+        // finish the sums
+        T w0, w1, xs;
+        {
+            const T k0 = hi8 ? jz : jx, s0 = hi8 ? jx : jz;
+            const T k1 = hi8 ? jm : jy, s1 = hi8 ? jy : jm;
+            w0 = row_pair(k0, s0, 3);
+            w1 = row_pair(k1, s1, 3);
         }
-        asm volatile("" : "+v"(jx), "+v"(jy), "+v"(jz), "+v"(jm));
-        if (ra == 0) {
-            V4 o;
-            o.x = jx;
-            o.y = jy;
-            o.z = jz;
-            o.w = jm;
-            jbuf[e] = o;
+        {
+            const T k = hi4 ? w1 : w0, s = hi4 ? w0 : w1;
+            xs = row_pair(k, s, 2);
         }
+        xs = row16_step(xs, 0);
+        xs = row16_step(xs, 1);
+        asm volatile("" : "+v"(xs));
+        if ((ra & 3) == 0) reinterpret_cast<T*>(jbuf)[4 * e + (ra >> 2)] = xs;
     }
 }
 
