@@ -498,25 +498,18 @@ __device__ __forceinline__ void potential_group(const GroupArgs& ga, const Src& 
         __syncthreads();
         if (active) {
             // FP32 partials over at most kFlush entries of this lane, added in FP64
-            int n = 0;
-            T acc = 0;
-            for (int k = st; k < nnear; k += S) {
-                acc += pair_pot<T, V4, true, RS>(tile[k], xi, yi, zi, c, ids[k] == me);
-                if (++n == kFlush) {
-                    sum += (double)acc;
-                    acc = 0;
-                    n = 0;
-                }
+            for (int k0 = st; k0 < nnear; k0 += kFlush * S) {
+                const int k1 = k0 + kFlush * S < nnear ? k0 + kFlush * S : nnear;
+                T acc = 0;
+                for (int k = k0; k < k1; k += S) acc += pair_pot<T, V4, true, RS>(tile[k], xi, yi, zi, c, ids[k] == me);
+                sum += (double)acc;
             }
-            for (int k = nnear + st; k < len; k += S) {
-                acc += pair_pot<T, V4, false, RS>(tile[k], xi, yi, zi, c, false);
-                if (++n == kFlush) {
-                    sum += (double)acc;
-                    acc = 0;
-                    n = 0;
-                }
+            for (int k0 = nnear + st; k0 < len; k0 += kFlush * S) {
+                const int k1 = k0 + kFlush * S < len ? k0 + kFlush * S : len;
+                T acc = 0;
+                for (int k = k0; k < k1; k += S) acc += pair_pot<T, V4, false, RS>(tile[k], xi, yi, zi, c, false);
+                sum += (double)acc;
             }
-            sum += (double)acc;
         }
     }
     red[lane] = active ? sum : 0.0;
