@@ -300,23 +300,27 @@ __global__ __launch_bounds__(kListThreads) void k_lists(int64_t ng, const double
     }
 }
 
-// Expansion: one wave per group turns its items into entries.  Items are
-// taken 64 at a time (one per lane); a leaf item stands for its particles
-// first..first+count-1, a cell item for itself.  An inclusive scan of the
-// item sizes places each item in the chunk.  When the chunk's entries fit
-// the LDS buffer, each lane writes its own item's entries there and the
-// wave copies the buffer out, 64 consecutive entries per store; otherwise
-// lane k writes entries k, k + 64, ... of the chunk directly, finding its
-// item by binary search over the scan.
+// Expansion: one wave per group turns its items into entries.  A leaf item
+// stands for its particles first..first+count-1, a cell item for itself.
+// Items are taken kExpandItems at a time: each lane loads four of them and
+// then their leaves' ranges (all loads of a batch in flight together), a
+// scan of the item sizes places each item, and the entries are written
+// either through an LDS buffer (each lane writes its own items' entries,
+// then the wave copies the buffer out, 64 consecutive entries per store) or,
+// when the batch's entries exceed the buffer, directly, lane k writing
+// entries k, k + 64, ... and finding its item by binary search over the
+// scan.
 // Items of group g: icnt[g] of them from g * slot when slot > 0, else
 // [ioff[g], ioff[g + 1]).
 constexpr int kExpandBuf = 1024;
+constexpr int kExpandPer = 2;                   // items per lane per batch
+constexpr int kExpandItems = 64 * kExpandPer;   // items per batch
 
 __global__ __launch_bounds__(64) void k_expand(int64_t ng, int64_t slot, const int64_t* __restrict__ icnt,
                                                const int64_t* __restrict__ ioff, const int32_t* __restrict__ items,
                                                const NodeRange* __restrict__ rng, const int64_t* __restrict__ off,
                                                int32_t* __restrict__ ent) {
-    __shared__ int32_t s_end[64], s_first[64];
+    __shared__ int32_t s_end[kExpandItems], s_first[kExpandItems];
     __shared__ int32_t s_ent[kExpandBuf];
     const int64_t g = xcd_block(blockIdx.x, gridDim.x);
     if (g >= ng) return;
@@ -324,54 +328,72 @@ __global__ __launch_bounds__(64) void k_expand(int64_t ng, int64_t slot, const i
     const int64_t i0 = slot > 0 ? g * slot : ioff[g];
     const int64_t i1 = slot > 0 ? i0 + icnt[g] : ioff[g + 1];
     int32_t* dst = ent + off[g];
-    for (int64_t c0 = i0; c0 < i1; c0 += 64) {
-        const int64_t ii = c0 + lane;
-        int32_t v = 0, first = 0, n = 0;
-        if (ii < i1) {
-            v = items[ii];
-            if (v >= 0) {
-                const NodeRange r = rng[v];
-                first = r.first;
-                n = r.count;
-            } else {
-                first = v;
-                n = 1;
+    for (int64_t c0 = i0; c0 < i1; c0 += kExpandItems) {
+        // item q = 64 k + lane of the batch
+        int32_t v[kExpandPer], first[kExpandPer], n[kExpandPer];
+#pragma unroll
+        for (int k = 0; k < kExpandPer; ++k) {
+            const int64_t ii = c0 + 64 * k + lane;
+            v[k] = ii < i1 ? items[ii] : INT32_MIN;
+        }
+#pragma unroll
+        for (int k = 0; k < kExpandPer; ++k) {
+            first[k] = v[k];
+            n[k] = v[k] == INT32_MIN ? 0 : 1;
+            if (v[k] >= 0) {
+                const NodeRange r = rng[v[k]];
+                first[k] = r.first;
+                n[k] = r.count;
             }
         }
-        int incl = n;
+        uint64_t leafmask[kExpandPer];
+        int carry = 0;
+        int incl[kExpandPer];
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int u = __shfl_up(incl, o, 64);
-            if (lane >= o) incl += u;
+        for (int k = 0; k < kExpandPer; ++k) {
+            int x = n[k];
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int u = __shfl_up(x, o, 64);
+                if (lane >= o) x += u;
+            }
+            incl[k] = x + carry;
+            carry += __shfl(x, 63, 64);
+            leafmask[k] = __ballot(v[k] >= 0 && n[k] > 0);
         }
-        const int total = __shfl(incl, 63, 64);
+        const int total = carry;
         if (total <= kExpandBuf) {
             // a leaf's entries are first, first + 1, ...; a cell's only
             // entry is its code
-            const int b = incl - n;
-            if (v >= 0) {
-                for (int q = 0; q < n; ++q) s_ent[b + q] = first + q;
-            } else if (n > 0) {
-                s_ent[b] = first;
+#pragma unroll
+            for (int k = 0; k < kExpandPer; ++k) {
+                const int b = incl[k] - n[k];
+                if (v[k] >= 0) {
+                    for (int q = 0; q < n[k]; ++q) s_ent[b + q] = first[k] + q;
+                } else if (n[k] > 0) {
+                    s_ent[b] = first[k];
+                }
             }
             __syncthreads();
             for (int k = lane; k < total; k += 64) dst[k] = s_ent[k];
             __syncthreads();
         } else {
+#pragma unroll
+            for (int k = 0; k < kExpandPer; ++k) {
+                s_end[64 * k + lane] = incl[k];
+                s_first[64 * k + lane] = v[k] >= 0 ? first[k] - (incl[k] - n[k]) : first[k];
+            }
             __syncthreads();
-            s_end[lane] = incl;
-            s_first[lane] = v >= 0 ? first - (incl - n) : first;
-            __syncthreads();
-            const uint64_t leafmask = __ballot(v >= 0 && n > 0);
-            for (int k = lane; k < total; k += 64) {
-                // first item whose end exceeds k
+            for (int e = lane; e < total; e += 64) {
+                // first item whose end exceeds e
                 int lo = 0;
 #pragma unroll
-                for (int step = 32; step >= 1; step >>= 1)
-                    if (s_end[lo + step - 1] <= k) lo += step;
+                for (int step = kExpandItems / 2; step >= 1; step >>= 1)
+                    if (s_end[lo + step - 1] <= e) lo += step;
                 const int32_t f = s_first[lo];
-                dst[k] = ((leafmask >> lo) & 1ull) ? f + k : f;
+                dst[e] = ((leafmask[lo >> 6] >> (lo & 63)) & 1ull) ? f + e : f;
             }
+            __syncthreads();
         }
         dst += total;
     }
