@@ -1,5 +1,12 @@
 // Steps a1-a2: periodic wrap, 63-bit Morton keys, stable LSD radix sort of
 // (key, input index), gather of the sorted SoA particle arrays.
+//
+// The sort moves 32-bit words: four passes order (low word, index) pairs by
+// the low word, the high words are then gathered in that order, and four
+// more passes order (high word, index) pairs by the high word.  Each pass is
+// stable, so the result is the order of (key, input index) -- the order of
+// eight passes over the whole 64-bit key -- with 8 instead of 12 bytes
+// moved per element and pass.
 #include "common.h"
 
 namespace srf {
@@ -32,7 +39,8 @@ __device__ __forceinline__ uint64_t grid21(double u) {
 
 __global__ void k_keys(int64_t n, const double* __restrict__ x, const double* __restrict__ y,
                        const double* __restrict__ z, int64_t ps, const double* __restrict__ m, int64_t ms,
-                       uint64_t* __restrict__ keys, int32_t* __restrict__ vals, int32_t* __restrict__ flag) {
+                       uint32_t* __restrict__ klo, uint32_t* __restrict__ klo2, uint32_t* __restrict__ khi,
+                       int32_t* __restrict__ vals, int32_t* __restrict__ flag) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     double a = x[i * ps], b = y[i * ps], c = z[i * ps], mm = m[i * ms];
@@ -41,7 +49,10 @@ __global__ void k_keys(int64_t n, const double* __restrict__ x, const double* __
     if (!(isfinite(mm) && mm > 0.0)) bad |= 2;
     if (bad) atomicOr(flag, bad);
     uint64_t kx = grid21(wrap01(a)), ky = grid21(wrap01(b)), kz = grid21(wrap01(c));
-    keys[i] = (spread3(kx) << 2) | (spread3(ky) << 1) | spread3(kz);
+    const uint64_t key = (spread3(kx) << 2) | (spread3(ky) << 1) | spread3(kz);
+    klo[i] = (uint32_t)key;    // one copy is sorted, the other kept in input order
+    klo2[i] = (uint32_t)key;
+    khi[i] = (uint32_t)(key >> 32);
     vals[i] = (int32_t)i;
 }
 
@@ -61,7 +72,7 @@ constexpr int kTile = kThreads * kItems;  // keys per block
 constexpr int kDigits = 256;
 static_assert(kThreads == kDigits, "one digit per thread in the per-digit steps");
 
-__global__ __launch_bounds__(kThreads) void k_hist(int64_t n, const uint64_t* __restrict__ keys, int shift,
+__global__ __launch_bounds__(kThreads) void k_hist(int64_t n, const uint32_t* __restrict__ keys, int shift,
                                                    int64_t tiles, int32_t* __restrict__ counts) {
     __shared__ int32_t h[kWaves][kDigits];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -69,11 +80,11 @@ __global__ __launch_bounds__(kThreads) void k_hist(int64_t n, const uint64_t* __
     for (int w = 0; w < kWaves; ++w) h[w][tid] = 0;
     __syncthreads();
     const int64_t base = blockIdx.x * (int64_t)kTile + wid * kWaveKeys + lane;
-    uint64_t k[kItems];
+    uint32_t k[kItems];
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
         const int64_t i = base + 64 * r;
-        k[r] = i < n ? keys[i] : 0;
+        k[r] = i < n ? keys[i] : 0u;
     }
 #pragma unroll
     for (int r = 0; r < kItems; ++r)
@@ -134,8 +145,8 @@ __global__ __launch_bounds__(kThreads) void k_digit_scan(int64_t tiles, int32_t*
 // plus the number of such lanes below it.  Tile position: digits in order,
 // within a digit the waves in order, then the rank.  The tile is reordered
 // in LDS so that each digit's run is written contiguously.
-__global__ __launch_bounds__(kThreads) void k_scatter(int64_t n, const uint64_t* __restrict__ kin,
-                                                      const int32_t* __restrict__ vin, uint64_t* __restrict__ kout,
+__global__ __launch_bounds__(kThreads) void k_scatter(int64_t n, const uint32_t* __restrict__ kin,
+                                                      const int32_t* __restrict__ vin, uint32_t* __restrict__ kout,
                                                       int32_t* __restrict__ vout, int shift, int64_t tiles,
                                                       const int32_t* __restrict__ offsets,
                                                       const int32_t* __restrict__ dtot) {
@@ -143,7 +154,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(int64_t n, const uint64_t*
     __shared__ int32_t toff[kDigits];         // tile-local exclusive offset of each digit
     __shared__ int32_t gdst[kDigits];         // global position of the tile's first key of each digit
     __shared__ int32_t wsum[kWaves][2];
-    __shared__ uint64_t skey[kTile];
+    __shared__ uint32_t skey[kTile];
     __shared__ int32_t sval[kTile];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
 #pragma unroll
@@ -153,12 +164,12 @@ __global__ __launch_bounds__(kThreads) void k_scatter(int64_t n, const uint64_t*
     __syncthreads();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int64_t wbase = blockIdx.x * (int64_t)kTile + wid * kWaveKeys + lane;
-    uint64_t key[kItems];
+    uint32_t key[kItems];
     int32_t val[kItems], rank[kItems];
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
         const int64_t i = wbase + 64 * r;
-        key[r] = i < n ? kin[i] : 0;
+        key[r] = i < n ? kin[i] : 0u;
         val[r] = i < n ? vin[i] : 0;
     }
 #pragma unroll
@@ -238,7 +249,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(int64_t n, const uint64_t*
     for (int r = 0; r < kItems; ++r) {
         const int p = r * kThreads + tid;
         if (p < cnt) {
-            const uint64_t k = skey[p];
+            const uint32_t k = skey[p];
             const int d = (int)((k >> shift) & 0xff);
             const int64_t dst = (int64_t)gdst[d] + (p - toff[d]);
             if ((uint64_t)dst < (uint64_t)n) {   // always, by construction; never a stray store
@@ -247,6 +258,20 @@ __global__ __launch_bounds__(kThreads) void k_scatter(int64_t n, const uint64_t*
             }
         }
     }
+}
+
+// out[s] = in[perm[s]] (a word of every key in the order of perm)
+__global__ void k_gather_u32(int64_t n, const int32_t* __restrict__ perm, const uint32_t* __restrict__ in,
+                             uint32_t* __restrict__ out) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s < n) out[s] = in[perm[s]];
+}
+
+// The sorted keys from their sorted high words and the low words in input order.
+__global__ void k_join_keys(int64_t n, const int32_t* __restrict__ perm, const uint32_t* __restrict__ hi,
+                            const uint32_t* __restrict__ lo_in, uint64_t* __restrict__ keys) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s < n) keys[s] = ((uint64_t)hi[s] << 32) | lo_in[perm[s]];
 }
 
 __global__ void k_gather(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ x,
@@ -297,33 +322,43 @@ void gather_refit(const Tree& t, const double* x, const double* y, const double*
 void build_sorted(Tree& t, const double* x, const double* y, const double* z, int64_t ps, const double* m,
                   int64_t ms, int32_t* d_flag, hipStream_t st) {
     const int64_t n = t.n;
-    DevBuf<uint64_t> kb(n, st);
+    const int B = 256;
+    DevBuf<uint32_t> lo_in(n, st), hi_in(n, st), wa(n, st), wb(n, st);
     DevBuf<int32_t> vb(n, st);
     t.keys.alloc(n, st);
     t.perm.alloc(n, st);
-    hipLaunchKernelGGL(k_keys, dim3(grid_for(n, 256, 1 << 30)), dim3(256), 0, st, n, x, y, z, ps, m, ms,
-                       t.keys.get(), t.perm.get(), d_flag);
+    hipLaunchKernelGGL(k_keys, dim3(grid_for(n, B, 1 << 30)), dim3(B), 0, st, n, x, y, z, ps, m, ms, wa.get(),
+                       lo_in.get(), hi_in.get(), t.perm.get(), d_flag);
     SRF_HIP(hipGetLastError());
     const int64_t tiles = (n + kTile - 1) / kTile;
     DevBuf<int32_t> counts(kDigits * tiles, st);
     DevBuf<int32_t> dtot(kDigits, st);
-    uint64_t* ka = t.keys.get();
-    int32_t* va = t.perm.get();
-    uint64_t* kk = kb.get();
-    int32_t* vv = vb.get();
-    for (int pass = 0; pass < 8; ++pass) {
-        const int shift = 8 * pass;
-        hipLaunchKernelGGL(k_hist, dim3((unsigned)tiles), dim3(kThreads), 0, st, n, ka, shift, tiles, counts.get());
-        SRF_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_digit_scan, dim3(kDigits), dim3(kThreads), 0, st, tiles, counts.get(), dtot.get());
-        SRF_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_scatter, dim3((unsigned)tiles), dim3(kThreads), 0, st, n, ka, va, kk, vv, shift, tiles,
-                           counts.get(), dtot.get());
-        SRF_HIP(hipGetLastError());
-        std::swap(ka, kk);
-        std::swap(va, vv);
-    }
-    // eight passes: the result is back in t.keys / t.perm
+    // four stable passes of 8 bits over one word; returns where the result is
+    auto passes = [&](uint32_t* ka, uint32_t* kk, int32_t* va, int32_t* vv) {
+        for (int pass = 0; pass < 4; ++pass) {
+            const int shift = 8 * pass;
+            hipLaunchKernelGGL(k_hist, dim3((unsigned)tiles), dim3(kThreads), 0, st, n, ka, shift, tiles,
+                               counts.get());
+            SRF_HIP(hipGetLastError());
+            hipLaunchKernelGGL(k_digit_scan, dim3(kDigits), dim3(kThreads), 0, st, tiles, counts.get(), dtot.get());
+            SRF_HIP(hipGetLastError());
+            hipLaunchKernelGGL(k_scatter, dim3((unsigned)tiles), dim3(kThreads), 0, st, n, ka, va, kk, vv, shift,
+                               tiles, counts.get(), dtot.get());
+            SRF_HIP(hipGetLastError());
+            std::swap(ka, kk);
+            std::swap(va, vv);
+        }
+    };
+    // low words (an even number of passes: the (word, index) pairs end where
+    // they started, in wa / t.perm), then the high words in that order
+    passes(wa.get(), wb.get(), t.perm.get(), vb.get());
+    hipLaunchKernelGGL(k_gather_u32, dim3(grid_for(n, B, 1 << 30)), dim3(B), 0, st, n, t.perm.get(), hi_in.get(),
+                       wa.get());
+    SRF_HIP(hipGetLastError());
+    passes(wa.get(), wb.get(), t.perm.get(), vb.get());
+    hipLaunchKernelGGL(k_join_keys, dim3(grid_for(n, B, 1 << 30)), dim3(B), 0, st, n, t.perm.get(), wa.get(),
+                       lo_in.get(), t.keys.get());
+    SRF_HIP(hipGetLastError());
     t.px.alloc(n, st);
     t.py.alloc(n, st);
     t.pz.alloc(n, st);
