@@ -296,7 +296,9 @@ int srf_tree_info(const srf_tree* t, int64_t* n, int64_t* n_nodes, int64_t* n_gr
  * (first, level)): node_level, node_prefix (top 3*level key bits),
  * node_first, node_count [n_nodes]; groups in order of first: group_first,
  * group_count [n_groups], group_lo, group_hi [n_groups*3] (tight box of the
- * wrapped positions, x,y,z per group). */
+ * wrapped positions, x,y,z per group; after srf_tree_refit, of the images
+ * nearest each group's first particle).  Keys, permutation and cells are
+ * those of the build; a refit keeps them. */
 int srf_tree_export(const srf_tree* t, uint64_t* keys_sorted, int64_t* perm,
                     int32_t* node_level, uint64_t* node_prefix, int64_t* node_first, int64_t* node_count,
                     int64_t* group_first, int64_t* group_count, double* group_lo, double* group_hi);
