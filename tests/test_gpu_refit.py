@@ -236,3 +236,50 @@ def test_refit_with_an_unbounded_cell():
         assert np.array_equal(L[k], getattr(rt.lists, k)), k
     a = srf.short_range_force(tree, lists, p).cpu().numpy()
     check(a, rt.force(), rt.force_bound(U32), constant("force", False, max_list(rt)), "unbounded-cell force")
+
+
+@pytest.mark.parametrize("name", ["clustered-20000", "slab-4000"])
+def test_refit_potential(name):
+    """The short-range potential over refitted lists: rms relative error
+    against the oracle's refitted tree as for a fresh tree (1e-5 FP32,
+    1e-12 FP64; the terms are all of one sign)."""
+    ps, new = _cases()[name]
+    params = synth.Params(1.0, ps.params.r_cut, ps.params.eps, 0.7, 64, 16)
+    ot, rt = _oracle(ps, new, params)
+    ref = rt.potential()
+    for precision, tol in ((srf.FP32_REL, 1e-5), (srf.FP64, 1e-12)):
+        p, tree, lists, _, _ = _refit(ps, new, params, precision)
+        phi = srf.short_range_potential(tree, lists, p).cpu().numpy()
+        rel = np.abs(phi - ref) / np.abs(ref)
+        say(f"[gpu] refit potential {name} precision={precision}: rms {np.sqrt(np.mean(rel ** 2)):.3e}")
+        assert np.sqrt(np.mean(rel ** 2)) <= tol
+
+
+def test_integrator_with_tree_reuse_tracks_rebuilding():
+    """At theta = 0.5 the step that refits the first PP cycle's tree in the
+    second differs from the step that rebuilds it only by the tree's
+    truncation error: after four steps the two trajectories agree far
+    below the displacement they took, and both conserve what the other
+    does (the PM and kick/drift parts are identical)."""
+    rng = np.random.default_rng(21)
+    n = 4096
+    x0 = rng.random((n, 3))
+    v0 = 0.05 * rng.standard_normal((n, 3))
+    m = torch.full((n,), 1.0 / n, dtype=torch.float64, device="cuda")
+    p = srf.Params(G=1.0, r_cut=0.1, eps=1e-2, theta=0.5)
+    out = []
+    for reuse in (True, False):
+        x = torch.tensor(x0, dtype=torch.float64, device="cuda")
+        v = torch.tensor(v0, dtype=torch.float64, device="cuda")
+        it = srf.TreePMIntegrator(p, 16, reuse_tree=reuse)
+        for _ in range(4):
+            it.step(x, v, m, 2e-3)
+        torch.cuda.synchronize()
+        out.append((x.cpu().numpy(), v.cpu().numpy()))
+    dx = out[0][0] - out[1][0]
+    dx = np.max(np.abs(dx - np.rint(dx)))
+    moved = out[1][0] - x0
+    moved = np.max(np.abs(moved - np.rint(moved)))
+    dv = np.max(np.abs(out[0][1] - out[1][1]))
+    say(f"[gpu] reuse vs rebuild after 4 steps: max |dx| {dx:.3e} (moved {moved:.3e}), max |dv| {dv:.3e}")
+    assert dx <= 1e-3 * moved and dv <= 1e-2 * np.max(np.abs(out[1][1] - v0))
