@@ -1,12 +1,12 @@
 // Steps a1-a2: periodic wrap, 63-bit Morton keys, stable LSD radix sort of
 // (key, input index), gather of the sorted SoA particle arrays.
 //
-// The sort moves 32-bit words: four passes order (low word, index) pairs by
-// the low word, the high words are then gathered in that order, and four
-// more passes order (high word, index) pairs by the high word.  Each pass is
-// stable, so the result is the order of (key, input index) -- the order of
-// eight passes over the whole 64-bit key -- with 8 instead of 12 bytes
-// moved per element and pass.
+// The sort moves 32-bit words: four passes order (low word; high word,
+// index) by the low word, four more order (high word; index) by the high
+// word.  Each pass is stable, so the result is the order of (key, input
+// index) -- that of eight passes over the whole 64-bit key -- with 12 and
+// then 8 instead of 12 bytes moved per element and pass.  The sorted keys
+// are recomputed from the sorted positions by the final gather.
 #include "common.h"
 
 namespace srf {
@@ -39,8 +39,8 @@ __device__ __forceinline__ uint64_t grid21(double u) {
 
 __global__ void k_keys(int64_t n, const double* __restrict__ x, const double* __restrict__ y,
                        const double* __restrict__ z, int64_t ps, const double* __restrict__ m, int64_t ms,
-                       uint32_t* __restrict__ klo, uint32_t* __restrict__ klo2, uint32_t* __restrict__ khi,
-                       int32_t* __restrict__ vals, int32_t* __restrict__ flag) {
+                       uint32_t* __restrict__ klo, uint32_t* __restrict__ khi, int32_t* __restrict__ vals,
+                       int32_t* __restrict__ flag) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     double a = x[i * ps], b = y[i * ps], c = z[i * ps], mm = m[i * ms];
@@ -50,8 +50,7 @@ __global__ void k_keys(int64_t n, const double* __restrict__ x, const double* __
     if (bad) atomicOr(flag, bad);
     uint64_t kx = grid21(wrap01(a)), ky = grid21(wrap01(b)), kz = grid21(wrap01(c));
     const uint64_t key = (spread3(kx) << 2) | (spread3(ky) << 1) | spread3(kz);
-    klo[i] = (uint32_t)key;    // one copy is sorted, the other kept in input order
-    klo2[i] = (uint32_t)key;
+    klo[i] = (uint32_t)key;
     khi[i] = (uint32_t)(key >> 32);
     vals[i] = (int32_t)i;
 }
@@ -145,9 +144,11 @@ __global__ __launch_bounds__(kThreads) void k_digit_scan(int64_t tiles, int32_t*
 // plus the number of such lanes below it.  Tile position: digits in order,
 // within a digit the waves in order, then the rank.  The tile is reordered
 // in LDS so that each digit's run is written contiguously.
+template <bool V2>
 __global__ __launch_bounds__(kThreads) void k_scatter(int64_t n, const uint32_t* __restrict__ kin,
                                                       const int32_t* __restrict__ vin, uint32_t* __restrict__ kout,
-                                                      int32_t* __restrict__ vout, int shift, int64_t tiles,
+                                                      int32_t* __restrict__ vout, const uint32_t* __restrict__ v2in,
+                                                      uint32_t* __restrict__ v2out, int shift, int64_t tiles,
                                                       const int32_t* __restrict__ offsets,
                                                       const int32_t* __restrict__ dtot) {
     __shared__ int32_t wc[kWaves][kDigits];   // running counts, then the waves' exclusive prefix
@@ -156,6 +157,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(int64_t n, const uint32_t*
     __shared__ int32_t wsum[kWaves][2];
     __shared__ uint32_t skey[kTile];
     __shared__ int32_t sval[kTile];
+    __shared__ uint32_t sval2[V2 ? kTile : 1];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) wc[w][tid] = 0;
@@ -164,13 +166,14 @@ __global__ __launch_bounds__(kThreads) void k_scatter(int64_t n, const uint32_t*
     __syncthreads();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int64_t wbase = blockIdx.x * (int64_t)kTile + wid * kWaveKeys + lane;
-    uint32_t key[kItems];
+    uint32_t key[kItems], val2[kItems];
     int32_t val[kItems], rank[kItems];
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
         const int64_t i = wbase + 64 * r;
         key[r] = i < n ? kin[i] : 0u;
         val[r] = i < n ? vin[i] : 0;
+        val2[r] = (V2 && i < n) ? v2in[i] : 0u;
     }
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
@@ -240,6 +243,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(int64_t n, const uint32_t*
         if ((unsigned)p < (unsigned)kTile) {
             skey[p] = key[r];
             sval[p] = val[r];
+            if (V2) sval2[p] = val2[r];
         }
     }
     __syncthreads();
@@ -255,36 +259,27 @@ __global__ __launch_bounds__(kThreads) void k_scatter(int64_t n, const uint32_t*
             if ((uint64_t)dst < (uint64_t)n) {   // always, by construction; never a stray store
                 kout[dst] = k;
                 vout[dst] = sval[p];
+                if (V2) v2out[dst] = sval2[p];
             }
         }
     }
 }
 
-// out[s] = in[perm[s]] (a word of every key in the order of perm)
-__global__ void k_gather_u32(int64_t n, const int32_t* __restrict__ perm, const uint32_t* __restrict__ in,
-                             uint32_t* __restrict__ out) {
-    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (s < n) out[s] = in[perm[s]];
-}
-
-// The sorted keys from their sorted high words and the low words in input order.
-__global__ void k_join_keys(int64_t n, const int32_t* __restrict__ perm, const uint32_t* __restrict__ hi,
-                            const uint32_t* __restrict__ lo_in, uint64_t* __restrict__ keys) {
-    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (s < n) keys[s] = ((uint64_t)hi[s] << 32) | lo_in[perm[s]];
-}
-
+// The sorted particles, and their keys computed again from the wrapped
+// positions exactly as k_keys computed them.
 __global__ void k_gather(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ x,
                          const double* __restrict__ y, const double* __restrict__ z, int64_t ps,
                          const double* __restrict__ m, int64_t ms, double* __restrict__ px, double* __restrict__ py,
-                         double* __restrict__ pz, double* __restrict__ pm) {
+                         double* __restrict__ pz, double* __restrict__ pm, uint64_t* __restrict__ keys) {
     int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= n) return;
     int64_t i = perm[s];
-    px[s] = wrap01(x[i * ps]);
-    py[s] = wrap01(y[i * ps]);
-    pz[s] = wrap01(z[i * ps]);
+    const double u = wrap01(x[i * ps]), v = wrap01(y[i * ps]), w = wrap01(z[i * ps]);
+    px[s] = u;
+    py[s] = v;
+    pz[s] = w;
     pm[s] = m[i * ms];
+    keys[s] = (spread3(grid21(u)) << 2) | (spread3(grid21(v)) << 1) | spread3(grid21(w));
 }
 
 // The same gather for a tree reused at new positions, with the input checks
@@ -323,48 +318,48 @@ void build_sorted(Tree& t, const double* x, const double* y, const double* z, in
                   int64_t ms, int32_t* d_flag, hipStream_t st) {
     const int64_t n = t.n;
     const int B = 256;
-    DevBuf<uint32_t> lo_in(n, st), hi_in(n, st), wa(n, st), wb(n, st);
+    DevBuf<uint32_t> ka(n, st), kb(n, st), ha(n, st), hb(n, st);
     DevBuf<int32_t> vb(n, st);
     t.keys.alloc(n, st);
     t.perm.alloc(n, st);
-    hipLaunchKernelGGL(k_keys, dim3(grid_for(n, B, 1 << 30)), dim3(B), 0, st, n, x, y, z, ps, m, ms, wa.get(),
-                       lo_in.get(), hi_in.get(), t.perm.get(), d_flag);
+    hipLaunchKernelGGL(k_keys, dim3(grid_for(n, B, 1 << 30)), dim3(B), 0, st, n, x, y, z, ps, m, ms, ka.get(),
+                       ha.get(), t.perm.get(), d_flag);
     SRF_HIP(hipGetLastError());
     const int64_t tiles = (n + kTile - 1) / kTile;
     DevBuf<int32_t> counts(kDigits * tiles, st);
     DevBuf<int32_t> dtot(kDigits, st);
-    // four stable passes of 8 bits over one word; returns where the result is
-    auto passes = [&](uint32_t* ka, uint32_t* kk, int32_t* va, int32_t* vv) {
-        for (int pass = 0; pass < 4; ++pass) {
-            const int shift = 8 * pass;
-            hipLaunchKernelGGL(k_hist, dim3((unsigned)tiles), dim3(kThreads), 0, st, n, ka, shift, tiles,
-                               counts.get());
-            SRF_HIP(hipGetLastError());
-            hipLaunchKernelGGL(k_digit_scan, dim3(kDigits), dim3(kThreads), 0, st, tiles, counts.get(), dtot.get());
-            SRF_HIP(hipGetLastError());
-            hipLaunchKernelGGL(k_scatter, dim3((unsigned)tiles), dim3(kThreads), 0, st, n, ka, va, kk, vv, shift,
-                               tiles, counts.get(), dtot.get());
-            SRF_HIP(hipGetLastError());
-            std::swap(ka, kk);
-            std::swap(va, vv);
-        }
+    // one stable pass of 8 bits over the words k (with index v and, for the
+    // low word, the high word h carried along)
+    auto pass = [&](int shift, const uint32_t* k, uint32_t* k2, const int32_t* v, int32_t* v2, const uint32_t* h,
+                    uint32_t* h2) {
+        hipLaunchKernelGGL(k_hist, dim3((unsigned)tiles), dim3(kThreads), 0, st, n, k, shift, tiles, counts.get());
+        SRF_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_digit_scan, dim3(kDigits), dim3(kThreads), 0, st, tiles, counts.get(), dtot.get());
+        SRF_HIP(hipGetLastError());
+        if (h)
+            hipLaunchKernelGGL(k_scatter<true>, dim3((unsigned)tiles), dim3(kThreads), 0, st, n, k, v, k2, v2, h, h2,
+                               shift, tiles, counts.get(), dtot.get());
+        else
+            hipLaunchKernelGGL(k_scatter<false>, dim3((unsigned)tiles), dim3(kThreads), 0, st, n, k, v, k2, v2,
+                               (const uint32_t*)nullptr, (uint32_t*)nullptr, shift, tiles, counts.get(), dtot.get());
+        SRF_HIP(hipGetLastError());
     };
-    // low words (an even number of passes: the (word, index) pairs end where
-    // they started, in wa / t.perm), then the high words in that order
-    passes(wa.get(), wb.get(), t.perm.get(), vb.get());
-    hipLaunchKernelGGL(k_gather_u32, dim3(grid_for(n, B, 1 << 30)), dim3(B), 0, st, n, t.perm.get(), hi_in.get(),
-                       wa.get());
-    SRF_HIP(hipGetLastError());
-    passes(wa.get(), wb.get(), t.perm.get(), vb.get());
-    hipLaunchKernelGGL(k_join_keys, dim3(grid_for(n, B, 1 << 30)), dim3(B), 0, st, n, t.perm.get(), wa.get(),
-                       lo_in.get(), t.keys.get());
-    SRF_HIP(hipGetLastError());
+    // low word: passes a -> b -> a -> b -> a (pairs of passes return to the
+    // first buffers); then the high word, already in that order, in ha
+    for (int p = 0; p < 4; p += 2) {
+        pass(8 * p, ka.get(), kb.get(), t.perm.get(), vb.get(), ha.get(), hb.get());
+        pass(8 * (p + 1), kb.get(), ka.get(), vb.get(), t.perm.get(), hb.get(), ha.get());
+    }
+    for (int p = 0; p < 4; p += 2) {
+        pass(8 * p, ha.get(), hb.get(), t.perm.get(), vb.get(), nullptr, nullptr);
+        pass(8 * (p + 1), hb.get(), ha.get(), vb.get(), t.perm.get(), nullptr, nullptr);
+    }
     t.px.alloc(n, st);
     t.py.alloc(n, st);
     t.pz.alloc(n, st);
     t.pm.alloc(n, st);
-    hipLaunchKernelGGL(k_gather, dim3(grid_for(n, 256, 1 << 30)), dim3(256), 0, st, n, t.perm.get(), x, y, z, ps, m,
-                       ms, t.px.get(), t.py.get(), t.pz.get(), t.pm.get());
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(n, B, 1 << 30)), dim3(B), 0, st, n, t.perm.get(), x, y, z, ps, m,
+                       ms, t.px.get(), t.py.get(), t.pz.get(), t.pm.get(), t.keys.get());
     SRF_HIP(hipGetLastError());
 }
 
