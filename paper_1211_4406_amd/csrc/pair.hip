@@ -15,11 +15,12 @@
 //   g(xi) = 1 + xi^3 (-8/5 + xi^2 (8/5 + xi (-1/2 + xi (-12/35 + 3/20 xi))))   xi <= 1
 //   g(xi) = t^5 (7 xi^3 + 22 xi^2 + 10 xi + 4) / 140,  t = 2 - xi              1 <= xi <= 2
 // (the second line is the printed zeta-branch polynomial in factored form;
-// it keeps relative accuracy as g -> 0).  t is clamped to [0,1], so a pair
-// with xi >= 2 in working precision contributes exactly zero: no separate
-// cutoff test is needed.  The polynomials are evaluated in r with the
-// powers of k = 2/r_cut folded into the coefficients; r is the unsoftened
-// distance.
+// it keeps relative accuracy as g -> 0).  The kernels evaluate both lines
+// as one expression (see the arithmetic below) whose factors are clamped so
+// that a pair with xi >= 2 in working precision contributes exactly zero:
+// no separate cutoff test is needed.  The polynomials are evaluated in r
+// with the powers of k = 2/r_cut folded into the coefficients; r is the
+// unsoftened distance.
 #include <cmath>
 #include <mutex>
 #include <string>
@@ -32,14 +33,25 @@ namespace {
 constexpr int kTile = 256;
 
 // ------------------------------------------------------------ arithmetic
+// The two pieces of eq. (cutoff) differ on [0,1] by a polynomial that
+// vanishes to sixth order at xi = 1:
+//   g_[0,1](xi) - g_[1,2](xi) = (1 - xi)^6 (3/35 + 18/35 xi + xi^2/5),
+// so with T = 1 - xi/2 and W = 1 - xi, each clamped to [0,1] (T = 0 from
+// xi = 2 on, W = 0 from xi = 1 on),
+//   g = 32 T^5 R + W^6 Q,  R = (7 xi^3 + 22 xi^2 + 10 xi + 4)/140,
+// one expression for every xi with no branch select; both terms are
+// nonnegative on [0,2], so the sum loses no accuracy.  The kernels carry
+// g/32 (the coefficients absorb the 1/32) and scale by 32 when they convert
+// to FP64, which is exact.  A far source (xi >= 1 for every target) takes
+// only the T term.
+constexpr double kGScale = 32.0;
+
 template <class T>
 struct Coef {
-    T A3, A5, A6, A7, A8;      // g on [0,1]: 1 + r^3 (A3 + r^2 (A5 + r (A6 + r (A7 + r A8))))
-    T R0, R1, R2, R3;          // (7 xi^3 + 22 xi^2 + 10 xi + 4) / 140 in r
-    T C1, C3, C4, C5, C6;      // k^2 g'(xi)/xi on [0,1], in r
-    T E0, E1, E2;              // k^2 g'(xi)/xi on [1,2] = -t^4 (E2 r^2 + E1 r + E0)
-    T k, eps2, rh2;            // k = 2/r_cut, eps^2, (r_cut/2)^2
-    T m3;                      // -3 (not an inline constant of the ISA)
+    T R0, R1, R2, R3;          // R in r
+    T Q0, Q1, Q2;              // Q / 32 in r
+    T kh, k;                   // k / 2, k = 2/r_cut
+    T eps2;                    // eps^2
     T heps2;                   // -eps^2 / 2
     double far2;               // (r_cut/2)^2 in FP64, for the near/far split of a tile
 };
@@ -47,31 +59,18 @@ struct Coef {
 template <class T>
 Coef<T> make_coef(double rc, double eps) {
     const double k = 2.0 / rc;
-    const double k2 = k * k, k3 = k2 * k, k4 = k3 * k, k5 = k4 * k, k6 = k5 * k, k7 = k6 * k, k8 = k7 * k;
+    const double k2 = k * k, k3 = k2 * k;
     Coef<T> c;
-    c.A3 = (T)(-8.0 / 5.0 * k3);
-    c.A5 = (T)(8.0 / 5.0 * k5);
-    c.A6 = (T)(-0.5 * k6);
-    c.A7 = (T)(-12.0 / 35.0 * k7);
-    c.A8 = (T)(3.0 / 20.0 * k8);
     c.R0 = (T)(4.0 / 140.0);
     c.R1 = (T)(10.0 / 140.0 * k);
     c.R2 = (T)(22.0 / 140.0 * k2);
     c.R3 = (T)(7.0 / 140.0 * k3);
-    // dg/dxi on [0,1] = -24/5 xi^2 + 8 xi^4 - 3 xi^5 - 12/5 xi^6 + 6/5 xi^7
-    c.C1 = (T)(-24.0 / 5.0 * k3);
-    c.C3 = (T)(8.0 * k5);
-    c.C4 = (T)(-3.0 * k6);
-    c.C5 = (T)(-12.0 / 5.0 * k7);
-    c.C6 = (T)(6.0 / 5.0 * k8);
-    // dg/dxi on [1,2] = -xi (xi - 2)^4 (2 xi^2 + 4 xi - 1) / 5
-    c.E0 = (T)(-0.2 * k2);
-    c.E1 = (T)(0.8 * k3);
-    c.E2 = (T)(0.4 * k4);
+    c.Q0 = (T)(3.0 / 35.0 / 32.0);
+    c.Q1 = (T)(18.0 / 35.0 / 32.0 * k);
+    c.Q2 = (T)(0.2 / 32.0 * k2);
+    c.kh = (T)(0.5 * k);
     c.k = (T)k;
     c.eps2 = (T)(eps * eps);
-    c.rh2 = (T)(0.25 * rc * rc);
-    c.m3 = (T)(-3.0);
     c.heps2 = (T)(-0.5 * eps * eps);
     c.far2 = 0.25 * rc * rc;
     return c;
@@ -102,11 +101,9 @@ __device__ __forceinline__ double pin_(double x) {
 template <class T>
 __device__ __forceinline__ Coef<T> pinned(const Coef<T>& a) {
     Coef<T> c;
-    c.A3 = pin_(a.A3); c.A5 = pin_(a.A5); c.A6 = pin_(a.A6); c.A7 = pin_(a.A7); c.A8 = pin_(a.A8);
     c.R0 = pin_(a.R0); c.R1 = pin_(a.R1); c.R2 = pin_(a.R2); c.R3 = pin_(a.R3);
-    c.C1 = pin_(a.C1); c.C3 = pin_(a.C3); c.C4 = pin_(a.C4); c.C5 = pin_(a.C5); c.C6 = pin_(a.C6);
-    c.E0 = pin_(a.E0); c.E1 = pin_(a.E1); c.E2 = pin_(a.E2);
-    c.k = pin_(a.k); c.eps2 = pin_(a.eps2); c.rh2 = pin_(a.rh2); c.m3 = pin_(a.m3); c.heps2 = pin_(a.heps2);
+    c.Q0 = pin_(a.Q0); c.Q1 = pin_(a.Q1); c.Q2 = pin_(a.Q2);
+    c.kh = pin_(a.kh); c.k = pin_(a.k); c.eps2 = pin_(a.eps2); c.heps2 = pin_(a.heps2);
     c.far2 = a.far2;
     return c;
 }
@@ -118,20 +115,15 @@ struct Vec4<float> { using type = float4; };
 template <>
 struct Vec4<double> { using type = double4; };
 
-// g for one pair: the [0,1] polynomial or the factored [1,2] form (0 at
-// and beyond xi = 2 through the clamp of t).
+// g/32 for one pair, from r (0 at and beyond xi = 2 through the clamp of T).
 template <class T>
-__device__ __forceinline__ T cutoff_g(T r, T r2, const Coef<T>& c, T& t) {
-    t = sat_(fma_(r, -c.k, T(2)));
-    T u = fma_(r, c.A8, c.A7);
-    u = fma_(r, u, c.A6);
-    u = fma_(r, u, c.A5);
-    u = fma_(r2, u, c.A3);
-    const T g1 = fma_(r2 * r, u, T(1));
+__device__ __forceinline__ T cutoff_g(T r, const Coef<T>& c) {
+    const T t = sat_(fma_(r, -c.kh, T(1)));
+    const T w = sat_(fma_(r, -c.k, T(1)));
     const T R = fma_(fma_(fma_(r, c.R3, c.R2), r, c.R1), r, c.R0);
-    const T t2 = t * t;
-    const T g2 = (t2 * t2) * (t * R);
-    return r2 < c.rh2 ? g1 : g2;
+    const T Q = fma_(fma_(r, c.Q2, c.Q1), r, c.Q0);
+    const T t2 = t * t, w2 = w * w;
+    return fma_((w2 * w2) * w2, Q, (t2 * t2) * (t * R));
 }
 
 // FP32 partial sums of one target over a tile.  With COMP each component
@@ -149,6 +141,12 @@ struct Acc {
         } else {
             a += v;
         }
+    }
+    // the partials, times 32 (g/32 was summed), added to FP64 totals
+    __device__ __forceinline__ void flush(double& sx, double& sy, double& sz) const {
+        sx += kGScale * (COMP ? (double)x - (double)cx : (double)x);
+        sy += kGScale * (COMP ? (double)y - (double)cy : (double)y);
+        sz += kGScale * (COMP ? (double)z - (double)cz : (double)z);
     }
     __device__ __forceinline__ void add(T f, T dx, T dy, T dz) {
         if (COMP) {
@@ -168,15 +166,16 @@ struct Acc {
 // relative error is y^2/8 + O(y^3) with y = eps^2 / s^2 <= (2 eps / r_cut)^2
 // for far pairs (s >= r_cut / 2); the host selects RS only when that bound
 // keeps the error below half an FP32 ulp.  Otherwise r = sqrt(r^2).
-template <class T, bool RS>
-__device__ __forceinline__ T far_r(T r2, T s2, T rinv, const Coef<T>& c) {
+template <class T, bool RS, class C>
+__device__ __forceinline__ T far_r(T r2, T s2, T rinv, const C& c) {
     return RS ? fma_(c.heps2, rinv, s2 * rinv) : sqrt_(r2);
 }
 
 // Force of one source (offset p.xyz, mass p.w) on one target (xi, yi, zi),
-// accumulated into acc.  NEAR selects the full cutoff function; otherwise
-// the source lies at xi >= 1 from the target, g = t^5 R, and the factor
-// m s^-3 t^5 R is formed as m (q^2)(q t)(t R) with q = t s^-1.
+// divided by 32, accumulated into acc.  NEAR selects the full cutoff
+// function; otherwise the source lies at xi >= 1 from the target,
+// g/32 = T^5 R, and the factor m s^-3 T^5 R is formed as m (q^2)(q T)(T R)
+// with q = T s^-1.
 template <class T, class V4, bool NEAR, bool COMP, bool RS>
 __device__ __forceinline__ void pair_force(const V4& p, T xi, T yi, T zi, const Coef<T>& c, Acc<T, COMP>& acc) {
     const T dx = p.x - xi, dy = p.y - yi, dz = p.z - zi;
@@ -188,11 +187,10 @@ __device__ __forceinline__ void pair_force(const V4& p, T xi, T yi, T zi, const 
     const T r = NEAR ? sqrt_(r2) : far_r<T, RS>(r2, s2, rinv, c);
     T f;
     if (NEAR) {
-        T t;
-        const T g = cutoff_g(r, r2, c, t);
+        const T g = cutoff_g(r, c);
         f = (p.w * rinv) * (rinv * rinv) * g;
     } else {
-        const T t = sat_(fma_(r, -c.k, T(2)));
+        const T t = sat_(fma_(r, -c.kh, T(1)));
         const T R = fma_(fma_(fma_(r, c.R3, c.R2), r, c.R1), r, c.R0);
         const T q = t * rinv;
         f = p.w * ((q * q) * ((q * t) * (t * R)));
@@ -311,15 +309,11 @@ __device__ __forceinline__ void force_segment(const V4* tile, int a, int b, int 
 #pragma unroll
             for (int u = 0; u < U; ++u) pair_force<T, V4, NEAR, COMP, RS>(pp[u], xi, yi, zi, c, acc);
         }
-        sx += COMP ? (double)acc.x - (double)acc.cx : (double)acc.x;
-        sy += COMP ? (double)acc.y - (double)acc.cy : (double)acc.y;
-        sz += COMP ? (double)acc.z - (double)acc.cz : (double)acc.z;
+        acc.flush(sx, sy, sz);
     }
     Acc<T, COMP> acc;
     for (int k = kk + st; k < b; k += S, tp += S) pair_force<T, V4, NEAR, COMP, RS>(tp[0], xi, yi, zi, c, acc);
-    sx += COMP ? (double)acc.x - (double)acc.cx : (double)acc.x;
-    sy += COMP ? (double)acc.y - (double)acc.cy : (double)acc.y;
-    sz += COMP ? (double)acc.z - (double)acc.cz : (double)acc.z;
+    acc.flush(sx, sy, sz);
 }
 
 struct GroupArgs {
@@ -546,35 +540,88 @@ __global__ __launch_bounds__(64) void k_potential(GroupArgs ga, Src src, PotCoef
 //   dL/dx_i -= mu V,   dL/dy_src += mu V,   dL/dmu_src += phi (d . w).
 // A self pair (the target itself in its list; the force sum is over j != i)
 // gets s^-1 = 0, so phi and psi vanish.
-// phi = s^-3 g and psi = phi'(r) / r = s^-3 (h - 3 s^-2 g), h = k^2 g'(xi)/xi,
-// from r^2, r and s^-1 (s^2 = r^2 + eps^2).  Without NEAR the source lies
-// at xi >= 1 from the target and only the [1,2] forms of g and g' are taken.
+// phi = s^-3 g and psi = phi'(r) / r = s^-3 (h - 3 s^-2 g), h = k^2 g'(xi)/xi.
+// With g in the one-expression form of the force kernel (T and W as there),
+// the derivatives of the two pieces of eq. (cutoff) differ on [0,1] by
+//   (g'_[0,1] - g'_[1,2]) / xi = (1 - xi)^5 (-16/5 - 8/5 xi),
+// so h = -16 T^4 P + W^5 L with P = k^2 (2 xi^2 + 4 xi - 1)/5 and L = k^2
+// times the polynomial above.  The kernel carries phi/32 and psi/32 and
+// scales by 32 in FP64.  A far source takes only the T terms.
+template <class T>
+struct AdjCoef {
+    T R0, R1, R2, R3;          // R in r
+    T P0, P1, P2;              // P / 2 in r
+    T Q0, Q1, Q2;              // Q / 32 in r
+    T L0, L1;                  // k^2 L / 32 in r
+    T kh, k;                   // k / 2, k = 2 / r_cut
+    T eps2, heps2, m3;         // eps^2, -eps^2 / 2, -3
+    double far2;               // (r_cut/2)^2 in FP64, for the near/far split of a tile
+};
+
+template <class T>
+AdjCoef<T> make_adj_coef(double rc, double eps) {
+    const double k = 2.0 / rc;
+    const double k2 = k * k, k3 = k2 * k, k4 = k3 * k;
+    AdjCoef<T> c;
+    c.R0 = (T)(4.0 / 140.0);
+    c.R1 = (T)(10.0 / 140.0 * k);
+    c.R2 = (T)(22.0 / 140.0 * k2);
+    c.R3 = (T)(7.0 / 140.0 * k3);
+    c.P0 = (T)(-0.1 * k2);
+    c.P1 = (T)(0.4 * k3);
+    c.P2 = (T)(0.2 * k4);
+    c.Q0 = (T)(3.0 / 35.0 / 32.0);
+    c.Q1 = (T)(18.0 / 35.0 / 32.0 * k);
+    c.Q2 = (T)(0.2 / 32.0 * k2);
+    c.L0 = (T)(-3.2 / 32.0 * k2);
+    c.L1 = (T)(-1.6 / 32.0 * k3);
+    c.kh = (T)(0.5 * k);
+    c.k = (T)k;
+    c.eps2 = (T)(eps * eps);
+    c.heps2 = (T)(-0.5 * eps * eps);
+    c.m3 = (T)(-3.0);
+    c.far2 = 0.25 * rc * rc;
+    return c;
+}
+
+template <class T>
+__device__ __forceinline__ AdjCoef<T> pinned(const AdjCoef<T>& a) {
+    AdjCoef<T> c;
+    c.R0 = pin_(a.R0); c.R1 = pin_(a.R1); c.R2 = pin_(a.R2); c.R3 = pin_(a.R3);
+    c.P0 = pin_(a.P0); c.P1 = pin_(a.P1); c.P2 = pin_(a.P2);
+    c.Q0 = pin_(a.Q0); c.Q1 = pin_(a.Q1); c.Q2 = pin_(a.Q2);
+    c.L0 = pin_(a.L0); c.L1 = pin_(a.L1);
+    c.kh = pin_(a.kh); c.k = pin_(a.k);
+    c.eps2 = pin_(a.eps2); c.heps2 = pin_(a.heps2); c.m3 = pin_(a.m3);
+    c.far2 = a.far2;
+    return c;
+}
+
+// phi/32 and psi/32 of one pair from r and s^-1.
 template <class T, bool NEAR>
-__device__ __forceinline__ void jac_coefs(T r2, T r, T rinv, const Coef<T>& c, T& phi, T& psi) {
+__device__ __forceinline__ void jac_coefs(T r, T rinv, const AdjCoef<T>& c, T& phi, T& psi) {
     const T u = rinv * rinv;
     const T s3 = u * rinv;
+    const T t = sat_(fma_(r, -c.kh, T(1)));
+    const T R = fma_(fma_(fma_(r, c.R3, c.R2), r, c.R1), r, c.R0);
+    const T P = fma_(fma_(r, c.P2, c.P1), r, c.P0);
+    const T t4 = (t * t) * (t * t);
     if (NEAR) {
-        T t;
-        const T g = cutoff_g(r, r2, c, t);
-        // h on each branch (no division by r needed)
-        T v = fma_(r, c.C6, c.C5);
-        v = fma_(r, v, c.C4);
-        v = fma_(r, v, c.C3);
-        v = fma_(r2, v, c.C1);
-        const T h1 = v * r;
-        const T t2 = t * t;
-        const T h2 = -(t2 * t2) * fma_(r2, c.E2, fma_(r, c.E1, c.E0));
-        const T h = r2 < c.rh2 ? h1 : h2;
+        const T w = sat_(fma_(r, -c.k, T(1)));
+        const T w2 = w * w;
+        const T w4 = w2 * w2;
+        const T Q = fma_(fma_(r, c.Q2, c.Q1), r, c.Q0);
+        const T L = fma_(r, c.L1, c.L0);
+        const T g = fma_(w4 * w2, Q, t4 * (t * R));
+        const T h = fma_(w4 * w, L, -(t4 * P));
         phi = s3 * g;
         psi = s3 * fma_(c.m3 * u, g, h);
     } else {
-        // g = t^4 (t R), h = -t^4 P; with a = s^-3 t^4:
-        // phi = a (t R), psi = -3 u phi - a P
-        const T t = sat_(fma_(r, -c.k, T(2)));
-        const T R = fma_(fma_(fma_(r, c.R3, c.R2), r, c.R1), r, c.R0);
-        const T a = s3 * ((t * t) * (t * t));
+        // g = T^4 (T R), h = -T^4 P; with a = s^-3 T^4:
+        // phi = a (T R), psi = -3 u phi - a P
+        const T a = s3 * t4;
         phi = a * (t * R);
-        psi = fma_(c.m3 * u, phi, -(a * fma_(fma_(r, c.E2, c.E1), r, c.E0)));
+        psi = fma_(c.m3 * u, phi, -(a * P));
     }
 }
 
@@ -648,7 +695,7 @@ struct Targets {
 // owns it (or lies past the tile's entries).
 template <class T, class V4, int NB, bool NEAR, bool RS>
 __device__ __forceinline__ void adjoint_entries(int a, int b, const V4* tile, const int32_t* ids, V4* jbuf,
-                                                int lane, Targets<T, NB>& tg, const Coef<T>& c) {
+                                                int lane, Targets<T, NB>& tg, const AdjCoef<T>& c) {
     const int ra = lane & (kRow - 1), rb = lane >> 4;
     const bool hi8 = ra & 8, hi4 = ra & 4;
     for (int eb = a; eb < b; eb += kRows) {
@@ -667,7 +714,7 @@ __device__ __forceinline__ void adjoint_entries(int a, int b, const V4* tile, co
             const T rinv = (NEAR && v == tg.id[ib]) ? T(0) : rsqrt_(s2);
             const T r = NEAR ? sqrt_(r2) : far_r<T, RS>(r2, s2, rinv, c);
             T phi, psi;
-            jac_coefs<T, NEAR>(r2, r, rinv, c, phi, psi);
+            jac_coefs<T, NEAR>(r, rinv, c, phi, psi);
             const T dw = fma_(dz, tg.wz[ib], fma_(dy, tg.wy[ib], dx * tg.wx[ib]));
             const T s = psi * dw;
             const T ms = p.w * s;
@@ -722,19 +769,19 @@ __device__ __forceinline__ void flush_jside(int len, const V4* tile, const int32
     for (int q = threadIdx.x; q < 4 * len; q += 64) {
         const int e = q >> 2, comp = q & 3;
         const T val = comp == 3 ? jv[q] : jv[q] * tile[e].w;
-        if (val != T(0)) unsafeAtomicAdd(gj + (4 * (int64_t)ids[e] + comp), (double)val);
+        if (val != T(0)) unsafeAtomicAdd(gj + (4 * (int64_t)ids[e] + comp), kGScale * (double)val);
     }
 }
 
 template <class T, int NB, bool RS>
-__device__ __forceinline__ void adjoint_group(const GroupArgs& ga, const Src& src, const Coef<T>& c0,
+__device__ __forceinline__ void adjoint_group(const GroupArgs& ga, const Src& src, const AdjCoef<T>& c0,
                                               const double* __restrict__ wx, const double* __restrict__ wy,
                                               const double* __restrict__ wz, int64_t ws, const AdjOut& out,
                                               int64_t g, int32_t first, int32_t cnt,
                                               typename Vec4<T>::type* tile, int32_t* ids,
                                               typename Vec4<T>::type* jbuf) {
     using V4 = typename Vec4<T>::type;
-    const Coef<T> c = pinned(c0);
+    const AdjCoef<T> c = pinned(c0);
     const int lane = threadIdx.x;
     const int ra = lane & (kRow - 1), rb = lane >> 4;
     const double cx = (ga.glo[g * 3 + 0] + ga.ghi[g * 3 + 0]) * 0.5;
@@ -774,9 +821,9 @@ __device__ __forceinline__ void adjoint_group(const GroupArgs& ga, const Src& sr
         // FP32 tile partials of the four rows summed in FP64 (xor 16, xor 32)
 #pragma unroll
         for (int ib = 0; ib < NB; ++ib) {
-            double px = (double)fma_(tg.A[ib], tg.wx[ib], tg.Bx[ib]);
-            double py = (double)fma_(tg.A[ib], tg.wy[ib], tg.By[ib]);
-            double pz = (double)fma_(tg.A[ib], tg.wz[ib], tg.Bz[ib]);
+            double px = kGScale * (double)fma_(tg.A[ib], tg.wx[ib], tg.Bx[ib]);
+            double py = kGScale * (double)fma_(tg.A[ib], tg.wy[ib], tg.By[ib]);
+            double pz = kGScale * (double)fma_(tg.A[ib], tg.wz[ib], tg.Bz[ib]);
             px += __shfl_xor(px, 16, 64);
             py += __shfl_xor(py, 16, 64);
             pz += __shfl_xor(pz, 16, 64);
@@ -800,7 +847,7 @@ __device__ __forceinline__ void adjoint_group(const GroupArgs& ga, const Src& sr
 }
 
 template <class T, bool RS>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) void k_adjoint(GroupArgs ga, Src src, Coef<T> c, const double* __restrict__ wx,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) void k_adjoint(GroupArgs ga, Src src, AdjCoef<T> c, const double* __restrict__ wx,
                                                 const double* __restrict__ wy, const double* __restrict__ wz, int64_t ws,
                                                 AdjOut out) {
     using V4 = typename Vec4<T>::type;
@@ -991,13 +1038,13 @@ static void adjoint_on(const Tree& t, const Lists& l, const srf_params& p, const
     if (ev0) SRF_HIP(hipEventRecord(ev0, st));
     if (p.precision == SRF_FP64) {
         hipLaunchKernelGGL((k_adjoint<double, false>), dim3((unsigned)ng), dim3(64), 0, st, group_args(t, l),
-                           src_args(t), make_coef<double>(p.r_cut, p.eps), wx, wy, wz, ws, o);
+                           src_args(t), make_adj_coef<double>(p.r_cut, p.eps), wx, wy, wz, ws, o);
     } else if (far_r_from_s(p)) {
         hipLaunchKernelGGL((k_adjoint<float, true>), dim3((unsigned)ng), dim3(64), 0, st, group_args(t, l),
-                           src_args(t), make_coef<float>(p.r_cut, p.eps), wx, wy, wz, ws, o);
+                           src_args(t), make_adj_coef<float>(p.r_cut, p.eps), wx, wy, wz, ws, o);
     } else {
         hipLaunchKernelGGL((k_adjoint<float, false>), dim3((unsigned)ng), dim3(64), 0, st, group_args(t, l),
-                           src_args(t), make_coef<float>(p.r_cut, p.eps), wx, wy, wz, ws, o);
+                           src_args(t), make_adj_coef<float>(p.r_cut, p.eps), wx, wy, wz, ws, o);
     }
     SRF_HIP(hipGetLastError());
     if (ev1) SRF_HIP(hipEventRecord(ev1, st));

@@ -363,9 +363,13 @@ def test_centre_of_mass_mac(name, theta):
     assert e.value.status == -5
 
 
+EXPAND_BATCH = 128   # items the expansion takes per batch
+
+
 def max_expand_chunk(ot):
-    """Largest number of entries in 64 consecutive items (leaves and accepted
-    cells, in preorder) of any group's list, from the oracle's structure."""
+    """Largest number of entries in one batch of EXPAND_BATCH consecutive
+    items (leaves and accepted cells, in preorder) of any group's list, from
+    the oracle's structure."""
     t, L = ot.tree, ot.lists
     leaf_of = np.full(ot.n, -1)
     for i in np.nonzero(t.leaf)[0]:
@@ -376,13 +380,13 @@ def max_expand_chunk(ot):
         cells = L.nidx[L.noff[g]:L.noff[g + 1]]
         ids = np.concatenate([leaves, cells])
         size = np.concatenate([t.count[leaves], np.ones(cells.size, np.int64)])[np.argsort(ids, kind="stable")]
-        for c0 in range(0, size.size, 64):
-            best = max(best, int(size[c0:c0 + 64].sum()))
+        for c0 in range(0, size.size, EXPAND_BATCH):
+            best = max(best, int(size[c0:c0 + EXPAND_BATCH].sum()))
     return best
 
 
 def test_lists_with_leaves_of_64():
-    """Leaves of up to 64 particles: some chunks of 64 items expand to more
+    """Leaves of up to 64 particles: some batches of items expand to more
     entries than the expansion's LDS buffer holds (1024) and take its direct
     path; the lists must equal the oracle's bit for bit."""
     ps = synth.small_clustered(20000, 101, r_cut=0.1, eps=2e-4, theta=0.5, per_halo=1000)
