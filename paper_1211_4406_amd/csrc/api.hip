@@ -118,9 +118,16 @@ int srf_tree_build(int64_t n, const double* x, const double* y, const double* z,
         t.stream = st;
         srf::DevBuf<int32_t> flag(1, st);
         srf::fill_i32(flag.get(), 0, 1, st);
-        srf::build_sorted(t, x, y, z, pos_stride, m, m_stride, flag.get(), st);
-        // reads the flag at its one synchronisation (SRF_EDOMAIN)
-        srf::build_cells_and_groups(t, flag.get(), st);
+        srf::build_sorted(t, x, y, z, pos_stride, m, m_stride, flag.get(), false, st);
+        // reads the flag at its one synchronisation (SRF_EDOMAIN); when more
+        // particles than the run sort takes share one high key word (a dense
+        // clump in a 2^-10 cube), the tree is built again on the full sort
+        if (!srf::build_cells_and_groups(t, flag.get(), st)) {
+            srf::fill_i32(flag.get(), 0, 1, st);
+            srf::build_sorted(t, x, y, z, pos_stride, m, m_stride, flag.get(), true, st);
+            if (!srf::build_cells_and_groups(t, flag.get(), st))
+                srf::fail(SRF_EHIP, "the full radix sort reported an incomplete order");
+        }
     });
     if (rc != SRF_OK) {
         delete h;

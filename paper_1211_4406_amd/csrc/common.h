@@ -162,15 +162,21 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
 // asked for it with `write_total`).
 void exclusive_scan_i64(int64_t* data, int64_t n, bool write_total, hipStream_t stream);
 void exclusive_scan_i32(int32_t* data, int64_t n, bool write_total, hipStream_t stream);
+// The same over the first *nd values (a count on the device, at most n_max;
+// data holds n_max + 1 values), the total at data[*nd].
+void exclusive_scan_i32_counted(int32_t* data, int64_t n_max, const int32_t* nd, hipStream_t stream);
 
 // ------------------------------------------------------------ launches
-// a1-a2: keys, sort, gather.  Returns the device error flag's address
-// inside `flag` (bit 0: non-finite position, bit 1: bad mass).
+// a1-a2: keys, sort, gather.  Sets bits of the device error flag *d_flag
+// (bit 0: non-finite position, bit 1: bad mass; bit 3: a run of more than
+// kRunMax particles shares the high key word, so the order is incomplete and
+// the sort must be run again with `full`).
 void build_sorted(Tree& t, const double* x, const double* y, const double* z, int64_t ps,
-                  const double* m, int64_t ms, int32_t* d_flag, hipStream_t stream);
-// a3-a5; synchronises `stream` once, and fails with SRF_EDOMAIN if *d_flag
-// (set by build_sorted) is nonzero
-void build_cells_and_groups(Tree& t, int32_t* d_flag, hipStream_t stream);
+                  const double* m, int64_t ms, int32_t* d_flag, bool full, hipStream_t stream);
+// a3-a5; synchronises `stream` once, and fails with SRF_EDOMAIN if bit 0 or
+// 1 of *d_flag (set by build_sorted) is set.  Returns false, having built
+// nothing, if bit 3 is set.
+bool build_cells_and_groups(Tree& t, int32_t* d_flag, hipStream_t stream);
 // Tree reuse: positions and masses (m may be NULL: masses kept) gathered in
 // the tree's sorted order into px..pm, wrapped, with the same checks as
 // build_sorted (bits of *d_flag)

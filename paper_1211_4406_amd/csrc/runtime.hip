@@ -172,9 +172,17 @@ __device__ T block_excl_scan(T v, T* total) {
 // per thread.
 template <class T>
 __global__ __launch_bounds__(kScanThreads) void k_scan_local(T* __restrict__ data, int64_t n_read, int64_t n_write,
-                                                             T* __restrict__ sums) {
+                                                             T* __restrict__ sums, const int32_t* __restrict__ nd) {
     __shared__ T buf[kScanTile];
     const int64_t b0 = (int64_t)blockIdx.x * kScanTile;
+    if (nd) {   // a count on the device: scan its first *nd values, total at [*nd]
+        n_read = *nd;
+        n_write = n_read + 1;
+        if (b0 >= n_write) {
+            if (threadIdx.x == 0 && sums) sums[blockIdx.x] = T(0);
+            return;
+        }
+    }
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         const int64_t i = b0 + k * kScanThreads + threadIdx.x;
@@ -205,7 +213,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_local(T* __restrict__ dat
 }
 
 template <class T>
-__global__ void k_scan_add(T* __restrict__ data, int64_t n, const T* __restrict__ sums) {
+__global__ void k_scan_add(T* __restrict__ data, int64_t n, const T* __restrict__ sums,
+                           const int32_t* __restrict__ nd) {
+    if (nd) n = (int64_t)*nd + 1;
     const int64_t i = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
     const T add = sums[blockIdx.x];
 #pragma unroll
@@ -215,22 +225,25 @@ __global__ void k_scan_add(T* __restrict__ data, int64_t n, const T* __restrict_
     }
 }
 
+// With nd, n_write is the largest count + 1 the device may hold, and the
+// top level scans the first *nd values (total at [*nd]).
 template <class T>
-static void scan_impl(T* data, int64_t n_read, int64_t n_write, hipStream_t s) {
+static void scan_impl(T* data, int64_t n_read, int64_t n_write, hipStream_t s, const int32_t* nd = nullptr) {
     if (n_write <= 0) return;
     int64_t nb = (n_write + kScanTile - 1) / kScanTile;
     if (nb == 1) {
-        hipLaunchKernelGGL(k_scan_local<T>, dim3(1), dim3(kScanThreads), 0, s, data, n_read, n_write, (T*)nullptr);
+        hipLaunchKernelGGL(k_scan_local<T>, dim3(1), dim3(kScanThreads), 0, s, data, n_read, n_write, (T*)nullptr,
+                           nd);
         SRF_HIP(hipGetLastError());
         return;
     }
     DevBuf<T> sums(nb, s);
     hipLaunchKernelGGL(k_scan_local<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n_read, n_write,
-                       sums.get());
+                       sums.get(), nd);
     SRF_HIP(hipGetLastError());
     scan_impl<T>(sums.get(), nb, nb, s);
     hipLaunchKernelGGL(k_scan_add<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n_write,
-                       (const T*)sums.get());
+                       (const T*)sums.get(), nd);
     SRF_HIP(hipGetLastError());
 }
 
@@ -239,6 +252,9 @@ void exclusive_scan_i64(int64_t* data, int64_t n, bool write_total, hipStream_t 
 }
 void exclusive_scan_i32(int32_t* data, int64_t n, bool write_total, hipStream_t s) {
     scan_impl<int32_t>(data, n, n + (write_total ? 1 : 0), s);
+}
+void exclusive_scan_i32_counted(int32_t* data, int64_t n_max, const int32_t* nd, hipStream_t s) {
+    scan_impl<int32_t>(data, n_max, n_max + 1, s, nd);
 }
 
 }  // namespace srf

@@ -1,12 +1,17 @@
 // Steps a1-a2: periodic wrap, 63-bit Morton keys, stable LSD radix sort of
 // (key, input index), gather of the sorted SoA particle arrays.
 //
-// The sort moves 32-bit words: four passes order (low word; high word,
-// index) by the low word, four more order (high word; index) by the high
-// word.  Each pass is stable, so the result is the order of (key, input
-// index) -- that of eight passes over the whole 64-bit key -- with 12 and
-// then 8 instead of 12 bytes moved per element and pass.  The sorted keys
-// are recomputed from the sorted positions by the final gather.
+// The sort orders (key, input index) with passes over 32-bit words.  Four
+// stable passes order (high word; index) by the high word.  Particles that
+// share their high word with a neighbour then form runs, and each run is
+// ordered by (low word, index): every member counts the members that come
+// before it (runs hold at most kRunMax particles; a longer run, which needs
+// more than kRunMax particles in one cube of side 2^-10 of the box, makes
+// the caller sort again in full).  The full sort: four passes order (low word; high
+// word, index) by the low word, four more (high word; index) by the high
+// word.  Both give the order of (key, input index), that of eight passes
+// over the whole 64-bit key.  The sorted keys are recomputed from the
+// sorted positions by the final gather.
 #include "common.h"
 
 namespace srf {
@@ -265,6 +270,91 @@ __global__ __launch_bounds__(kThreads) void k_scatter(int64_t n, const uint32_t*
     }
 }
 
+// ------------------------------------------------------------- runs
+// After the high-word passes: positions whose high word a neighbour
+// shares (mark 1), compacted in order with their low words, and each such
+// run put in (low word, index) order by counting.
+constexpr int64_t kRunMax = 1024;
+
+__device__ __forceinline__ bool in_run(const uint32_t* __restrict__ hi, int64_t n, int64_t s) {
+    const uint32_t h = hi[s];
+    return (s > 0 && hi[s - 1] == h) || (s + 1 < n && hi[s + 1] == h);
+}
+
+__global__ void k_run_mark(int64_t n, const uint32_t* __restrict__ hi, int32_t* __restrict__ mark) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    mark[s] = in_run(hi, n, s) ? 1 : 0;
+}
+
+// `at`: exclusive scan of the marks (at[n] = their number)
+__global__ void k_run_compact(int64_t n, const uint32_t* __restrict__ hi, const int32_t* __restrict__ idx,
+                              const uint32_t* __restrict__ klo, const int32_t* __restrict__ at,
+                              uint32_t* __restrict__ clo, uint32_t* __restrict__ chi, int32_t* __restrict__ cidx,
+                              int32_t* __restrict__ cpos) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n || !in_run(hi, n, s)) return;
+    const int64_t j = at[s];
+    const int32_t i = idx[s];
+    clo[j] = klo[i];
+    chi[j] = hi[s];
+    cidx[j] = i;
+    cpos[j] = (int32_t)s;
+}
+
+// Run starts in the compacted array: rid[j] = 1 where run j begins (then
+// scanned into run numbers).
+__global__ void k_run_starts(const int32_t* __restrict__ md, const uint32_t* __restrict__ chi,
+                             int32_t* __restrict__ rid) {
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t m = *md;
+    if (j >= m) return;
+    rid[j] = (j == 0 || chi[j] != chi[j - 1]) ? 1 : 0;
+}
+
+// rstart[r] = first member of run r (rid: exclusive scan of the starts,
+// so rid[j] is the run number of a start j and rid[m] the number of runs);
+// rstart[number of runs] = m.
+__global__ void k_run_index(const int32_t* __restrict__ md, const uint32_t* __restrict__ chi,
+                            const int32_t* __restrict__ rid, int32_t* __restrict__ rstart) {
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t m = *md;
+    if (j > m) return;
+    if (j == m) {
+        rstart[rid[m]] = (int32_t)m;
+    } else if (j == 0 || chi[j] != chi[j - 1]) {
+        rstart[rid[j]] = (int32_t)j;
+    }
+}
+
+// Member j of a run [r0, r1) of the compacted array goes to r0 + the number
+// of members with a smaller (low word, index); the members' positions in
+// the sorted array are the run's positions, in order.  A run longer than
+// kRunMax sets bit 3 of *flag instead.
+__global__ void k_run_rank(int64_t n, const int32_t* __restrict__ md, const uint32_t* __restrict__ clo,
+                           const int32_t* __restrict__ cidx, const int32_t* __restrict__ cpos,
+                           const int32_t* __restrict__ rid, const int32_t* __restrict__ rstart,
+                           int32_t* __restrict__ perm, int32_t* __restrict__ flag) {
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= *md) return;
+    const int32_t r = rid[j + 1] - 1;   // starts in [0, j], less one: j's run
+    const int32_t r0 = rstart[r], r1 = rstart[r + 1];
+    if (r1 - r0 > kRunMax) {
+        atomicOr(flag, 8);
+        return;
+    }
+    const uint32_t lo = clo[j];
+    const int32_t id = cidx[j];
+    int32_t rank = 0;
+#pragma unroll 4
+    for (int32_t k = r0; k < r1; ++k) {
+        const uint32_t l = clo[k];
+        rank += (l < lo || (l == lo && cidx[k] < id)) ? 1 : 0;
+    }
+    const int32_t p = cpos[r0 + rank];
+    if ((uint64_t)p < (uint64_t)n) perm[p] = id;
+}
+
 // The sorted particles, and their keys computed again from the wrapped
 // positions exactly as k_keys computed them.
 __global__ void k_gather(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ x,
@@ -315,7 +405,7 @@ void gather_refit(const Tree& t, const double* x, const double* y, const double*
 }
 
 void build_sorted(Tree& t, const double* x, const double* y, const double* z, int64_t ps, const double* m,
-                  int64_t ms, int32_t* d_flag, hipStream_t st) {
+                  int64_t ms, int32_t* d_flag, bool full, hipStream_t st) {
     const int64_t n = t.n;
     const int B = 256;
     DevBuf<uint32_t> ka(n, st), kb(n, st), ha(n, st), hb(n, st);
@@ -344,15 +434,42 @@ void build_sorted(Tree& t, const double* x, const double* y, const double* z, in
                                (const uint32_t*)nullptr, (uint32_t*)nullptr, shift, tiles, counts.get(), dtot.get());
         SRF_HIP(hipGetLastError());
     };
-    // low word: passes a -> b -> a -> b -> a (pairs of passes return to the
-    // first buffers); then the high word, already in that order, in ha
-    for (int p = 0; p < 4; p += 2) {
-        pass(8 * p, ka.get(), kb.get(), t.perm.get(), vb.get(), ha.get(), hb.get());
-        pass(8 * (p + 1), kb.get(), ka.get(), vb.get(), t.perm.get(), hb.get(), ha.get());
+    // full: the low word first, passes a -> b -> a -> b -> a (pairs of
+    // passes return to the first buffers), then the high word, already in
+    // that order, in ha; otherwise the high word alone, then the runs
+    if (full) {
+        for (int p = 0; p < 4; p += 2) {
+            pass(8 * p, ka.get(), kb.get(), t.perm.get(), vb.get(), ha.get(), hb.get());
+            pass(8 * (p + 1), kb.get(), ka.get(), vb.get(), t.perm.get(), hb.get(), ha.get());
+        }
     }
     for (int p = 0; p < 4; p += 2) {
         pass(8 * p, ha.get(), hb.get(), t.perm.get(), vb.get(), nullptr, nullptr);
         pass(8 * (p + 1), hb.get(), ha.get(), vb.get(), t.perm.get(), nullptr, nullptr);
+    }
+    if (!full) {
+        DevBuf<int32_t> at(n + 1, st);
+        const dim3 grid(grid_for(n, B, 1 << 30));
+        hipLaunchKernelGGL(k_run_mark, grid, dim3(B), 0, st, n, ha.get(), at.get());
+        SRF_HIP(hipGetLastError());
+        exclusive_scan_i32(at.get(), n, true, st);
+        // the compacted runs: low word in kb, high word in hb, index in vb, position in cpos
+        DevBuf<int32_t> cpos(n, st);
+        hipLaunchKernelGGL(k_run_compact, grid, dim3(B), 0, st, n, ha.get(), t.perm.get(), ka.get(), at.get(),
+                           kb.get(), hb.get(), vb.get(), cpos.get());
+        SRF_HIP(hipGetLastError());
+        // runs: numbers (exclusive scan of the starts) and first members
+        const int32_t* md = at.get() + n;
+        DevBuf<int32_t> rid(n + 1, st), rstart(n + 1, st);
+        hipLaunchKernelGGL(k_run_starts, grid, dim3(B), 0, st, md, hb.get(), rid.get());
+        SRF_HIP(hipGetLastError());
+        exclusive_scan_i32_counted(rid.get(), n, md, st);
+        hipLaunchKernelGGL(k_run_index, dim3(grid_for(n + 1, B, 1 << 30)), dim3(B), 0, st, md, hb.get(), rid.get(),
+                           rstart.get());
+        SRF_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_run_rank, grid, dim3(B), 0, st, n, md, kb.get(), vb.get(), cpos.get(), rid.get(),
+                           rstart.get(), t.perm.get(), d_flag);
+        SRF_HIP(hipGetLastError());
     }
     t.px.alloc(n, st);
     t.py.alloc(n, st);

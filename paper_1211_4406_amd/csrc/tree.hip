@@ -647,7 +647,7 @@ __global__ __launch_bounds__(256) void k_group_bbox(int64_t ng, const int32_t* _
 
 }  // namespace
 
-void build_cells_and_groups(Tree& t, int32_t* d_flag, hipStream_t st) {
+bool build_cells_and_groups(Tree& t, int32_t* d_flag, hipStream_t st) {
     const int64_t n = t.n;
     const int B = 256;
     const int64_t nblocks = (n + kLvTile - 1) / kLvTile;
@@ -672,6 +672,7 @@ void build_cells_and_groups(Tree& t, int32_t* d_flag, hipStream_t st) {
     SRF_HIP(hipStreamSynchronize(st));
     if (hs.flag & 1) fail(SRF_EDOMAIN, "non-finite particle position");
     if (hs.flag & 2) fail(SRF_EDOMAIN, "particle mass not finite and > 0");
+    if (hs.flag & 8) return false;   // the order is incomplete (see build_sorted)
     // (a level holds fewer than 2^31 cells: its per-block counts are exact
     // int32 sums of counts below n; the total is checked here)
     LevelBase base;
@@ -741,6 +742,7 @@ void build_cells_and_groups(Tree& t, int32_t* d_flag, hipStream_t st) {
                        t.gfirst.get(),
                        t.gcount.get(), t.px.get(), t.py.get(), t.pz.get(), t.glo.get(), t.ghi.get());
     SRF_HIP(hipGetLastError());
+    return true;
 }
 
 void refit_cells_and_groups(Tree& t, hipStream_t st) {

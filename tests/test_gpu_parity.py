@@ -220,6 +220,36 @@ def test_sort_tiles_and_repeated_keys(n, distinct):
     assert np.all(np.isfinite(a32))
 
 
+@pytest.mark.parametrize("clump", [300, 1024, 1025, 3000])
+def test_sort_runs_sharing_the_high_key_word(clump):
+    """Clumps of `clump` particles, each inside a cube of side 2e-4 centred in
+    a level-11 cell (so every member shares the high 32-bit word of its key
+    but not the low word), over a uniform background: the sort orders each
+    run by the low word and the index when it holds at most 1024 particles,
+    and the tree is built again on the full sort when a run is longer;
+    either way keys, permutation, cells, groups and lists equal the
+    oracle's."""
+    rng = np.random.default_rng(1700 + clump)
+    n_clumps, n_bg = 3, 20_000
+    cells = rng.integers(0, 2 ** 11, (n_clumps, 3))
+    parts = [rng.random((n_bg, 3))]
+    for c in cells:
+        centre = (c + 0.5) / 2 ** 11
+        parts.append(centre + (rng.random((clump, 3)) - 0.5) * 2e-4)
+    pos = np.concatenate(parts)[rng.permutation(n_bg + n_clumps * clump)]
+    n = len(pos)
+    say(f"[gpu] sort runs clump={clump} n={n}")
+    p = synth.Params(1.0, 0.05, 1e-4, 0.5, 64, 16)
+    ps = synth.ParticleSet(pos[:, 0].copy(), pos[:, 1].copy(), pos[:, 2].copy(), np.full(n, 1.0 / n), p)
+    ot = oracle.OracleTree(ps.x, ps.y, ps.z, ps.m, p)
+    hi = ot.keys >> np.uint64(32)
+    starts = np.flatnonzero(np.concatenate([[True], hi[1:] != hi[:-1], [True]]))
+    assert np.diff(starts).max() == clump, "each clump is one run of equal high words"
+    tree, lists, a32 = gpu_forward(ps, p)
+    check_structure(tree, lists, ot)
+    assert np.all(np.isfinite(a32))
+
+
 def test_lists_with_more_items_than_a_slot():
     """With single-particle leaves and a wide cutoff every group's list holds
     more than 2048 leaves and cells, which overflows the per-group slot of
