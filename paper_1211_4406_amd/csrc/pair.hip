@@ -642,42 +642,15 @@ struct AdjOut {
 //     target (summed over the rows once per tile, in FP64, into the FP64
 //     total the target's own lane keeps),
 //   - V = J w_i and phi (d . w_i) are summed in registers over the NB
-//     blocks, then over the 16 lanes of the row by a transposed reduction
-//     (two exchange steps that halve the number of values a lane holds,
-//     then two quad steps: 6 selects and 5 DPP adds instead of 16 DPP adds,
-//     which cost 1.5 times a plain instruction); four lanes of the row store
-//     the four totals in the tile's j-side slot of the entry, and once per
-//     tile the slots are scaled by the source masses and added to the
-//     sources' gradients with FP64 atomics (four lanes per source, one
-//     32-byte row each).
+//     blocks; the lane stores these four partial sums in LDS, and after
+//     every four entry blocks each lane adds the 16 partials of one (entry,
+//     value) of them (LDS operations, which issue beside the vector ALU,
+//     where summing across the row in registers took 6 selects and 5 DPP
+//     adds per block), scales the entry's V by its mass and adds the total
+//     to the source's gradient with an FP64 atomic.
 // Targets past N_i carry zero weight, so they add nothing to either side.
 constexpr int kRow = 16;   // lanes per row: targets per block
 constexpr int kRows = 4;   // rows: entries per block
-
-// Sum over the 16 lanes of a row (lanes 16r..16r+15) with DPP moves, which
-// stay in the vector ALU: xor 1 and xor 2 within quads, then the
-// half-row and row mirrors pair up the quads and the half-rows.  Every lane
-// of the row ends with the total.
-__device__ __forceinline__ float dpp_f(float v, int ctrl) {
-    switch (ctrl) {
-        case 0: return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xf, 0xf, false));
-        case 1: return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4E, 0xf, 0xf, false));
-        case 2: return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x141, 0xf, 0xf, false));
-        default: return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x140, 0xf, 0xf, false));
-    }
-}
-// Step k of the row sum: quad_perm [1,0,3,2], quad_perm [2,3,0,1],
-// row_half_mirror, row_mirror.  After steps 0..k-1 the lanes of each group
-// of 2^k hold equal values, so step k adds the partner at xor 2^k; the FP64
-// form uses that shuffle directly.
-__device__ __forceinline__ float row16_step(float v, int k) { return v + dpp_f(v, k); }
-__device__ __forceinline__ double row16_step(double v, int k) { return v + __shfl_xor(v, 1 << k, 64); }
-// keep + the partner's send, the partner being the row mirror (k = 3: lane
-// 15 - i) or the half-row mirror (k = 2: lane i ^ 7)
-__device__ __forceinline__ float row_pair(float keep, float send, int k) { return keep + dpp_f(send, k); }
-__device__ __forceinline__ double row_pair(double keep, double send, int k) {
-    return keep + __shfl_xor(send, k == 3 ? 15 : 7, 64);
-}
 
 // Targets of one lane: block ib holds target 16 ib + a.
 template <class T, int NB>
@@ -691,13 +664,37 @@ struct Targets {
 
 // Entry blocks [a, b) of a staged tile (all near or all far).  Slots past
 // b hold entries of the next segment or the zero padding: their mass is
-// taken as zero and their j-side slot is written again by the segment that
-// owns it (or lies past the tile's entries).
+// taken as zero, and their j-side sums are not added (the segment that owns
+// them adds its own).
+// Row sums through LDS: after each entry block a lane stores its four
+// partial sums in `part` ([block][value][row][17], rows padded against bank
+// conflicts); after every kGroupBlocks blocks (and at the segment's end)
+// lane (block, value, row) adds the row's 16 partials, and the totals of
+// (mu V_x, mu V_y, mu V_z, sum phi (d . w)) of each entry go to row ids[e]
+// of the j-side array with FP64 atomics (a zero, every pair of the entry
+// beyond r_cut, is not added).
+constexpr int kGroupBlocks = 4;
+constexpr int kPartRow = 17;
+constexpr int kPartBlock = 4 * kRows * kPartRow;
+
+__device__ __forceinline__ void lds_order() {
+    // one wave: its LDS operations complete in order; this keeps the
+    // compiler from moving them across
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <class T, class V4, int NB, bool NEAR, bool RS>
-__device__ __forceinline__ void adjoint_entries(int a, int b, const V4* tile, const int32_t* ids, V4* jbuf,
-                                                int lane, Targets<T, NB>& tg, const AdjCoef<T>& c) {
+__device__ __forceinline__ void adjoint_entries(int a, int b, const V4* tile, const int32_t* ids,
+                                                double* __restrict__ gj, T* part, int lane, Targets<T, NB>& tg,
+                                                const AdjCoef<T>& c) {
     const int ra = lane & (kRow - 1), rb = lane >> 4;
-    const bool hi8 = ra & 8, hi4 = ra & 4;
+    int nblk = 0, eb0 = a;
+    T* wp = part + rb * kPartRow + ra;
+    // this lane's sum in the reduction: block, value, row
+    const int sb = lane >> 4, sv = (lane >> 2) & 3, sr = lane & 3;
+    const T* rp = part + sb * kPartBlock + sv * (kRows * kPartRow) + sr * kPartRow;
     for (int eb = a; eb < b; eb += kRows) {
         const int e = eb + rb;
         V4 p = tile[e];
@@ -735,41 +732,26 @@ __device__ __forceinline__ void adjoint_entries(int a, int b, const V4* tile, co
                 jm = fma_(phi, dw, jm);
             }
         }
-        // row sums of the four values, transposed: the row mirror pairs each
-        // lane of the low half with one of the high half, which keeps (jx, jy)
-        // resp. (jz, jm) and adds its partner's; the half-row mirror then
-        // pairs lanes 4 apart in the same way, leaving one value per lane
-        // (lanes 0-3: jx, 4-7: jy, 8-11: jz, 12-15: jm), and two quad steps
-        // finish the sums
-        T w0, w1, xs;
-        {
-            const T k0 = hi8 ? jz : jx, s0 = hi8 ? jx : jz;
-            const T k1 = hi8 ? jm : jy, s1 = hi8 ? jy : jm;
-            w0 = row_pair(k0, s0, 3);
-            w1 = row_pair(k1, s1, 3);
+        T* w = wp + nblk * kPartBlock;
+        w[0] = jx;
+        w[kRows * kPartRow] = jy;
+        w[2 * kRows * kPartRow] = jz;
+        w[3 * kRows * kPartRow] = jm;
+        ++nblk;
+        if (nblk == kGroupBlocks || eb + kRows >= b) {
+            lds_order();
+            const int e = eb0 + kRows * sb + sr;
+            if (sb < nblk && e < b) {
+                T sum = rp[0];
+#pragma unroll
+                for (int q = 1; q < kRow; ++q) sum += rp[q];
+                const T val = sv == 3 ? sum : sum * tile[e].w;
+                if (val != T(0)) unsafeAtomicAdd(gj + (4 * (int64_t)ids[e] + sv), kGScale * (double)val);
+            }
+            lds_order();
+            nblk = 0;
+            eb0 = eb + kRows;
         }
-        {
-            const T k = hi4 ? w1 : w0, s = hi4 ? w0 : w1;
-            xs = row_pair(k, s, 2);
-        }
-        xs = row16_step(xs, 0);
-        xs = row16_step(xs, 1);
-        asm volatile("" : "+v"(xs));
-        if ((ra & 3) == 0) reinterpret_cast<T*>(jbuf)[4 * e + (ra >> 2)] = xs;
-    }
-}
-
-// j-side slots of a finished tile -> FP64 atomics: (mu V_x, mu V_y, mu V_z,
-// sum phi (d . w)) of entry e go to row ids[e] of the j-side array.  A zero
-// (every pair of the entry beyond r_cut) is not added.
-template <class T, class V4>
-__device__ __forceinline__ void flush_jside(int len, const V4* tile, const int32_t* ids, const V4* jbuf,
-                                            double* __restrict__ gj) {
-    const T* jv = reinterpret_cast<const T*>(jbuf);
-    for (int q = threadIdx.x; q < 4 * len; q += 64) {
-        const int e = q >> 2, comp = q & 3;
-        const T val = comp == 3 ? jv[q] : jv[q] * tile[e].w;
-        if (val != T(0)) unsafeAtomicAdd(gj + (4 * (int64_t)ids[e] + comp), kGScale * (double)val);
     }
 }
 
@@ -778,8 +760,7 @@ __device__ __forceinline__ void adjoint_group(const GroupArgs& ga, const Src& sr
                                               const double* __restrict__ wx, const double* __restrict__ wy,
                                               const double* __restrict__ wz, int64_t ws, const AdjOut& out,
                                               int64_t g, int32_t first, int32_t cnt,
-                                              typename Vec4<T>::type* tile, int32_t* ids,
-                                              typename Vec4<T>::type* jbuf) {
+                                              typename Vec4<T>::type* tile, int32_t* ids, T* part) {
     using V4 = typename Vec4<T>::type;
     const AdjCoef<T> c = pinned(c0);
     const int lane = threadIdx.x;
@@ -816,8 +797,8 @@ __device__ __forceinline__ void adjoint_group(const GroupArgs& ga, const Src& sr
         __syncthreads();
 #pragma unroll
         for (int ib = 0; ib < NB; ++ib) tg.A[ib] = tg.Bx[ib] = tg.By[ib] = tg.Bz[ib] = T(0);
-        adjoint_entries<T, V4, NB, true, RS>(0, nnear, tile, ids, jbuf, lane, tg, c);
-        adjoint_entries<T, V4, NB, false, RS>(nnear, len, tile, ids, jbuf, lane, tg, c);
+        adjoint_entries<T, V4, NB, true, RS>(0, nnear, tile, ids, out.gj, part, lane, tg, c);
+        adjoint_entries<T, V4, NB, false, RS>(nnear, len, tile, ids, out.gj, part, lane, tg, c);
         // FP32 tile partials of the four rows summed in FP64 (xor 16, xor 32)
 #pragma unroll
         for (int ib = 0; ib < NB; ++ib) {
@@ -836,8 +817,6 @@ __device__ __forceinline__ void adjoint_group(const GroupArgs& ga, const Src& sr
                 gz -= pz;
             }
         }
-        __syncthreads();
-        flush_jside<T, V4>(len, tile, ids, jbuf, out.gj);
     }
     if (lane < cnt) {
         out.gix[first + lane] = gx;
@@ -853,18 +832,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     using V4 = typename Vec4<T>::type;
     __shared__ V4 tile[kTile + kRows];
     __shared__ int32_t ids[kTile + kRows];
-    __shared__ V4 jbuf[kTile + kRows];   // j-side totals of the tile's entries
+    __shared__ T part[kGroupBlocks * kPartBlock];   // row partials of the j-side sums
     const int64_t g = xcd_block(blockIdx.x, gridDim.x);
     const int32_t first = ga.gfirst[g], cnt = ga.gcount[g];
     static_assert(kRow * kRows == 64, "one wave is kRows rows of kRow lanes");
     if (cnt > 48)
-        adjoint_group<T, 4, RS>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, ids, jbuf);
+        adjoint_group<T, 4, RS>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, ids, part);
     else if (cnt > 32)
-        adjoint_group<T, 3, RS>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, ids, jbuf);
+        adjoint_group<T, 3, RS>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, ids, part);
     else if (cnt > 16)
-        adjoint_group<T, 2, RS>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, ids, jbuf);
+        adjoint_group<T, 2, RS>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, ids, part);
     else
-        adjoint_group<T, 1, RS>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, ids, jbuf);
+        adjoint_group<T, 1, RS>(ga, src, c, wx, wy, wz, ws, out, g, first, cnt, tile, ids, part);
 }
 
 // Node sources -> member particles.  For a cell c0 and its ancestors c
