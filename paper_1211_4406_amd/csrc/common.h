@@ -74,11 +74,19 @@ struct __align__(16) NodeGeo {
 struct __align__(16) NodeRange {
     int32_t first, count, skip, parent;
 };
-// The same cell packed into one 16-byte record for the list traversal:
+// The same cell packed into one 16-byte record (the refitted tree's walk
+// records hold it):
 //   x = ix | (skip & 0x7ff) << 21,  y = iy | ((skip >> 11) & 0x7ff) << 21,
 //   z = iz | ((skip >> 22) & 0x3ff) << 21,
 //   w = level | leaf << 5 | min(count, kPackCountMax) << 6.
 constexpr uint32_t kPackCountMax = 0x3ffffffu;
+// and into one 8-byte record for the walk over a built tree, which finds the
+// cell's coordinates from those of the cell it visited before (the new
+// cell's parent is that cell or one of its ancestors):
+//   x = level | leaf << 5 | oct << 6 | min(count, kWalkCountMax) << 9,
+//   y = skip,
+// oct = the low bits of (ix, iy, iz) as x << 2 | y << 1 | z.
+constexpr uint32_t kWalkCountMax = 0x7fffffu;
 // A cell of a refitted tree for the list traversal, 32 bytes: the packed
 // record and its box rounded outward to multiples of q = 2^-(level + 10),
 // per axis a the 16-bit offsets (in q) of its lower and upper bound from
@@ -110,7 +118,7 @@ struct Tree {
     // cells, preorder
     DevBuf<NodeGeo> geo;
     DevBuf<NodeRange> range;
-    DevBuf<uint4> pack;        // packed records (see kPackCountMax)
+    DevBuf<uint2> pack;        // walk records (see kWalkCountMax)
     DevBuf<uint64_t> prefix;
     DevBuf<double> nM, nX, nY, nZ;   // monopoles
     // the cells again as level slots (each level's cells ordered by first

@@ -65,6 +65,35 @@ struct Cell {
     int64_t skip;
 };
 
+// The cell of an 8-byte walk record, its coordinates found from those of
+// the cell visited before (w): the new cell's parent is that cell or one of
+// its ancestors, at level k.level - 1, whose coordinates are w's shifted
+// down by the levels between; the cell's own low bits are `oct`.
+struct WalkPos {
+    uint32_t ix = 0, iy = 0, iz = 0;
+    int level = -1;
+};
+
+__device__ __forceinline__ Cell decode_walk(const uint2 r, WalkPos& w) {
+    Cell k;
+    k.level = (int)(r.x & 31u);
+    k.leaf = (int)((r.x >> 5) & 1u);
+    const uint32_t oct = (r.x >> 6) & 7u;
+    k.count = r.x >> 9;
+    k.skip = (int64_t)r.y;
+    const int sh = w.level + 1 - k.level;
+    w.ix = ((w.ix >> sh) << 1) | (oct >> 2);
+    w.iy = ((w.iy >> sh) << 1) | ((oct >> 1) & 1u);
+    w.iz = ((w.iz >> sh) << 1) | (oct & 1u);
+    w.level = k.level;
+    k.side = ldexp(1.0, -k.level);
+    k.hs = k.side * 0.5;
+    k.c[0] = ldexp((double)w.ix + 0.5, -k.level);
+    k.c[1] = ldexp((double)w.iy + 0.5, -k.level);
+    k.c[2] = ldexp((double)w.iz + 0.5, -k.level);
+    return k;
+}
+
 __device__ __forceinline__ Cell decode(const uint4 r) {
     Cell k;
     k.level = (int)(r.w & 31u);
@@ -193,7 +222,7 @@ constexpr int kListThreads = 64;   // one wave per block (128 and 256 measured s
 template <int G, bool WRITE, bool COM, bool REFIT>
 __global__ __launch_bounds__(kListThreads) void k_lists(int64_t ng, const double* __restrict__ glo,
                                                const double* __restrict__ ghi, const int32_t* __restrict__ gcount,
-                                               const uint4* __restrict__ pack, const NodeRange* __restrict__ rng,
+                                               const uint2* __restrict__ pack, const NodeRange* __restrict__ rng,
                                                const double* __restrict__ nX, const double* __restrict__ nY,
                                                const double* __restrict__ nZ,
                                                const RefitCell* __restrict__ rpack, int64_t nn, double rc2, double th2, int64_t* __restrict__ cnt,
@@ -221,10 +250,11 @@ __global__ __launch_bounds__(kListThreads) void k_lists(int64_t ng, const double
     const uint64_t full = (1ull << G) - 1ull;
     uint64_t masks = valid;  // level 0
     int64_t i = valid ? 0 : nn;
+    WalkPos wpos;
     while (i < nn) {
         RefitCell rc;
         if (REFIT) rc = rpack[i];
-        const Cell k = decode(REFIT ? rc.pk : pack[i]);
+        const Cell k = REFIT ? decode(rc.pk) : decode_walk(pack[i], wpos);
         const uint64_t act = (masks >> (k.level * G)) & full;
         uint64_t open = 0;
         if (act) {
@@ -255,7 +285,7 @@ __global__ __launch_bounds__(kListThreads) void k_lists(int64_t ng, const double
                     out[q].put((int32_t)i);
                     if (!WRITE) {
                         uint32_t m = k.count;
-                        if (m == kPackCountMax) m = (uint32_t)rng[i].count;
+                        if (m == (REFIT ? kPackCountMax : kWalkCountMax)) m = (uint32_t)rng[i].count;
                         np[q] += m;
                         ++w[q];
                     }

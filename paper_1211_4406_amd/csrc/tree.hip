@@ -536,13 +536,8 @@ __global__ __launch_bounds__(256) void k_refit_level(int32_t lo, int32_t hi, int
     }
 }
 
-// The packed walk record of each cell (preorder).
-__global__ void k_pack(int64_t nn, const NodeGeo* __restrict__ geo, const NodeRange* __restrict__ rng,
-                       uint4* __restrict__ pack) {
-    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (c >= nn) return;
-    const NodeGeo g = geo[c];
-    const NodeRange r = rng[c];
+// A cell's 16-byte packed record.
+__device__ __forceinline__ uint4 pack16(const NodeGeo& g, const NodeRange& r) {
     const uint32_t sk = (uint32_t)r.skip;
     const uint32_t lv = g.level_leaf & 0xffu;
     const bool leaf = (g.level_leaf >> 8) & 1u;
@@ -551,14 +546,28 @@ __global__ void k_pack(int64_t nn, const NodeGeo* __restrict__ geo, const NodeRa
     pk.y = g.iy | (((sk >> 11) & 0x7ffu) << 21);
     pk.z = g.iz | (((sk >> 22) & 0x3ffu) << 21);
     pk.w = lv | (leaf ? 0x20u : 0u) | ((uint32_t)(r.count < (int32_t)kPackCountMax ? r.count : (int32_t)kPackCountMax) << 6);
-    pack[c] = pk;
+    return pk;
+}
+
+// The 8-byte walk record of each cell (preorder).
+__global__ void k_pack(int64_t nn, const NodeGeo* __restrict__ geo, const NodeRange* __restrict__ rng,
+                       uint2* __restrict__ pack) {
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= nn) return;
+    const NodeGeo g = geo[c];
+    const NodeRange r = rng[c];
+    const uint32_t lv = g.level_leaf & 0xffu;
+    const uint32_t leaf = (g.level_leaf >> 8) & 1u;
+    const uint32_t oct = ((g.ix & 1u) << 2) | ((g.iy & 1u) << 1) | (g.iz & 1u);
+    const uint32_t cnt = r.count < (int32_t)kWalkCountMax ? (uint32_t)r.count : kWalkCountMax;
+    pack[c] = make_uint2(lv | (leaf << 5) | (oct << 6) | (cnt << 9), (uint32_t)r.skip);
 }
 
 // The walk record of each cell of a refitted tree (preorder): the packed
 // record, and the box rounded outward to multiples of q = 2^-(level + 10),
 // K = floor(lo / q) and ceil(hi / q) (exact), stored as offsets from the
 // centre's multiple ic * 1024 + 512 when both fit 16 bits.
-__global__ void k_refit_pack(int64_t nn, const NodeGeo* __restrict__ geo, const uint4* __restrict__ pack,
+__global__ void k_refit_pack(int64_t nn, const NodeGeo* __restrict__ geo, const NodeRange* __restrict__ rng,
                              const double* __restrict__ clo, const double* __restrict__ chi,
                              RefitCell* __restrict__ out) {
     const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -567,7 +576,7 @@ __global__ void k_refit_pack(int64_t nn, const NodeGeo* __restrict__ geo, const 
     const int e = (int)(g.level_leaf & 0xffu) + kRefitShift;
     const uint32_t ic[3] = {g.ix, g.iy, g.iz};
     RefitCell r;
-    r.pk = pack[c];
+    r.pk = pack16(g, rng[c]);
     bool ok = true;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -764,7 +773,7 @@ void refit_cells_and_groups(Tree& t, hipStream_t st) {
     }
     if (!t.rpack.get()) t.rpack.alloc(nn, st);
     hipLaunchKernelGGL(k_refit_pack, dim3(grid_for(nn, 256, 1 << 30)), dim3(256), 0, st, nn, t.geo.get(),
-                       t.pack.get(), t.clo.get(), t.chi.get(), t.rpack.get());
+                       t.range.get(), t.clo.get(), t.chi.get(), t.rpack.get());
     SRF_HIP(hipGetLastError());
     if (ng > 0) {
         hipLaunchKernelGGL(k_group_bbox<true>, dim3(grid_for(ng, 256 / kBoxLanes, 1 << 30)), dim3(256), 0, st, ng,
