@@ -667,15 +667,18 @@ struct Targets {
 // taken as zero, and their j-side sums are not added (the segment that owns
 // them adds its own).
 // Row sums through LDS: after each entry block a lane stores its four
-// partial sums in `part` ([block][value][row][17], rows padded against bank
-// conflicts); after every kGroupBlocks blocks (and at the segment's end)
+// partial sums in `part` ([block][value][row][16], each [row][16] group
+// followed by one padding word, so that both the stores of one value by the
+// 64 lanes and the reads of one partial index by them fall on distinct
+// banks in pairs); after every kGroupBlocks blocks (and at the segment's end)
 // lane (block, value, row) adds the row's 16 partials, and the totals of
 // (mu V_x, mu V_y, mu V_z, sum phi (d . w)) of each entry go to row ids[e]
 // of the j-side array with FP64 atomics (a zero, every pair of the entry
 // beyond r_cut, is not added).
 constexpr int kGroupBlocks = 4;
-constexpr int kPartRow = 17;
-constexpr int kPartBlock = 4 * kRows * kPartRow;
+constexpr int kPartRow = kRow;                     // one row's 16 partials
+constexpr int kPartValue = kRows * kPartRow + 1;   // one value of a block: 4 rows + padding
+constexpr int kPartBlock = 4 * kPartValue;
 
 __device__ __forceinline__ void lds_order() {
     // one wave: its LDS operations complete in order; this keeps the
@@ -694,7 +697,7 @@ __device__ __forceinline__ void adjoint_entries(int a, int b, const V4* tile, co
     T* wp = part + rb * kPartRow + ra;
     // this lane's sum in the reduction: block, value, row
     const int sb = lane >> 4, sv = (lane >> 2) & 3, sr = lane & 3;
-    const T* rp = part + sb * kPartBlock + sv * (kRows * kPartRow) + sr * kPartRow;
+    const T* rp = part + sb * kPartBlock + sv * kPartValue + sr * kPartRow;
     for (int eb = a; eb < b; eb += kRows) {
         const int e = eb + rb;
         V4 p = tile[e];
@@ -734,9 +737,9 @@ __device__ __forceinline__ void adjoint_entries(int a, int b, const V4* tile, co
         }
         T* w = wp + nblk * kPartBlock;
         w[0] = jx;
-        w[kRows * kPartRow] = jy;
-        w[2 * kRows * kPartRow] = jz;
-        w[3 * kRows * kPartRow] = jm;
+        w[kPartValue] = jy;
+        w[2 * kPartValue] = jz;
+        w[3 * kPartValue] = jm;
         ++nblk;
         if (nblk == kGroupBlocks || eb + kRows >= b) {
             lds_order();
