@@ -281,25 +281,65 @@ __device__ __forceinline__ bool in_run(const uint32_t* __restrict__ hi, int64_t 
     return (s > 0 && hi[s - 1] == h) || (s + 1 < n && hi[s + 1] == h);
 }
 
-__global__ void k_run_mark(int64_t n, const uint32_t* __restrict__ hi, int32_t* __restrict__ mark) {
+// The marks, and one past the last marked position: the largest over the
+// blocks, kept in kRunSlots slots (block b in slot b mod kRunSlots, zeroed
+// first) so that few atomics meet on one address.
+constexpr int kRunSlots = 1024;
+__global__ __launch_bounds__(256) void k_run_mark(int64_t n, const uint32_t* __restrict__ hi,
+                                                  int32_t* __restrict__ mark, int32_t* __restrict__ blast) {
+    __shared__ int32_t last;
+    if (threadIdx.x == 0) last = 0;
+    __syncthreads();
     const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    mark[s] = in_run(hi, n, s) ? 1 : 0;
+    const bool m = s < n && in_run(hi, n, s);
+    if (s < n) mark[s] = m ? 1 : 0;
+    // the wave's last marked lane, then the block's
+    const uint64_t b = __ballot(m);
+    if (b && (threadIdx.x & 63) == 0)
+        atomicMax(&last, (int32_t)(s + (63 - __clzll((long long)b)) + 1));
+    __syncthreads();
+    if (threadIdx.x == 0 && last > 0) atomicMax(&blast[blockIdx.x & (kRunSlots - 1)], last);
 }
 
-// `at`: exclusive scan of the marks (at[n] = their number)
-__global__ void k_run_compact(int64_t n, const uint32_t* __restrict__ hi, const int32_t* __restrict__ idx,
-                              const uint32_t* __restrict__ klo, const int32_t* __restrict__ at,
-                              uint32_t* __restrict__ clo, uint32_t* __restrict__ chi, int32_t* __restrict__ cidx,
-                              int32_t* __restrict__ cpos) {
+// rc[0] = one past the last marked position (the largest slot), so that
+// the scan of the marks can stop there and costs nothing when no two
+// particles share a high word; rc[1] = 0 (the number of marks, written by
+// the compaction).  One block, one slot per thread.
+__global__ __launch_bounds__(kRunSlots) void k_run_end(const int32_t* __restrict__ blast, int32_t* __restrict__ rc) {
+    __shared__ int32_t wmax[kRunSlots / 64];
+    int32_t v = blast[threadIdx.x];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const int32_t u = __shfl_xor(v, o, 64);
+        v = u > v ? u : v;
+    }
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t r = 0;
+        for (int w = 0; w < kRunSlots / 64; ++w) r = wmax[w] > r ? wmax[w] : r;
+        rc[0] = r;
+        rc[1] = 0;
+    }
+}
+
+// `at`: exclusive scan of the marks before rc[0]; the last marked position
+// writes their number to rc[1] (zeroed first).
+__global__ void k_run_compact(const int32_t* __restrict__ rc_end, const uint32_t* __restrict__ hi,
+                              const int32_t* __restrict__ idx, const uint32_t* __restrict__ klo,
+                              const int32_t* __restrict__ at, uint32_t* __restrict__ clo,
+                              uint32_t* __restrict__ chi, int32_t* __restrict__ cidx, int32_t* __restrict__ cpos,
+                              int32_t* __restrict__ rc_count, int64_t n) {
     const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (s >= n || !in_run(hi, n, s)) return;
+    const int64_t end = *rc_end;
+    if (s >= end || !in_run(hi, n, s)) return;
     const int64_t j = at[s];
     const int32_t i = idx[s];
     clo[j] = klo[i];
     chi[j] = hi[s];
     cidx[j] = i;
     cpos[j] = (int32_t)s;
+    if (s == end - 1) *rc_count = (int32_t)(j + 1);
 }
 
 // Run starts in the compacted array: rid[j] = 1 where run j begins (then
@@ -448,18 +488,21 @@ void build_sorted(Tree& t, const double* x, const double* y, const double* z, in
         pass(8 * (p + 1), hb.get(), ha.get(), vb.get(), t.perm.get(), nullptr, nullptr);
     }
     if (!full) {
-        DevBuf<int32_t> at(n + 1, st);
         const dim3 grid(grid_for(n, B, 1 << 30));
-        hipLaunchKernelGGL(k_run_mark, grid, dim3(B), 0, st, n, ha.get(), at.get());
+        DevBuf<int32_t> at(n + 1, st), rc(2, st), blast(kRunSlots, st);   // rc: end of the marks, their number
+        fill_i32(blast.get(), 0, kRunSlots, st);
+        hipLaunchKernelGGL(k_run_mark, grid, dim3(B), 0, st, n, ha.get(), at.get(), blast.get());
         SRF_HIP(hipGetLastError());
-        exclusive_scan_i32(at.get(), n, true, st);
+        hipLaunchKernelGGL(k_run_end, dim3(1), dim3(kRunSlots), 0, st, blast.get(), rc.get());
+        SRF_HIP(hipGetLastError());
+        exclusive_scan_i32_counted(at.get(), n, rc.get(), st);
         // the compacted runs: low word in kb, high word in hb, index in vb, position in cpos
         DevBuf<int32_t> cpos(n, st);
-        hipLaunchKernelGGL(k_run_compact, grid, dim3(B), 0, st, n, ha.get(), t.perm.get(), ka.get(), at.get(),
-                           kb.get(), hb.get(), vb.get(), cpos.get());
+        hipLaunchKernelGGL(k_run_compact, grid, dim3(B), 0, st, rc.get(), ha.get(), t.perm.get(), ka.get(),
+                           at.get(), kb.get(), hb.get(), vb.get(), cpos.get(), rc.get() + 1, n);
         SRF_HIP(hipGetLastError());
         // runs: numbers (exclusive scan of the starts) and first members
-        const int32_t* md = at.get() + n;
+        const int32_t* md = rc.get() + 1;
         DevBuf<int32_t> rid(n + 1, st), rstart(n + 1, st);
         hipLaunchKernelGGL(k_run_starts, grid, dim3(B), 0, st, md, hb.get(), rid.get());
         SRF_HIP(hipGetLastError());
