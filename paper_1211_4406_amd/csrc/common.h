@@ -31,6 +31,12 @@ void* dev_alloc(size_t bytes, hipStream_t stream);
 void dev_free(void* p, hipStream_t stream);
 void dev_release_all();
 
+// A second stream of the current device (non-blocking, default priority),
+// for work that overlaps the caller's stream; created on first use and kept
+// until the process ends.  Work on it is ordered by events only, and every
+// buffer it touches is allocated on the caller's stream.
+hipStream_t aux_stream();
+
 template <class T>
 struct DevBuf {
     T* p = nullptr;
@@ -130,6 +136,15 @@ struct Tree {
     // groups, in order of first
     DevBuf<int32_t> gfirst, gcount;
     DevBuf<double> glo, ghi;   // [ng*3]
+    // The sorted positions and masses may be gathered on aux_stream():
+    // `sorted` marks the sort's end on the build's stream, `gathered` the
+    // gather's end, which the build's stream waits for before the cells.
+    hipEvent_t sorted = nullptr, gathered = nullptr;
+    void release_events();   // waits for `gathered`, then destroys both
+    Tree() = default;
+    Tree(const Tree&) = delete;
+    Tree& operator=(const Tree&) = delete;
+    ~Tree() { release_events(); }   // before the buffers the gather writes are freed
 };
 
 struct Lists {
@@ -178,12 +193,13 @@ void exclusive_scan_i32_counted(int32_t* data, int64_t n_max, const int32_t* nd,
 // a1-a2: keys, sort, gather.  Sets bits of the device error flag *d_flag
 // (bit 0: non-finite position, bit 1: bad mass; bit 3: a run of more than
 // kRunMax particles shares the high key word, so the order is incomplete and
-// the sort must be run again with `full`).
+// the sort must be run again with `full`).  Without `full` the positions
+// and masses are gathered on aux_stream() (t.gathered marks their end).
 void build_sorted(Tree& t, const double* x, const double* y, const double* z, int64_t ps,
                   const double* m, int64_t ms, int32_t* d_flag, bool full, hipStream_t stream);
-// a3-a5; synchronises `stream` once, and fails with SRF_EDOMAIN if bit 0 or
-// 1 of *d_flag (set by build_sorted) is set.  Returns false, having built
-// nothing, if bit 3 is set.
+// a3-a5; synchronises `stream` once, then makes it wait for t.gathered, and
+// fails with SRF_EDOMAIN if bit 0 or 1 of *d_flag (set by build_sorted) is
+// set.  Returns false, having built nothing, if bit 3 is set.
 bool build_cells_and_groups(Tree& t, int32_t* d_flag, hipStream_t stream);
 // Tree reuse: positions and masses (m may be NULL: masses kept) gathered in
 // the tree's sorted order into px..pm, wrapped, with the same checks as

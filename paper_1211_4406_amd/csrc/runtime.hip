@@ -105,6 +105,32 @@ void dev_release_all() {
     c.free_blocks.clear();
 }
 
+hipStream_t aux_stream() {
+    static std::mutex mu;
+    static std::map<int, hipStream_t>* streams = new std::map<int, hipStream_t>();   // never destroyed
+    int dev = 0;
+    SRF_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = streams->find(dev);
+    if (it != streams->end()) return it->second;
+    hipStream_t s = nullptr;
+    SRF_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    (*streams)[dev] = s;
+    return s;
+}
+
+void Tree::release_events() {
+    if (gathered) {
+        (void)hipEventSynchronize(gathered);
+        (void)hipEventDestroy(gathered);
+        gathered = nullptr;
+    }
+    if (sorted) {
+        (void)hipEventDestroy(sorted);
+        sorted = nullptr;
+    }
+}
+
 // ------------------------------------------------------------------ fills
 template <class T>
 __global__ void k_fill(T* __restrict__ p, T v, int64_t n) {

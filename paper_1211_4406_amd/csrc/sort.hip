@@ -275,6 +275,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(int64_t n, const uint32_t*
 // shares (mark 1), compacted in order with their low words, and each such
 // run put in (low word, index) order by counting.
 constexpr int64_t kRunMax = 1024;
+constexpr int kRunGrid = 4096;   // blocks of the kernels that loop over the run members
 
 __device__ __forceinline__ bool in_run(const uint32_t* __restrict__ hi, int64_t n, int64_t s) {
     const uint32_t h = hi[s];
@@ -330,26 +331,26 @@ __global__ void k_run_compact(const int32_t* __restrict__ rc_end, const uint32_t
                               const int32_t* __restrict__ at, uint32_t* __restrict__ clo,
                               uint32_t* __restrict__ chi, int32_t* __restrict__ cidx, int32_t* __restrict__ cpos,
                               int32_t* __restrict__ rc_count, int64_t n) {
-    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t end = *rc_end;
-    if (s >= end || !in_run(hi, n, s)) return;
-    const int64_t j = at[s];
-    const int32_t i = idx[s];
-    clo[j] = klo[i];
-    chi[j] = hi[s];
-    cidx[j] = i;
-    cpos[j] = (int32_t)s;
-    if (s == end - 1) *rc_count = (int32_t)(j + 1);
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < end; s += (int64_t)gridDim.x * blockDim.x) {
+        if (!in_run(hi, n, s)) continue;
+        const int64_t j = at[s];
+        const int32_t i = idx[s];
+        clo[j] = klo[i];
+        chi[j] = hi[s];
+        cidx[j] = i;
+        cpos[j] = (int32_t)s;
+        if (s == end - 1) *rc_count = (int32_t)(j + 1);
+    }
 }
 
 // Run starts in the compacted array: rid[j] = 1 where run j begins (then
 // scanned into run numbers).
 __global__ void k_run_starts(const int32_t* __restrict__ md, const uint32_t* __restrict__ chi,
                              int32_t* __restrict__ rid) {
-    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t m = *md;
-    if (j >= m) return;
-    rid[j] = (j == 0 || chi[j] != chi[j - 1]) ? 1 : 0;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < m; j += (int64_t)gridDim.x * blockDim.x)
+        rid[j] = (j == 0 || chi[j] != chi[j - 1]) ? 1 : 0;
 }
 
 // rstart[r] = first member of run r (rid: exclusive scan of the starts,
@@ -357,13 +358,13 @@ __global__ void k_run_starts(const int32_t* __restrict__ md, const uint32_t* __r
 // rstart[number of runs] = m.
 __global__ void k_run_index(const int32_t* __restrict__ md, const uint32_t* __restrict__ chi,
                             const int32_t* __restrict__ rid, int32_t* __restrict__ rstart) {
-    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t m = *md;
-    if (j > m) return;
-    if (j == m) {
-        rstart[rid[m]] = (int32_t)m;
-    } else if (j == 0 || chi[j] != chi[j - 1]) {
-        rstart[rid[j]] = (int32_t)j;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j <= m; j += (int64_t)gridDim.x * blockDim.x) {
+        if (j == m) {
+            rstart[rid[m]] = (int32_t)m;
+        } else if (j == 0 || chi[j] != chi[j - 1]) {
+            rstart[rid[j]] = (int32_t)j;
+        }
     }
 }
 
@@ -375,28 +376,30 @@ __global__ void k_run_rank(int64_t n, const int32_t* __restrict__ md, const uint
                            const int32_t* __restrict__ cidx, const int32_t* __restrict__ cpos,
                            const int32_t* __restrict__ rid, const int32_t* __restrict__ rstart,
                            int32_t* __restrict__ perm, int32_t* __restrict__ flag) {
-    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (j >= *md) return;
-    const int32_t r = rid[j + 1] - 1;   // starts in [0, j], less one: j's run
-    const int32_t r0 = rstart[r], r1 = rstart[r + 1];
-    if (r1 - r0 > kRunMax) {
-        atomicOr(flag, 8);
-        return;
-    }
-    const uint32_t lo = clo[j];
-    const int32_t id = cidx[j];
-    int32_t rank = 0;
+    const int64_t m = *md;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < m; j += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t r = rid[j + 1] - 1;   // starts in [0, j], less one: j's run
+        const int32_t r0 = rstart[r], r1 = rstart[r + 1];
+        if (r1 - r0 > kRunMax) {
+            atomicOr(flag, 8);
+            continue;
+        }
+        const uint32_t lo = clo[j];
+        const int32_t id = cidx[j];
+        int32_t rank = 0;
 #pragma unroll 4
-    for (int32_t k = r0; k < r1; ++k) {
-        const uint32_t l = clo[k];
-        rank += (l < lo || (l == lo && cidx[k] < id)) ? 1 : 0;
+        for (int32_t k = r0; k < r1; ++k) {
+            const uint32_t l = clo[k];
+            rank += (l < lo || (l == lo && cidx[k] < id)) ? 1 : 0;
+        }
+        const int32_t p = cpos[r0 + rank];
+        if ((uint64_t)p < (uint64_t)n) perm[p] = id;
     }
-    const int32_t p = cpos[r0 + rank];
-    if ((uint64_t)p < (uint64_t)n) perm[p] = id;
 }
 
-// The sorted particles, and their keys computed again from the wrapped
-// positions exactly as k_keys computed them.
+// The sorted particles and, with KEYS, their keys computed again from the
+// wrapped positions exactly as k_keys computed them.
+template <bool KEYS>
 __global__ void k_gather(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ x,
                          const double* __restrict__ y, const double* __restrict__ z, int64_t ps,
                          const double* __restrict__ m, int64_t ms, double* __restrict__ px, double* __restrict__ py,
@@ -409,7 +412,16 @@ __global__ void k_gather(int64_t n, const int32_t* __restrict__ perm, const doub
     py[s] = v;
     pz[s] = w;
     pm[s] = m[i * ms];
-    keys[s] = (spread3(grid21(u)) << 2) | (spread3(grid21(v)) << 1) | spread3(grid21(w));
+    if (KEYS) keys[s] = (spread3(grid21(u)) << 2) | (spread3(grid21(v)) << 1) | spread3(grid21(w));
+}
+
+// The sorted keys from the sorted high words and the low words k_keys left
+// in input order.
+__global__ void k_sorted_keys(int64_t n, const int32_t* __restrict__ perm, const uint32_t* __restrict__ hi,
+                              const uint32_t* __restrict__ lo, uint64_t* __restrict__ keys) {
+    int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    keys[s] = ((uint64_t)hi[s] << 32) | lo[perm[s]];
 }
 
 // The same gather for a tree reused at new positions, with the input checks
@@ -498,16 +510,21 @@ void build_sorted(Tree& t, const double* x, const double* y, const double* z, in
         exclusive_scan_i32_counted(at.get(), n, rc.get(), st);
         // the compacted runs: low word in kb, high word in hb, index in vb, position in cpos
         DevBuf<int32_t> cpos(n, st);
-        hipLaunchKernelGGL(k_run_compact, grid, dim3(B), 0, st, rc.get(), ha.get(), t.perm.get(), ka.get(),
+        // the kernels below loop over a count held on the device: a grid of
+        // kRunGrid blocks covers any count, and costs little when it is 0
+        // (the ranking, whose members' work varies with their run's length,
+        // keeps one thread per position)
+        const dim3 rgrid(grid_for(n + 1, B, kRunGrid));
+        hipLaunchKernelGGL(k_run_compact, rgrid, dim3(B), 0, st, rc.get(), ha.get(), t.perm.get(), ka.get(),
                            at.get(), kb.get(), hb.get(), vb.get(), cpos.get(), rc.get() + 1, n);
         SRF_HIP(hipGetLastError());
         // runs: numbers (exclusive scan of the starts) and first members
         const int32_t* md = rc.get() + 1;
         DevBuf<int32_t> rid(n + 1, st), rstart(n + 1, st);
-        hipLaunchKernelGGL(k_run_starts, grid, dim3(B), 0, st, md, hb.get(), rid.get());
+        hipLaunchKernelGGL(k_run_starts, rgrid, dim3(B), 0, st, md, hb.get(), rid.get());
         SRF_HIP(hipGetLastError());
         exclusive_scan_i32_counted(rid.get(), n, md, st);
-        hipLaunchKernelGGL(k_run_index, dim3(grid_for(n + 1, B, 1 << 30)), dim3(B), 0, st, md, hb.get(), rid.get(),
+        hipLaunchKernelGGL(k_run_index, rgrid, dim3(B), 0, st, md, hb.get(), rid.get(),
                            rstart.get());
         SRF_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_run_rank, grid, dim3(B), 0, st, n, md, kb.get(), vb.get(), cpos.get(), rid.get(),
@@ -518,9 +535,28 @@ void build_sorted(Tree& t, const double* x, const double* y, const double* z, in
     t.py.alloc(n, st);
     t.pz.alloc(n, st);
     t.pm.alloc(n, st);
-    hipLaunchKernelGGL(k_gather, dim3(grid_for(n, B, 1 << 30)), dim3(B), 0, st, n, t.perm.get(), x, y, z, ps, m,
-                       ms, t.px.get(), t.py.get(), t.pz.get(), t.pm.get(), t.keys.get());
+    t.release_events();
+    if (full) {
+        hipLaunchKernelGGL(k_gather<true>, dim3(grid_for(n, B, 1 << 30)), dim3(B), 0, st, n, t.perm.get(), x, y, z,
+                           ps, m, ms, t.px.get(), t.py.get(), t.pz.get(), t.pm.get(), t.keys.get());
+        SRF_HIP(hipGetLastError());
+        return;
+    }
+    // the keys from the sort's words (ha sorted, ka still in input order);
+    // the positions and masses on the second stream, where they overlap the
+    // cell levels and the tree build's one synchronisation
+    hipLaunchKernelGGL(k_sorted_keys, dim3(grid_for(n, B, 1 << 30)), dim3(B), 0, st, n, t.perm.get(), ha.get(),
+                       ka.get(), t.keys.get());
     SRF_HIP(hipGetLastError());
+    hipStream_t aux = aux_stream();
+    SRF_HIP(hipEventCreateWithFlags(&t.sorted, hipEventDisableTiming));
+    SRF_HIP(hipEventCreateWithFlags(&t.gathered, hipEventDisableTiming));
+    SRF_HIP(hipEventRecord(t.sorted, st));
+    SRF_HIP(hipStreamWaitEvent(aux, t.sorted, 0));
+    hipLaunchKernelGGL(k_gather<false>, dim3(grid_for(n, B, 1 << 30)), dim3(B), 0, aux, n, t.perm.get(), x, y, z,
+                       ps, m, ms, t.px.get(), t.py.get(), t.pz.get(), t.pm.get(), (uint64_t*)nullptr);
+    SRF_HIP(hipGetLastError());
+    SRF_HIP(hipEventRecord(t.gathered, aux));
 }
 
 }  // namespace srf

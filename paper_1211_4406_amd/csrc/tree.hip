@@ -679,6 +679,8 @@ bool build_cells_and_groups(Tree& t, int32_t* d_flag, hipStream_t st) {
     Summary hs;
     SRF_HIP(hipMemcpyAsync(&hs, dsum.get(), sizeof(Summary), hipMemcpyDeviceToHost, st));
     SRF_HIP(hipStreamSynchronize(st));
+    // the cells below read the sorted positions, gathered on the second stream
+    if (t.gathered) SRF_HIP(hipStreamWaitEvent(st, t.gathered, 0));
     if (hs.flag & 1) fail(SRF_EDOMAIN, "non-finite particle position");
     if (hs.flag & 2) fail(SRF_EDOMAIN, "particle mass not finite and > 0");
     if (hs.flag & 8) return false;   // the order is incomplete (see build_sorted)
