@@ -113,7 +113,10 @@ typedef struct srf_lists srf_lists;
  *   out:        (host) receives the new handle.
  * The inputs are copied; they may be reused once `stream` passes this call.
  * Synchronises `stream` once (to read the number of cells and groups and
- * the device's check of the inputs).
+ * the device's check of the inputs).  Part of the work runs on a second,
+ * library-owned stream of the same device (created on first use, default
+ * priority); `stream` waits for it before this call returns, so work
+ * queued on `stream` afterwards sees the whole tree.
  * Errors: SRF_EINVAL, SRF_EDOMAIN (checked on the device, reported here),
  * SRF_ENOMEM, SRF_EHIP.  On error *out is NULL. */
 int srf_tree_build(int64_t n, const double* x, const double* y, const double* z, int64_t pos_stride,

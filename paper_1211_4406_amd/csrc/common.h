@@ -136,11 +136,13 @@ struct Tree {
     // groups, in order of first
     DevBuf<int32_t> gfirst, gcount;
     DevBuf<double> glo, ghi;   // [ng*3]
-    // The sorted positions and masses may be gathered on aux_stream():
-    // `sorted` marks the sort's end on the build's stream, `gathered` the
-    // gather's end, which the build's stream waits for before the cells.
-    hipEvent_t sorted = nullptr, gathered = nullptr;
-    void release_events();   // waits for `gathered`, then destroys both
+    // Work of the build on aux_stream(): the gather of the sorted positions
+    // and masses (after `sorted`, recorded on the build's stream; it ends at
+    // `gathered`, which the build's stream waits for before the cells) and
+    // the groups (after `sized`; they end at `grouped`, which the build's
+    // stream waits for before the build returns).
+    hipEvent_t sorted = nullptr, gathered = nullptr, sized = nullptr, grouped = nullptr;
+    void release_events();   // waits for `gathered` and `grouped`, then destroys all four
     Tree() = default;
     Tree(const Tree&) = delete;
     Tree& operator=(const Tree&) = delete;

@@ -2,6 +2,7 @@
 // kernels and the device-wide exclusive scan.
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -120,14 +121,11 @@ hipStream_t aux_stream() {
 }
 
 void Tree::release_events() {
-    if (gathered) {
-        (void)hipEventSynchronize(gathered);
-        (void)hipEventDestroy(gathered);
-        gathered = nullptr;
-    }
-    if (sorted) {
-        (void)hipEventDestroy(sorted);
-        sorted = nullptr;
+    for (hipEvent_t* e : {&gathered, &grouped})
+        if (*e) (void)hipEventSynchronize(*e);
+    for (hipEvent_t* e : {&sorted, &gathered, &sized, &grouped}) {
+        if (*e) (void)hipEventDestroy(*e);
+        *e = nullptr;
     }
 }
 

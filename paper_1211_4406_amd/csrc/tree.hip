@@ -721,6 +721,35 @@ bool build_cells_and_groups(Tree& t, int32_t* d_flag, hipStream_t st) {
     int32_t* schild = t.schild.get();
     DevBuf<int32_t> pfirst(nn, st), scount(nn, st);
     DevBuf<double> sM(nn, st), sX(nn, st), sY(nn, st), sZ(nn, st);
+
+    // groups (from the marks and the sorted positions alone) on the second
+    // stream, beside the cells
+    t.gfirst.alloc(ng, st);
+    t.gcount.alloc(ng, st);
+    t.glo.alloc(ng * 3, st);
+    t.ghi.alloc(ng * 3, st);
+    hipStream_t aux = aux_stream();
+    SRF_HIP(hipEventCreateWithFlags(&t.sized, hipEventDisableTiming));
+    SRF_HIP(hipEventCreateWithFlags(&t.grouped, hipEventDisableTiming));
+    SRF_HIP(hipEventRecord(t.sized, st));
+    SRF_HIP(hipStreamWaitEvent(aux, t.sized, 0));
+    hipLaunchKernelGGL(k_group_write, dim3(grid_for(n, B, 1 << 30)), dim3(B), 0, aux, n, mark.get(), t.gfirst.get());
+    SRF_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_group_count, dim3(grid_for(ng, B, 1 << 30)), dim3(B), 0, aux, ng, n, t.gfirst.get(),
+                       t.gcount.get());
+    SRF_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_group_bbox<false>, dim3(grid_for(ng, 256 / kBoxLanes, 1 << 30)), dim3(256), 0, aux, ng,
+                       t.gfirst.get(), t.gcount.get(), t.px.get(), t.py.get(), t.pz.get(), t.glo.get(), t.ghi.get());
+    SRF_HIP(hipGetLastError());
+    SRF_HIP(hipEventRecord(t.grouped, aux));
+    // the build's stream waits for the groups before the marks are freed
+    // (declared after them, so destroyed first) and before it returns
+    struct JoinAtExit {
+        hipStream_t st;
+        hipEvent_t e;
+        ~JoinAtExit() { (void)hipStreamWaitEvent(st, e, 0); }
+    } join{st, t.grouped};
+
     hipLaunchKernelGGL(k_cells, dim3((unsigned)nblocks), dim3(kLvThreads), 0, st, n, nblocks, t.keys.get(),
                        delta.get(), leaflv.get(), start.get(), base, blk.get(), t.geo.get(), pfirst.get(),
                        t.prefix.get(), sfirst, spre, schild);
@@ -737,21 +766,6 @@ bool build_cells_and_groups(Tree& t, int32_t* d_flag, hipStream_t st) {
     }
     hipLaunchKernelGGL(k_pack, dim3(grid_for(nn, B, 1 << 30)), dim3(B), 0, st, nn, t.geo.get(), t.range.get(),
                        t.pack.get());
-    SRF_HIP(hipGetLastError());
-
-    // groups
-    t.gfirst.alloc(ng, st);
-    t.gcount.alloc(ng, st);
-    t.glo.alloc(ng * 3, st);
-    t.ghi.alloc(ng * 3, st);
-    hipLaunchKernelGGL(k_group_write, dim3(grid_for(n, B, 1 << 30)), dim3(B), 0, st, n, mark.get(), t.gfirst.get());
-    SRF_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_group_count, dim3(grid_for(ng, B, 1 << 30)), dim3(B), 0, st, ng, n, t.gfirst.get(),
-                       t.gcount.get());
-    SRF_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_group_bbox<false>, dim3(grid_for(ng, 256 / kBoxLanes, 1 << 30)), dim3(256), 0, st, ng,
-                       t.gfirst.get(),
-                       t.gcount.get(), t.px.get(), t.py.get(), t.pz.get(), t.glo.get(), t.ghi.get());
     SRF_HIP(hipGetLastError());
     return true;
 }
