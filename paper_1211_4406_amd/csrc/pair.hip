@@ -644,10 +644,10 @@ struct AdjOut {
 //   - V = J w_i and phi (d . w_i) are summed in registers over the NB
 //     blocks; the lane stores these four partial sums in LDS, and after
 //     every four entry blocks each lane adds the 16 partials of one (entry,
-//     value) of them (LDS operations, which issue beside the vector ALU,
-//     where summing across the row in registers took 6 selects and 5 DPP
-//     adds per block), scales the entry's V by its mass and adds the total
-//     to the source's gradient with an FP64 atomic.
+//     value), scales the entry's V by its mass and adds the total to the
+//     source's gradient with an FP64 atomic (the stores and reads are LDS
+//     operations, which issue beside the vector ALU; a sum across the row's
+//     lanes in registers costs 6 selects and 5 DPP adds per block).
 // Targets past N_i carry zero weight, so they add nothing to either side.
 constexpr int kRow = 16;   // lanes per row: targets per block
 constexpr int kRows = 4;   // rows: entries per block
