@@ -332,9 +332,10 @@ __global__ __launch_bounds__(kListThreads) void k_lists(int64_t ng, const double
 
 // Expansion: one wave per group turns its items into entries.  A leaf item
 // stands for its particles first..first+count-1, a cell item for itself.
-// Items are taken kExpandItems at a time: each lane loads four of them and
-// then their leaves' ranges (all loads of a batch in flight together), a
-// scan of the item sizes places each item, and the entries are written
+// Items are taken kExpandItems at a time: each lane loads four of them, the
+// next batch's four while it places these, and the four items' ranges (all
+// of a batch's range loads in flight together), a scan of the item sizes
+// places each item, and the entries are written
 // either through an LDS buffer (each lane writes its own items' entries,
 // then the wave copies the buffer out, 64 consecutive entries per store) or,
 // when the batch's entries exceed the buffer, directly, lane k writing
@@ -343,7 +344,7 @@ __global__ __launch_bounds__(kListThreads) void k_lists(int64_t ng, const double
 // Items of group g: icnt[g] of them from g * slot when slot > 0, else
 // [ioff[g], ioff[g + 1]).
 constexpr int kExpandBuf = 1024;
-constexpr int kExpandPer = 2;                   // items per lane per batch
+constexpr int kExpandPer = 4;                   // items per lane per batch
 constexpr int kExpandItems = 64 * kExpandPer;   // items per batch
 
 __global__ __launch_bounds__(64) void k_expand(int64_t ng, int64_t slot, const int64_t* __restrict__ icnt,
@@ -358,23 +359,32 @@ __global__ __launch_bounds__(64) void k_expand(int64_t ng, int64_t slot, const i
     const int64_t i0 = slot > 0 ? g * slot : ioff[g];
     const int64_t i1 = slot > 0 ? i0 + icnt[g] : ioff[g + 1];
     int32_t* dst = ent + off[g];
+    // item q = 64 k + lane of the batch at c0
+    int32_t v[kExpandPer];
+#pragma unroll
+    for (int k = 0; k < kExpandPer; ++k) {
+        const int64_t ii = i0 + 64 * k + lane;
+        v[k] = ii < i1 ? items[ii] : INT32_MIN;
+    }
     for (int64_t c0 = i0; c0 < i1; c0 += kExpandItems) {
-        // item q = 64 k + lane of the batch
-        int32_t v[kExpandPer], first[kExpandPer], n[kExpandPer];
+        // every lane loads a range (a cell item or an empty place that of
+        // cell 0, unused), so that no branch separates the batch's loads
+        int32_t rf[kExpandPer], rc[kExpandPer], vn[kExpandPer], first[kExpandPer], n[kExpandPer];
 #pragma unroll
         for (int k = 0; k < kExpandPer; ++k) {
-            const int64_t ii = c0 + 64 * k + lane;
-            v[k] = ii < i1 ? items[ii] : INT32_MIN;
+            const NodeRange& r = rng[v[k] >= 0 ? v[k] : 0];
+            rf[k] = r.first;
+            rc[k] = r.count;
         }
 #pragma unroll
         for (int k = 0; k < kExpandPer; ++k) {
-            first[k] = v[k];
-            n[k] = v[k] == INT32_MIN ? 0 : 1;
-            if (v[k] >= 0) {
-                const NodeRange r = rng[v[k]];
-                first[k] = r.first;
-                n[k] = r.count;
-            }
+            const int64_t ii = c0 + kExpandItems + 64 * k + lane;
+            vn[k] = ii < i1 ? items[ii] : INT32_MIN;
+        }
+#pragma unroll
+        for (int k = 0; k < kExpandPer; ++k) {
+            first[k] = v[k] >= 0 ? rf[k] : v[k];
+            n[k] = v[k] >= 0 ? rc[k] : (v[k] == INT32_MIN ? 0 : 1);
         }
         uint64_t leafmask[kExpandPer];
         int carry = 0;
@@ -426,6 +436,8 @@ __global__ __launch_bounds__(64) void k_expand(int64_t ng, int64_t slot, const i
             __syncthreads();
         }
         dst += total;
+#pragma unroll
+        for (int k = 0; k < kExpandPer; ++k) v[k] = vn[k];
     }
 }
 
