@@ -91,6 +91,10 @@ __global__ __launch_bounds__(kLvThreads) void k_levels(int64_t n, const uint64_t
     const int64_t b0 = blockIdx.x * (int64_t)kLvTile;
     const int tid = threadIdx.x, lane = tid & 63;
     if (tid < kLevels) lh[tid] = 0;
+    if (blockIdx.x == 0 && tid == 0) {   // the entries past the end, for the scans' totals
+        chain[n] = 0;
+        mark[n] = 0;
+    }
     for (int j = tid; j < kScanSpan; j += kLvThreads) {
         const int64_t i = b0 - kLeft + j;
         int d = -1;
@@ -664,8 +668,6 @@ bool build_cells_and_groups(Tree& t, int32_t* d_flag, hipStream_t st) {
     DevBuf<int8_t> delta(n, st), leaflv(n, st);
     DevBuf<int32_t> start(n + 1, st), mark(n + 1, st), blk(kLevels * nblocks, st), tot(kLevels, st);
     DevBuf<Summary> dsum(1, st);
-    fill_i32(start.get() + n, 0, 1, st);
-    fill_i32(mark.get() + n, 0, 1, st);
     hipLaunchKernelGGL(k_levels, dim3((unsigned)nblocks), dim3(kLvThreads), 0, st, n, t.keys.get(), t.n_leaf,
                        t.n_group, nblocks, delta.get(), leaflv.get(), start.get(), mark.get(), blk.get());
     SRF_HIP(hipGetLastError());
@@ -721,34 +723,11 @@ bool build_cells_and_groups(Tree& t, int32_t* d_flag, hipStream_t st) {
     int32_t* schild = t.schild.get();
     DevBuf<int32_t> pfirst(nn, st), scount(nn, st);
     DevBuf<double> sM(nn, st), sX(nn, st), sY(nn, st), sZ(nn, st);
-
-    // groups (from the marks and the sorted positions alone) on the second
-    // stream, beside the cells
-    t.gfirst.alloc(ng, st);
-    t.gcount.alloc(ng, st);
-    t.glo.alloc(ng * 3, st);
-    t.ghi.alloc(ng * 3, st);
+    // the point after which the second stream may build the groups
     hipStream_t aux = aux_stream();
     SRF_HIP(hipEventCreateWithFlags(&t.sized, hipEventDisableTiming));
     SRF_HIP(hipEventCreateWithFlags(&t.grouped, hipEventDisableTiming));
     SRF_HIP(hipEventRecord(t.sized, st));
-    SRF_HIP(hipStreamWaitEvent(aux, t.sized, 0));
-    hipLaunchKernelGGL(k_group_write, dim3(grid_for(n, B, 1 << 30)), dim3(B), 0, aux, n, mark.get(), t.gfirst.get());
-    SRF_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_group_count, dim3(grid_for(ng, B, 1 << 30)), dim3(B), 0, aux, ng, n, t.gfirst.get(),
-                       t.gcount.get());
-    SRF_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_group_bbox<false>, dim3(grid_for(ng, 256 / kBoxLanes, 1 << 30)), dim3(256), 0, aux, ng,
-                       t.gfirst.get(), t.gcount.get(), t.px.get(), t.py.get(), t.pz.get(), t.glo.get(), t.ghi.get());
-    SRF_HIP(hipGetLastError());
-    SRF_HIP(hipEventRecord(t.grouped, aux));
-    // the build's stream waits for the groups before the marks are freed
-    // (declared after them, so destroyed first) and before it returns
-    struct JoinAtExit {
-        hipStream_t st;
-        hipEvent_t e;
-        ~JoinAtExit() { (void)hipStreamWaitEvent(st, e, 0); }
-    } join{st, t.grouped};
 
     hipLaunchKernelGGL(k_cells, dim3((unsigned)nblocks), dim3(kLvThreads), 0, st, n, nblocks, t.keys.get(),
                        delta.get(), leaflv.get(), start.get(), base, blk.get(), t.geo.get(), pfirst.get(),
@@ -766,6 +745,34 @@ bool build_cells_and_groups(Tree& t, int32_t* d_flag, hipStream_t st) {
     }
     hipLaunchKernelGGL(k_pack, dim3(grid_for(nn, B, 1 << 30)), dim3(B), 0, st, nn, t.geo.get(), t.range.get(),
                        t.pack.get());
+    SRF_HIP(hipGetLastError());
+
+    // groups (from the marks and the sorted positions alone) on the second
+    // stream, beside the cells (queued after them: the cells are the longer
+    // chain)
+    t.gfirst.alloc(ng, st);
+    t.gcount.alloc(ng, st);
+    t.glo.alloc(ng * 3, st);
+    t.ghi.alloc(ng * 3, st);
+    // on every way out (an error included) `grouped` marks all the work
+    // queued on the second stream, and the build's stream waits for it
+    // before the marks are freed (declared after them, so destroyed first)
+    struct JoinAtExit {
+        hipStream_t st, aux;
+        hipEvent_t e;
+        ~JoinAtExit() {
+            (void)hipEventRecord(e, aux);
+            (void)hipStreamWaitEvent(st, e, 0);
+        }
+    } join{st, aux, t.grouped};
+    SRF_HIP(hipStreamWaitEvent(aux, t.sized, 0));
+    hipLaunchKernelGGL(k_group_write, dim3(grid_for(n, B, 1 << 30)), dim3(B), 0, aux, n, mark.get(), t.gfirst.get());
+    SRF_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_group_count, dim3(grid_for(ng, B, 1 << 30)), dim3(B), 0, aux, ng, n, t.gfirst.get(),
+                       t.gcount.get());
+    SRF_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_group_bbox<false>, dim3(grid_for(ng, 256 / kBoxLanes, 1 << 30)), dim3(256), 0, aux, ng,
+                       t.gfirst.get(), t.gcount.get(), t.px.get(), t.py.get(), t.pz.get(), t.glo.get(), t.ghi.get());
     SRF_HIP(hipGetLastError());
     return true;
 }
