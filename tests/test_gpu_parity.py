@@ -489,6 +489,36 @@ def test_work_ordered_on_the_callers_stream():
             assert torch.allclose(gm, gm0, rtol=1e-12, atol=1e-12 * gm0.abs().max().item())
 
 
+def test_inputs_reusable_once_the_stream_passes_the_build():
+    """The tree build gathers the sorted particles on the library's second
+    stream; the caller's stream waits for that gather before the call
+    returns, so inputs overwritten on that stream right after the call leave
+    the tree as built from the originals (2^22 particles: a gather long
+    enough that a missing wait would let the overwrite reach it)."""
+    rng = np.random.default_rng(1717)
+    n = 1 << 22
+    p = srf.Params(r_cut=0.02, eps=1e-4)
+    x = torch.tensor(rng.random((n, 3)), dtype=torch.float64, device="cuda")
+    m = torch.tensor(rng.random(n) + 0.5, dtype=torch.float64, device="cuda")
+    x0, m0 = x.clone(), m.clone()
+    for st in (torch.cuda.current_stream(), torch.cuda.Stream()):
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            x.copy_(x0)
+            m.copy_(m0)
+            tree = srf.tree_build(x, m, p)
+            x.fill_(0.5)
+            m.fill_(2.0)
+        st.synchronize()
+        ref = srf.tree_build(x0, m0, p)
+        torch.cuda.synchronize()
+        xs, ms = tree.sorted_particles()
+        xr, mr = ref.sorted_particles()
+        assert np.array_equal(xs, xr) and np.array_equal(ms, mr)
+        assert np.array_equal(tree.export()["gfirst"], ref.export()["gfirst"])
+        del tree, ref
+
+
 def test_domain_errors_reported():
     p = srf.Params(r_cut=0.1, eps=1e-3)
     x = torch.rand((100, 3), dtype=torch.float64, device="cuda")
