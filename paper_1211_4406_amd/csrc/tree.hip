@@ -68,7 +68,8 @@ __device__ __forceinline__ int64_t first_equal(const uint64_t* __restrict__ keys
 
 // Per particle: delta, leaf level, the chain length of the cells starting
 // there and the group-start mark; per block and level the number of cells
-// (blk[L * nblocks + block]).
+// (blk[L * nblocks + block]), and per block the sums of the chain lengths
+// and of the marks (rows kLevels and kLevels + 1 of blk).
 //
 // Group starts.  A candidate (level >= 1, at most n_group particles, parent
 // the root or holding more than n_group) starts a group under the root, and
@@ -87,14 +88,10 @@ __global__ __launch_bounds__(kLvThreads) void k_levels(int64_t n, const uint64_t
     __shared__ int8_t mn[kLog][kLvSpan];   // mn[k][j] = min delta over [j, j + 2^k)
     __shared__ int8_t mx[kLog][kLvRuns];   // mx[k][j] = max run minimum over run starts [j, j + 2^k)
     __shared__ int8_t dl[kScanSpan];       // delta of global index b0 - kLeft + j
-    __shared__ unsigned lh[kLevels];
+    __shared__ unsigned lh[kLevels + 2];   // cells per level; the tile's chain and mark sums
     const int64_t b0 = blockIdx.x * (int64_t)kLvTile;
     const int tid = threadIdx.x, lane = tid & 63;
-    if (tid < kLevels) lh[tid] = 0;
-    if (blockIdx.x == 0 && tid == 0) {   // the entries past the end, for the scans' totals
-        chain[n] = 0;
-        mark[n] = 0;
-    }
+    if (tid < kLevels + 2) lh[tid] = 0;
     for (int j = tid; j < kScanSpan; j += kLvThreads) {
         const int64_t i = b0 - kLeft + j;
         int d = -1;
@@ -148,6 +145,7 @@ __global__ __launch_bounds__(kLvThreads) void k_levels(int64_t n, const uint64_t
         }
         __syncthreads();
     }
+    int32_t csum = 0, msum = 0;   // this thread's chain lengths and group marks
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
         const int64_t s = b0 + tid + q * kLvThreads;   // a wave holds 64 consecutive particles
@@ -164,6 +162,7 @@ __global__ __launch_bounds__(kLvThreads) void k_levels(int64_t n, const uint64_t
             delta[s] = (int8_t)d;
             leaflv[s] = (int8_t)ll;
             chain[s] = ll > d ? ll - d : 0;
+            csum += ll > d ? ll - d : 0;
             for (int L = d + 1; L <= ll; ++L) atomicAdd(&lh[L], 1u);
             if (lg >= kMaxLevel) {
                 m = ((s - first_equal(keys, 0, s)) % n_group) == 0;   // chunks of a level-21 cell
@@ -213,13 +212,100 @@ __global__ __launch_bounds__(kLvThreads) void k_levels(int64_t n, const uint64_t
             if (lane == src) m = !(open && run + own <= n_group);
         }
         if (on) mark[s] = m;
+        msum += on ? m : 0;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        csum += __shfl_xor(csum, o, 64);
+        msum += __shfl_xor(msum, o, 64);
+    }
+    if (lane == 0) {
+        atomicAdd(&lh[kLevels], (unsigned)csum);
+        atomicAdd(&lh[kLevels + 1], (unsigned)msum);
     }
     __syncthreads();
-    if (tid < kLevels) blk[(int64_t)tid * nblocks + blockIdx.x] = (int32_t)lh[tid];
+    if (tid < kLevels + 2) blk[(int64_t)tid * nblocks + blockIdx.x] = (int32_t)lh[tid];
+}
+
+// In place, over the tiles of k_levels: the exclusive scans of the chain
+// lengths (the preorder number of each chain's first cell) and of the group
+// marks (the group number of each group start), each tile starting from its
+// scanned sum (rows kLevels and kLevels + 1 of blk); entry n of each gets
+// the total.  Thread t takes the tile's entries 4t .. 4t + 3.
+__global__ __launch_bounds__(kLvThreads) void k_scan_tiles(int64_t n, int64_t nblocks, int32_t* __restrict__ chain,
+                                                           int32_t* __restrict__ mark,
+                                                           const int32_t* __restrict__ blk,
+                                                           const int32_t* __restrict__ tot) {
+    static_assert(kPer == 4, "four entries per thread");
+    __shared__ int32_t wsum[kLvThreads / 64][2];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int64_t s0 = blockIdx.x * (int64_t)kLvTile + kPer * tid;
+    int32_t c[kPer], m[kPer];
+    if (s0 + kPer <= n) {
+        const int4 cv = *reinterpret_cast<const int4*>(chain + s0);
+        const int4 mv = *reinterpret_cast<const int4*>(mark + s0);
+        c[0] = cv.x, c[1] = cv.y, c[2] = cv.z, c[3] = cv.w;
+        m[0] = mv.x, m[1] = mv.y, m[2] = mv.z, m[3] = mv.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            c[k] = s0 + k < n ? chain[s0 + k] : 0;
+            m[k] = s0 + k < n ? mark[s0 + k] : 0;
+        }
+    }
+    const int32_t cs = c[0] + c[1] + c[2] + c[3], ms = m[0] + m[1] + m[2] + m[3];
+    int32_t ci = cs, mi = ms;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t u = __shfl_up(ci, o, 64), v = __shfl_up(mi, o, 64);
+        if (lane >= o) {
+            ci += u;
+            mi += v;
+        }
+    }
+    if (lane == 63) {
+        wsum[wid][0] = ci;
+        wsum[wid][1] = mi;
+    }
+    __syncthreads();
+    int32_t co = blk[(int64_t)kLevels * nblocks + blockIdx.x] + ci - cs;
+    int32_t mo = blk[(int64_t)(kLevels + 1) * nblocks + blockIdx.x] + mi - ms;
+#pragma unroll
+    for (int w = 0; w < kLvThreads / 64; ++w) {
+        if (w < wid) {
+            co += wsum[w][0];
+            mo += wsum[w][1];
+        }
+    }
+    int32_t cx[kPer], mx[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        cx[k] = co;
+        mx[k] = mo;
+        co += c[k];
+        mo += m[k];
+    }
+    if (s0 + kPer <= n) {
+        *reinterpret_cast<int4*>(chain + s0) = make_int4(cx[0], cx[1], cx[2], cx[3]);
+        *reinterpret_cast<int4*>(mark + s0) = make_int4(mx[0], mx[1], mx[2], mx[3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            if (s0 + k < n) {
+                chain[s0 + k] = cx[k];
+                mark[s0 + k] = mx[k];
+            }
+        }
+    }
+    if (blockIdx.x == 0 && tid == 0) {
+        chain[n] = tot[kLevels];
+        mark[n] = tot[kLevels + 1];
+    }
 }
 
 // Exclusive scan of one level's per-block cell counts (block = level), in
-// place; the level's total goes to tot.
+// place; the level's total goes to tot.  Rows kLevels and kLevels + 1 (the
+// tiles' chain and mark sums) are scanned the same way.
 __global__ __launch_bounds__(256) void k_level_scan(int64_t nblocks, int32_t* __restrict__ blk,
                                                     int32_t* __restrict__ tot) {
     constexpr int kItems = 4;
@@ -666,15 +752,17 @@ bool build_cells_and_groups(Tree& t, int32_t* d_flag, hipStream_t st) {
     const int64_t nblocks = (n + kLvTile - 1) / kLvTile;
     // per-particle levels, chain lengths and group starts; per-block cell counts
     DevBuf<int8_t> delta(n, st), leaflv(n, st);
-    DevBuf<int32_t> start(n + 1, st), mark(n + 1, st), blk(kLevels * nblocks, st), tot(kLevels, st);
+    DevBuf<int32_t> start(n + 1, st), mark(n + 1, st), blk((kLevels + 2) * nblocks, st), tot(kLevels + 2, st);
     DevBuf<Summary> dsum(1, st);
     hipLaunchKernelGGL(k_levels, dim3((unsigned)nblocks), dim3(kLvThreads), 0, st, n, t.keys.get(), t.n_leaf,
                        t.n_group, nblocks, delta.get(), leaflv.get(), start.get(), mark.get(), blk.get());
     SRF_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_level_scan, dim3(kLevels), dim3(256), 0, st, nblocks, blk.get(), tot.get());
+    hipLaunchKernelGGL(k_level_scan, dim3(kLevels + 2), dim3(256), 0, st, nblocks, blk.get(), tot.get());
     SRF_HIP(hipGetLastError());
-    exclusive_scan_i32(start.get(), n, true, st);   // preorder number of each chain's first cell
-    exclusive_scan_i32(mark.get(), n, true, st);    // group number of each group start
+    // preorder number of each chain's first cell, group number of each group start
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nblocks), dim3(kLvThreads), 0, st, n, nblocks, start.get(),
+                       mark.get(), blk.get(), tot.get());
+    SRF_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_summary, dim3(1), dim3(64), 0, st, n, mark.get(), d_flag, tot.get(), dsum.get());
     SRF_HIP(hipGetLastError());
     // the one synchronisation: sizes and the device's check of the inputs
