@@ -186,9 +186,8 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
 // nothing (the total is out[n] if the caller allocated n+1 entries and
 // asked for it with `write_total`).
 void exclusive_scan_i64(int64_t* data, int64_t n, bool write_total, hipStream_t stream);
-void exclusive_scan_i32(int32_t* data, int64_t n, bool write_total, hipStream_t stream);
-// The same over the first *nd values (a count on the device, at most n_max;
-// data holds n_max + 1 values), the total at data[*nd].
+// The same for int32 over the first *nd values (a count on the device, at
+// most n_max; data holds n_max + 1 values), the total at data[*nd].
 void exclusive_scan_i32_counted(int32_t* data, int64_t n_max, const int32_t* nd, hipStream_t stream);
 
 // ------------------------------------------------------------ launches

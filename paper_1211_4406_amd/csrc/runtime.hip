@@ -274,9 +274,6 @@ static void scan_impl(T* data, int64_t n_read, int64_t n_write, hipStream_t s, c
 void exclusive_scan_i64(int64_t* data, int64_t n, bool write_total, hipStream_t s) {
     scan_impl<int64_t>(data, n, n + (write_total ? 1 : 0), s);
 }
-void exclusive_scan_i32(int32_t* data, int64_t n, bool write_total, hipStream_t s) {
-    scan_impl<int32_t>(data, n, n + (write_total ? 1 : 0), s);
-}
 void exclusive_scan_i32_counted(int32_t* data, int64_t n_max, const int32_t* nd, hipStream_t s) {
     scan_impl<int32_t>(data, n_max, n_max + 1, s, nd);
 }
