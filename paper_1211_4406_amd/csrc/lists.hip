@@ -26,7 +26,11 @@
 //   accept iff s * s < (theta * theta) * d2(half = 0, cen_c or the centre of mass),
 // s the larger of the cell's dyadic side and the box's longest side
 // (2 max(half)), so that a cell holding a member of the group is never
-// accepted, however small its box.
+// accepted, however small its box.  For a fresh tree the walk first takes
+// the two tests in FP32 with an error margin, and evaluates the FP64
+// expressions only for the few cells whose FP32 values lie within the
+// margin of a threshold (classify32 below): the decisions, and so the
+// lists, are those of the FP64 expressions.
 #include <type_traits>
 
 #include "common.h"
@@ -86,12 +90,16 @@ __device__ __forceinline__ Cell decode_walk(const uint2 r, WalkPos& w) {
     w.iy = ((w.iy >> sh) << 1) | ((oct >> 1) & 1u);
     w.iz = ((w.iz >> sh) << 1) | (oct & 1u);
     w.level = k.level;
+    return k;
+}
+
+// The exact centre and side of the cell last decoded into w.
+__device__ __forceinline__ void cell_geometry(Cell& k, const WalkPos& w) {
     k.side = ldexp(1.0, -k.level);
     k.hs = k.side * 0.5;
     k.c[0] = ldexp((double)w.ix + 0.5, -k.level);
     k.c[1] = ldexp((double)w.iy + 0.5, -k.level);
     k.c[2] = ldexp((double)w.iz + 0.5, -k.level);
-    return k;
 }
 
 __device__ __forceinline__ Cell decode(const uint4 r) {
@@ -123,6 +131,49 @@ __device__ __forceinline__ int classify(const Cell& k, const double* mc, const F
     double d2 = (ex * ex + ey * ey) + ez * ez;
     if (k.side * k.side < th2 * d2) return 1;
     return k.leaf ? 2 : 3;
+}
+
+// A first look in FP32 at the same two tests.  Every quantity before the
+// squares is within 4e-7 of its exact value (the centres are exact in FP32,
+// the group's centre and half sizes are rounded once, and each of the four
+// operations per axis rounds a value below 1), so a squared distance D2 is
+// within 1.4e-6 sqrt(D2) + 2.4e-7 D2 + 1e-12 of its exact value; FP64 is
+// within 1e-15.  A test is decided here only when the FP32 value clears its
+// threshold X by more than b(X) = 2.5e-6 sqrt(X) + 2e-6 X + 1e-12, which
+// exceeds both errors together, so that the FP64 expressions would decide
+// the same way; otherwise (-1) they are evaluated.
+struct Frame32 {
+    float cg[3], hg[3];
+};
+
+__device__ __forceinline__ float axis_gap32(float cen, float cg, float half) {
+    float t = fabsf(cen - cg);
+    const float t2 = 1.0f - t;
+    t = t2 < t ? t2 : t;
+    const float r = t - half;
+    return r > 0.0f ? r : 0.0f;
+}
+
+// rc_hi / rc_lo: r_cut^2 +- b(r_cut^2); inv_th: 1 / theta.
+__device__ __forceinline__ int classify32(int level, int leaf, const float* c, const float* mc, const Frame32& f,
+                                          float rc_hi, float rc_lo, float inv_th) {
+    const float side = __int_as_float((127 - level) << 23);   // 2^-level, exact
+    const float hs = side * 0.5f;
+    float ex = axis_gap32(c[0], f.cg[0], hs + f.hg[0]);
+    float ey = axis_gap32(c[1], f.cg[1], hs + f.hg[1]);
+    float ez = axis_gap32(c[2], f.cg[2], hs + f.hg[2]);
+    const float D2 = (ex * ex + ey * ey) + ez * ez;
+    if (D2 >= rc_hi) return 0;
+    if (!(D2 < rc_lo)) return -1;
+    ex = axis_gap32(mc[0], f.cg[0], f.hg[0]);
+    ey = axis_gap32(mc[1], f.cg[1], f.hg[1]);
+    ez = axis_gap32(mc[2], f.cg[2], f.hg[2]);
+    const float d2 = (ex * ex + ey * ey) + ez * ez;
+    const float sx = side * inv_th, X = sx * sx;   // accept iff d2 > side^2 / theta^2
+    const float b = 2.5e-6f * sx + 2e-6f * X + 1e-12f;
+    if (d2 > X + b) return 1;
+    if (!(d2 < X - b)) return -1;
+    return leaf ? 2 : 3;
 }
 
 __device__ __forceinline__ double refit_axis_gap(double cen, double cg, double half) {
@@ -247,6 +298,18 @@ __global__ __launch_bounds__(kListThreads) void k_lists(int64_t ng, const double
         out[q].start = out[q].pos = WRITE ? ioff[g] : g * kSlot;
         out[q].end = WRITE ? INT64_MAX : g * kSlot + kSlot;
     }
+    Frame32 f32[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            f32[q].cg[a] = (float)f[q].cg[a];
+            f32[q].hg[a] = (float)f[q].hg[a];
+        }
+    const float rc2f = (float)rc2;
+    const float bp = 2.5e-6f * sqrtf(rc2f) + 2e-6f * rc2f + 1e-12f;
+    const float rc_hi = rc2f + bp, rc_lo = rc2f - bp;
+    const float inv_th = th2 > 0.0 ? (float)(1.0 / sqrt(th2)) : INFINITY;
     const uint64_t full = (1ull << G) - 1ull;
     uint64_t masks = valid;  // level 0
     int64_t i = valid ? 0 : nn;
@@ -254,15 +317,37 @@ __global__ __launch_bounds__(kListThreads) void k_lists(int64_t ng, const double
     while (i < nn) {
         RefitCell rc;
         if (REFIT) rc = rpack[i];
-        const Cell k = REFIT ? decode(rc.pk) : decode_walk(pack[i], wpos);
+        Cell k = REFIT ? decode(rc.pk) : decode_walk(pack[i], wpos);
         const uint64_t act = (masks >> (k.level * G)) & full;
         uint64_t open = 0;
         if (act) {
-            double mcen[3] = {k.c[0], k.c[1], k.c[2]};
+            float c32[3] = {0.0f, 0.0f, 0.0f}, mc32[3] = {0.0f, 0.0f, 0.0f};
+            double com[3] = {0.0, 0.0, 0.0};
+            if (!REFIT) {
+                const float side32 = __int_as_float((127 - k.level) << 23);
+                const float hs32 = side32 * 0.5f;
+                // (i + 1/2) 2^-level: exact in FP32 (i < 2^21)
+                c32[0] = __fmaf_rn((float)wpos.ix, side32, hs32);
+                c32[1] = __fmaf_rn((float)wpos.iy, side32, hs32);
+                c32[2] = __fmaf_rn((float)wpos.iz, side32, hs32);
+                mc32[0] = c32[0];
+                mc32[1] = c32[1];
+                mc32[2] = c32[2];
+            }
             if (COM) {
-                mcen[0] = nX[i];
-                mcen[1] = nY[i];
-                mcen[2] = nZ[i];
+                com[0] = nX[i];
+                com[1] = nY[i];
+                com[2] = nZ[i];
+                mc32[0] = (float)com[0];
+                mc32[1] = (float)com[1];
+                mc32[2] = (float)com[2];
+            }
+            bool geom = REFIT;   // FP64 geometry computed (a refitted cell's comes with its record)
+            double mcen[3] = {0.0, 0.0, 0.0};
+            if (REFIT) {
+                mcen[0] = COM ? com[0] : k.c[0];
+                mcen[1] = COM ? com[1] : k.c[1];
+                mcen[2] = COM ? com[2] : k.c[2];
             }
             double bl[3] = {0, 0, 0}, bh[3] = {0, 0, 0};
             bool bounded = true;
@@ -273,9 +358,22 @@ __global__ __launch_bounds__(kListThreads) void k_lists(int64_t ng, const double
 #pragma unroll
             for (int q = 0; q < G; ++q) {
                 if (!((act >> q) & 1ull)) continue;
-                const int cls = REFIT ? (bounded ? classify_refit(k, bl, bh, mcen, COM, f[q], rc2, th2)
-                                                 : (k.leaf ? 2 : 3))
-                                      : classify(k, mcen, f[q], rc2, th2);
+                int cls;
+                if (REFIT) {
+                    cls = bounded ? classify_refit(k, bl, bh, mcen, COM, f[q], rc2, th2) : (k.leaf ? 2 : 3);
+                } else {
+                    cls = classify32(k.level, k.leaf, c32, mc32, f32[q], rc_hi, rc_lo, inv_th);
+                    if (cls < 0) {
+                        if (!geom) {
+                            cell_geometry(k, wpos);
+                            mcen[0] = COM ? com[0] : k.c[0];
+                            mcen[1] = COM ? com[1] : k.c[1];
+                            mcen[2] = COM ? com[2] : k.c[2];
+                            geom = true;
+                        }
+                        cls = classify(k, mcen, f[q], rc2, th2);
+                    }
+                }
                 if (cls == 3) {
                     open |= 1ull << q;
                 } else if (cls == 1) {
