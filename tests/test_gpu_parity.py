@@ -201,6 +201,27 @@ def test_edge_cases():
         say(f"    fp32 {s32}")
 
 
+@pytest.mark.parametrize("theta", [0.5, 1.0])
+def test_lists_with_distances_exactly_at_the_thresholds(theta):
+    """A 32^3 lattice with r_cut = 5/32: cell and group boxes sit on
+    multiples of 1/32, so many squared distances equal r_cut^2 exactly (a
+    tie: pruned) and many equal (side / theta)^2 exactly (a tie: not
+    accepted).  The walk's FP32 first look must leave every such case to the
+    FP64 expressions; the structure and lists must match the oracle's bit
+    for bit."""
+    g = np.arange(32) / 32.0
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    pos = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    n = len(pos)
+    p = synth.Params(1.0, 5.0 / 32.0, 1e-3, theta, 64, 16)
+    ps = synth.ParticleSet(pos[:, 0].copy(), pos[:, 1].copy(), pos[:, 2].copy(), np.full(n, 1.0 / n), p)
+    say(f"[gpu] lattice ties theta={theta} n={n}")
+    ot = oracle.OracleTree(ps.x, ps.y, ps.z, ps.m, p)
+    tree, lists, a32 = gpu_forward(ps, p)
+    check_structure(tree, lists, ot)
+    assert lists.info()["n_node_entries"] > 0   # accepted cells, some of them next to a tie
+
+
 @pytest.mark.parametrize("n,distinct", [(4096, 4096), (4097, 4097), (8191, 8191), (100_000, 1000), (70_000, 7)])
 def test_sort_tiles_and_repeated_keys(n, distinct):
     """The radix sort at exactly one tile of 4096 keys, one past it, one
